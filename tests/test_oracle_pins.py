@@ -1,0 +1,320 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here re-types an oracle formula: each check reaches the same result
+by another road (Eq. 1's autocorrelation, closed forms that follow from it,
+numpy's FFT, scipy's circulant and lstsq, dense brute force, finite
+differences, torch's own float conversions).
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+import oracle
+import synth
+
+
+def dense_P(s, K):
+    """Explicit N x K matrix whose column k is the sequence delayed by k."""
+    return np.stack([np.roll(np.asarray(s, np.float64), k) for k in range(K)], axis=1)
+
+
+def rand_c(shape, seed):
+    return synth.gaussian(shape, seed)
+
+
+# ---------------------------------------------------------------- a1: sequence
+@pytest.mark.parametrize("d", list(range(2, 17)))
+def test_mseq_balance_and_two_level_autocorrelation(d):
+    """Eq. 1: circular autocorrelation N at lag 0 and -1 at every other lag
+    (equivalently R[n] = 1 and -1/M after the 1/M normalisation)."""
+    s = oracle.mseq(d).astype(np.float64)
+    N = (1 << d) - 1
+    assert s.shape == (N,)
+    assert set(np.unique(s)) <= {-1.0, 1.0}
+    assert np.sum(s == -1) == (N + 1) // 2            # (N+1)/2 ones
+    ac = np.real(np.fft.ifft(np.abs(np.fft.fft(s)) ** 2))
+    assert abs(ac[0] - N) < 1e-6
+    assert np.max(np.abs(ac[1:] + 1.0)) < 1e-6
+    R = ac / N
+    assert abs(R[0] - 1.0) < 1e-9 and np.allclose(R[1:], -1.0 / N, atol=1e-9)
+
+
+@pytest.mark.parametrize("d", [5, 7])
+def test_mseq_autocorrelation_direct(d):
+    """Eq. 1 again, by the direct sum over np.roll (no FFT)."""
+    s = oracle.mseq(d).astype(np.int64)
+    N = s.size
+    for n in range(N):
+        c = int(np.sum(s * np.roll(s, -n)))
+        assert c == (N if n == 0 else -1)
+
+
+def test_mseq_rejects_bad_degree():
+    with pytest.raises(ValueError):
+        oracle.mseq(1)
+    with pytest.raises(ValueError):
+        oracle.mseq(17)
+
+
+# -------------------------------------------------------- a4: the correlator
+@pytest.mark.parametrize("d,K", [(5, 8), (5, 31), (5, 40), (7, 64)])
+def test_correlate_equals_dense_brute_force(d, K):
+    s = oracle.mseq(d)
+    N = s.size
+    Y = rand_c((2, 3, N), seed=d * 100 + K)
+    H = oracle.correlate(Y, s, K)
+    ref = Y @ dense_P(s, K) / N
+    assert np.max(np.abs(H - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("d,K", [(7, 64), (10, 512), (10, 1024), (12, 2048)])
+def test_correlate_equals_fft_cross_correlation(d, K):
+    """Textbook circular cross-correlation through the DFT."""
+    s = oracle.mseq(d)
+    N = s.size
+    Y = rand_c((1, 2, N), seed=d + K)
+    H = oracle.correlate(Y, s, K)
+    c = np.fft.ifft(np.fft.fft(Y, axis=-1) * np.conj(np.fft.fft(s.astype(np.float64))), axis=-1)
+    ref = c[..., np.arange(K) % N] / N
+    assert np.max(np.abs(H - ref)) < 1e-12
+
+
+def test_sequential_case_is_full_circulant():
+    """T = 1, L = N: H = S^T y / N with S the circulant of Eq. 2 (first row
+    s0, s_{M-1}, ..., s1), built by scipy."""
+    s = oracle.mseq(6)
+    N = s.size
+    S = scipy.linalg.circulant(s.astype(np.float64))
+    assert np.array_equal(S[0], np.concatenate([[s[0]], s[:0:-1]]))
+    y = rand_c((1, 1, N), seed=7)
+    H = oracle.correlate(y, s, N)
+    ref = (S.T @ y[0, 0]) / N
+    assert np.max(np.abs(H[0, 0] - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("d,T,L", [(7, 4, 16), (10, 16, 32), (5, 2, 4), (6, 1, 63)])
+def test_noiseless_bias_closed_form(d, T, L):
+    """From Eq. 1, P^T P = (N+1) I - J, so a noiseless frame gives
+    h_hat = h + (h - sum(h)) / N (the -sum(h)/N bias, sum over the K lags)."""
+    s = oracle.mseq(d)
+    N = s.size
+    h = rand_c((2, 3, T, L), seed=d * T * L)
+    y, _ = oracle.received(s, h, np.zeros((2, 3, N)), np.full(2, 300.0))
+    H = oracle.correlate(y, s, T * L)
+    hs = h.reshape(2, 3, T * L)
+    expect = hs + (hs - hs.sum(axis=-1, keepdims=True)) / N
+    assert np.max(np.abs(H - expect)) < 1e-12
+
+
+def test_noiseless_least_squares_recovers_channel():
+    s = oracle.mseq(7)
+    N = s.size
+    h = rand_c((1, 4, 4, 16), seed=3)
+    y, _ = oracle.received(s, h, np.zeros((1, 4, N)), np.array([400.0]))
+    H = oracle.correlate(y, s, 64)
+    x = oracle.ls_closed_form(H, N)
+    assert np.max(np.abs(x - h.reshape(1, 4, 64))) < 1e-12
+
+
+def test_demultiplex_view():
+    """Eq. 10: transmitter t's CIR estimate is H[..., t*L:(t+1)*L]."""
+    s = oracle.mseq(8)
+    N = s.size
+    T, L = 4, 16
+    h = np.zeros((1, 1, T, L), dtype=np.complex128)
+    h[0, 0, 2, 5] = 1.0
+    y, _ = oracle.received(s, h, np.zeros((1, 1, N)), np.array([300.0]))
+    H = oracle.correlate(y, s, T * L).reshape(1, 1, T, L)
+    assert np.argmax(np.abs(H[0, 0]).ravel()) == 2 * L + 5
+    assert abs(H[0, 0, 2, 5] - 1.0) < 1e-12        # the tap itself
+    others = np.delete(H[0, 0].ravel(), 2 * L + 5)
+    assert np.max(np.abs(others + 1.0 / N)) < 1e-12  # -1/M floor of Eq. 1
+
+
+def test_linearity_and_shift_equivariance():
+    s = oracle.mseq(7)
+    N = s.size
+    K = 40
+    a = rand_c((1, 2, N), 1)
+    b = rand_c((1, 2, N), 2)
+    Ha, Hb = oracle.correlate(a, s, K), oracle.correlate(b, s, K)
+    H = oracle.correlate(2.5 * a - 1j * b, s, K)
+    assert np.max(np.abs(H - (2.5 * Ha - 1j * Hb))) < 1e-12
+    Hs = oracle.correlate(np.roll(a, 1, axis=-1), s, K)
+    assert np.max(np.abs(Hs[..., 1:] - Ha[..., :-1])) < 1e-12
+
+
+def test_lag_alias_when_T_L_exceeds_N():
+    """Lags are taken mod N: with T*L > N column k + N repeats column k."""
+    s = oracle.mseq(5)
+    N = s.size
+    Y = rand_c((1, 2, N), 9)
+    H = oracle.correlate(Y, s, N + 9)
+    assert np.max(np.abs(H[..., N:] - H[..., :9])) < 1e-14
+
+
+# ------------------------------------------------------------ a7: adjoint
+@pytest.mark.parametrize("d,K", [(5, 8), (5, 40), (7, 64)])
+def test_adjoint_brute_force_and_dot_identity(d, K):
+    s = oracle.mseq(d)
+    N = s.size
+    G = rand_c((2, 3, K), 11)
+    Y = rand_c((2, 3, N), 12)
+    A = oracle.adjoint(G, s)
+    assert np.max(np.abs(A - G @ dense_P(s, K).T / N)) < 1e-13
+    lhs = np.vdot(G, oracle.correlate(Y, s, K))      # <H(Y), G>
+    rhs = np.vdot(oracle.adjoint(G, s), Y)           # <Y, A(G)>
+    assert abs(lhs - rhs) < 1e-10 * max(1.0, abs(lhs))
+
+
+def test_received_model_equals_dense_product():
+    """Eq. 9: the noiseless frame is P h_stack (dense), noise then scaled to
+    the requested SNR."""
+    s = oracle.mseq(6)
+    N = s.size
+    h = rand_c((2, 3, 3, 5), 4)
+    w = rand_c((2, 3, N), 5)
+    y, yc = oracle.received(s, h, w, np.array([10.0, 0.0]))
+    ref = h.reshape(2, 3, 15) @ dense_P(s, 15).T
+    assert np.max(np.abs(yc - ref)) < 1e-12
+    noise_p = np.mean(np.abs(y - yc) ** 2, axis=(1, 2))
+    sig_p = np.mean(np.abs(yc) ** 2, axis=(1, 2))
+    wp = np.mean(np.abs(w) ** 2, axis=(1, 2))
+    snr = 10 * np.log10(sig_p / (noise_p / wp))
+    assert np.allclose(snr, [10.0, 0.0], atol=1e-9)
+
+
+# ------------------------------------------------------- a6: refinement
+def test_refinement_converges_to_lstsq():
+    s = oracle.mseq(5)
+    N = s.size
+    K = 8
+    y = rand_c((1, 2, N), 21)
+    its = oracle.refine(y, s, K, 60)
+    P = dense_P(s, K)
+    ls = np.stack([np.linalg.lstsq(P, y[0, r], rcond=None)[0] for r in range(2)])
+    assert np.max(np.abs(its[-1][0] - ls)) < 1e-12
+    assert np.max(np.abs(oracle.ls_closed_form(its[0], N)[0] - ls)) < 1e-12
+
+
+def test_refinement_contraction_rates():
+    """Error to the LS point shrinks by (K-1)/N along the all-ones lag vector
+    and by -1/N on its complement, per step."""
+    s = oracle.mseq(7)
+    N = s.size
+    K = 64
+    y = rand_c((1, 1, N), 22)
+    its = oracle.refine(y, s, K, 3)
+    ls = oracle.ls_closed_form(its[0], N)[0, 0]
+    e = [x[0, 0] - ls for x in its]
+    one = np.ones(K) / np.sqrt(K)
+    for j in range(3):
+        a0, a1 = np.vdot(one, e[j]), np.vdot(one, e[j + 1])
+        c0, c1 = e[j] - a0 * one, e[j + 1] - a1 * one
+        assert abs(a1 - (K - 1) / N * a0) < 1e-12 * max(1, abs(a0))
+        assert np.max(np.abs(c1 + c0 / N)) < 1e-12
+
+
+def test_loss_gradient_finite_differences():
+    s = oracle.mseq(5)
+    N = s.size
+    K = 8
+    y = rand_c((1, 2, N), 31)
+    x = rand_c((1, 2, K), 32)
+    loss, g = oracle.loss_grad(y, s, x)
+    eps = 1e-6
+    for idx in [(0, 0, 0), (0, 1, 5), (0, 0, 7)]:
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            xp = x.copy(); xp[idx] += eps * unit
+            xm = x.copy(); xm[idx] -= eps * unit
+            fd = (oracle.loss_grad(y, s, xp)[0] - oracle.loss_grad(y, s, xm)[0]) / (2 * eps)
+            got = g[idx].real if part == "re" else g[idx].imag
+            assert abs(fd - got) < 1e-5 * max(1.0, abs(got))
+
+
+# --------------------------------------------------- a3: reduced precision
+def test_bf16_and_f16_codes_match_torch_rounding():
+    v = rand_c((3, 4, 127), 41).astype(np.complex64) * 7.3
+    for fmt, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        codes, sc = oracle.quantize(v, fmt)
+        planes = np.stack([v.real, v.imag], axis=2).astype(np.float32)
+        t = torch.from_numpy(planes) * torch.from_numpy(1.0 / sc)[:, None, None, None]
+        ref = t.to(tdt).view(torch.int16).numpy().view(np.uint16)
+        assert np.array_equal(codes[..., :127], ref)
+        assert np.all(codes[..., 127] == 0)
+
+
+def test_e4m3_codes_and_decode_match_torch():
+    allc = np.arange(256, dtype=np.uint8)
+    ref = torch.from_numpy(allc).view(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+    mine = oracle.decode(allc, "e4m3")
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isnan(mine), np.isnan(ref))
+    assert np.array_equal(mine[fin], ref[fin])
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.uniform(-448, 448, 5000), rng.normal(0, 1, 5000),
+                        rng.normal(0, 1e-2, 2000), _e4m3_midpoints()]).astype(np.float32)
+    got = oracle._e4m3_bits(x)
+    want = torch.from_numpy(x).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    assert np.array_equal(got, want)
+
+
+def _e4m3_midpoints():
+    v = oracle.decode(np.arange(127, dtype=np.uint8), "e4m3")
+    mids = (v[:-1] + v[1:]) / 2
+    return np.concatenate([mids, -mids])
+
+
+def test_e4m3_saturates():
+    x = np.array([448.0, 449.0, 480.0, 1e30, np.inf, -500.0, -np.inf], dtype=np.float32)
+    c = oracle._e4m3_bits(x)
+    assert list(c) == [0x7E, 0x7E, 0x7E, 0x7E, 0x7E, 0xFE, 0xFE]
+
+
+@pytest.mark.parametrize("fmt", oracle.FORMATS)
+def test_scale_is_smallest_power_of_two(fmt):
+    y = rand_c((4, 3, 31), 51).astype(np.complex64) * np.array([1e-3, 1, 37, 5e4])[:, None, None]
+    y[2, 0, 0] = 448.0 * 4 if fmt == "e4m3" else 4.0   # exact boundary
+    sc = oracle.frame_scale(y, fmt)
+    tgt = 448.0 if fmt == "e4m3" else 1.0
+    mx = np.maximum(np.abs(y.real), np.abs(y.imag)).reshape(4, -1).max(axis=1)
+    for b in range(4):
+        m, e = np.frexp(sc[b])
+        assert m == 0.5                       # power of two
+        assert mx[b] <= tgt * sc[b] and mx[b] > tgt * sc[b] / 2
+    assert oracle.frame_scale(np.zeros((1, 2, 3), np.complex64), fmt)[0] == 1.0
+
+
+@pytest.mark.parametrize("fmt,tol", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11), ("e4m3", 2.0 ** -4)])
+def test_dequantize_error_bound(fmt, tol):
+    y = rand_c((2, 5, 63), 61).astype(np.complex64)
+    codes, sc = oracle.quantize(y, fmt)
+    z = oracle.dequantize(codes, sc, fmt, 63)
+    big = np.abs(y) > 0.05 * np.abs(y).max()
+    for part in (np.real, np.imag):
+        a, b = part(z), part(y).astype(np.float64)
+        m = big & (np.abs(b) > 0.05 * np.abs(y).max())
+        assert np.max(np.abs(a[m] - b[m]) / np.abs(b[m])) <= tol
+
+
+# ------------------------------------------------------------- metrics
+def test_metrics_by_hand():
+    h = np.array([[[1.0, 1j, -2.0]]])
+    hh = np.array([[[1.5, 0.0, -2.0]]])
+    assert abs(oracle.mae(hh, h) - (0.5 + 1.0 + 0.0) / 3) < 1e-15     # Eq. 12
+    assert abs(oracle.nmse_db(hh, h) - 10 * np.log10(1.25 / 6.0)) < 1e-12
+    assert abs(oracle.relerr(hh, h) - np.sqrt(1.25 / 6.0)) < 1e-15
+
+
+def test_synth_is_deterministic_and_normalised():
+    cfg = synth.PLAIN
+    a = synth.batch_draws(cfg)
+    b = synth.batch_draws(cfg)
+    assert np.array_equal(a["h"], b["h"]) and np.array_equal(a["w"], b["w"])
+    e = np.sum(np.abs(a["h"]) ** 2, axis=-1)
+    assert np.allclose(e, 1.0)
+    f3 = synth.batch_draws(synth.FP32, frames=[3])
+    assert np.array_equal(f3["h"][0], synth.frame_draws(synth.FP32, 3)[1])
+    shp = synth.varlen_shapes(64)
+    assert np.all(shp[:, 2] * shp[:, 3] <= (1 << shp[:, 1]) - 1)
