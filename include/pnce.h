@@ -1,0 +1,171 @@
+/*
+ * pnce.h -- PN-sequence correlation channel estimation on AMD Instinct MI355X
+ * (gfx950): the C ABI of libpnce.so.
+ *
+ * Method (arXiv 2206.05506, Sections II-A and II-B): T transmitters send the
+ * same m-sequence s of length N = 2^d - 1 at once, transmitter t delayed by
+ * t*L samples (Eq. 7-8 with the shift spacing equal to the CIR length L).
+ * Receive antenna r hears one frame y_r of N samples (cyclic prefix removed).
+ * Correlating y_r with s at the K = T*L lags those transmitters occupy gives
+ * every (transmitter, antenna) L-tap CIR at once (Eq. 3, Eq. 10):
+ *
+ *     H[b][r][k] = (1/N) * sum_{n<N} Y[b][r][n] * s[(n - k) mod N],  k < K,
+ *
+ * i.e. the dense contraction H = Y P / N with P[n][k] = s[(n-k) mod N] a
+ * Toeplitz +-1 slice of the circulant of Eq. 2. Transmitter t's CIR is the
+ * view H[b][r][t*L : (t+1)*L] (Eq. 10). The library never stores P: the
+ * kernels expand it from the sequence bits on chip.
+ *
+ * Conventions for every entry point
+ *  - Tensor pointers are DEVICE memory owned by the caller, dense row-major,
+ *    with the shapes stated per call. Complex numbers are interleaved
+ *    (re, im) float pairs ("c64") or double pairs ("c128").
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Compute calls only enqueue work and return; results are ready when the
+ *    stream is. Faults of enqueued kernels surface at the caller's next sync.
+ *  - Return value: 0 = PNCE_OK; > 0 = a warning, the call did its work;
+ *    < 0 = an error, nothing was enqueued and no output was touched. The
+ *    text of the last error on the calling thread is pnce_last_error().
+ *  - No C++ exception and no abort crosses this boundary.
+ *  - A plan is immutable after pnce_create; calls on one plan from several
+ *    host threads or streams are safe, except that pnce_refine uses the
+ *    workspace its caller passes.
+ */
+#ifndef PNCE_H
+#define PNCE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pnce_plan pnce_plan;   /* opaque, owned by the library */
+typedef int pnce_status;
+
+#define PNCE_OK 0
+#define PNCE_W_LAG_ALIAS 1      /* T*L > N: lags are taken mod N, so some   */
+                                /* columns of H repeat (Eq. 7 violated)      */
+#define PNCE_E_INVALID (-1)     /* null pointer, size <= 0, bad enum value   */
+#define PNCE_E_UNSUPPORTED (-2) /* N is not 2^d - 1 with 2 <= d <= 16        */
+#define PNCE_E_NOMEM (-3)       /* device or host allocation failed          */
+#define PNCE_E_HIP (-4)         /* a HIP runtime call failed                 */
+
+/* Arithmetic of a contraction (estimate / adjoint). */
+#define PNCE_PREC_F32 0   /* FP32 matrix cores: v_mfma_f32_32x32x2_f32        */
+#define PNCE_PREC_F32S 1  /* FP32-accurate on bf16 matrix cores: each FP32    */
+                          /* operand split into three bf16 parts (exact, the  */
+                          /* other operand being +-1), FP32 accumulation      */
+#define PNCE_PREC_BF16 2  /* operand rounded once to bf16 (round to nearest   */
+                          /* even), bf16 matrix cores, FP32 accumulation      */
+#define PNCE_PREC_F64 3   /* FP64 vector ALU on c128 buffers (for gradient    */
+                          /* checks; not a throughput path)                   */
+
+/* Reduced-precision storage formats of Y (the half-precision conversion
+ * before correlation, Section III-B). */
+#define PNCE_FMT_BF16 1
+#define PNCE_FMT_F16 2
+#define PNCE_FMT_E4M3 3   /* OCP e4m3fn, saturating at +-448 */
+
+/*
+ * Create a plan for sequence length N, T multiplexed transmitters, L taps
+ * and R receive antennas (Sections II-A, II-B). Builds the m-sequence on the
+ * host (degree d = log2(N+1); fixed primitive polynomial per degree; LFSR
+ * state 1,0,...,0; bit 0 sent as +1 and bit 1 as -1) and uploads its bits
+ * (a few KiB) to the current device. Synchronous.
+ * Errors: plan == NULL or T, L, R <= 0 -> PNCE_E_INVALID; N not 2^d - 1 with
+ * 2 <= d <= 16 -> PNCE_E_UNSUPPORTED; T*L > 16*N or R > 65535 ->
+ * PNCE_E_INVALID. Warning: T*L > N (Eq. 7's bound N_batch <= floor(N/L)
+ * broken) -> PNCE_W_LAG_ALIAS, with a valid plan. On error *plan = NULL.
+ */
+pnce_status pnce_create(pnce_plan **plan, int N, int T, int L, int R);
+
+/* Free a plan and its device tables. NULL is a no-op. Synchronous: the
+ * caller must not destroy a plan that enqueued work still uses. */
+pnce_status pnce_destroy(pnce_plan *plan);
+
+/* Copy the plan's sequence as N host bytes of +1 / -1 (Eq. 1). */
+pnce_status pnce_get_sequence(const pnce_plan *plan, signed char *s_host);
+
+/* Plan geometry: writes N, T, L, R (any pointer may be NULL). */
+pnce_status pnce_get_shape(const pnce_plan *plan, int *N, int *T, int *L, int *R);
+
+/*
+ * Correlator (Eq. 3, Eq. 10) on complex input.
+ *   H = alpha_b * (Y P) + beta * H,  alpha_b = (scales ? scales[b] : 1) / N.
+ * Y: [batch][R][N] c64 (c128 when precision == PNCE_PREC_F64);
+ * H: [batch][R][T*L] c64 (c128 for PNCE_PREC_F64), read only if beta != 0;
+ * scales: NULL or `batch` device floats. Y and H must not overlap.
+ * Errors: null Y/H, batch <= 0, unknown precision -> PNCE_E_INVALID.
+ */
+pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y,
+                          void *H, int batch, int precision,
+                          const float *scales, double beta);
+
+/*
+ * Quantise a complex64 batch for storage (the conversion to half precision
+ * before correlation, Section III-B) with a per-frame power-of-two scale.
+ * scale_b is the smallest 2^e with maxabs_b <= target * 2^e, maxabs_b the
+ * largest |re| or |im| in frame b, target 1 (bf16, f16) or 448 (e4m3);
+ * a frame of zeros or with a non-finite maxabs gets 1. Each value is
+ * multiplied by 1/scale_b in FP32 and rounded to nearest even.
+ * Y: [batch][R][N] c64. Yq: [batch][R][2][N+1] codes, 2 bytes each for
+ * bf16/f16 and 1 byte for e4m3: per antenna the real plane then the
+ * imaginary plane, each padded with one zero sample. scales: [batch] float.
+ * Runs two kernels (per-frame max, then convert) on `stream`.
+ * Errors: null pointer, batch <= 0, bad format -> PNCE_E_INVALID.
+ */
+pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y,
+                      void *Yq, float *scales, int batch, int format);
+
+/*
+ * Correlator on a quantised batch (layout of pnce_pack) with FP32
+ * accumulation on bf16 / f16 / fp8 matrix cores; the +-1 operand is exact in
+ * every format. H = (scales[b] / N) * (Yq P) + beta * H, H [batch][R][T*L]
+ * c64. scales may be NULL (all 1).
+ * Errors: null Yq/H, batch <= 0, bad format -> PNCE_E_INVALID.
+ */
+pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream,
+                                 const void *Yq, const float *scales, void *H,
+                                 int batch, int format, double beta);
+
+/*
+ * Adjoint of the correlator: a circular convolution with the sequence,
+ *   A = alpha * (G P^T) + beta * C,  (G P^T)[b][r][n] = sum_{k<T*L}
+ *   G[b][r][k] s[(n - k) mod N].
+ * alpha and beta are applied in FP32 (FP64 for PNCE_PREC_F64).
+ * With alpha = 1/N it is the transpose of pnce_estimate (the backward of
+ * the correlator); with alpha = -1, beta = 1, C = y and G a CIR stack it is
+ * the residual y - P h of the receive model of Eq. 9.
+ * G: [batch][R][T*L]; A, C: [batch][R][N]; c64, or c128 for
+ * PNCE_PREC_F64. C may equal A, or be NULL when beta == 0. G must not
+ * overlap A. precision: PNCE_PREC_F32, _F32S, _BF16 or _F64.
+ */
+pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
+                         void *A, const void *C, int batch, int precision,
+                         double alpha, double beta);
+
+/*
+ * Least-squares refinement of a CIR estimate (the correlator's bias floor
+ * comes from the -1/M term of Eq. 1; each step removes part of it):
+ *   repeat `steps` times:  r = y - P x;  x = x + P^T r / N.
+ * Both contractions are FP32-accurate (PNCE_PREC_F32S); the residual of the
+ * last step is accumulated in FP64 (FP64 matrix cores).
+ * y: [batch][R][N] c64 (the original, unquantised frames);
+ * X: [batch][R][T*L] c64, in: the starting estimate, out: refined;
+ * work: device scratch of batch*R*N*8 bytes (the residual). steps >= 0.
+ */
+pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y,
+                        void *X, void *work, int batch, int steps);
+
+/* Text of a status code (static storage). */
+const char *pnce_status_string(pnce_status status);
+
+/* Detail of the last error returned on the calling thread ("" if none). */
+const char *pnce_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PNCE_H */

@@ -1,0 +1,132 @@
+"""ctypes binding of libpnce.so: the C entry points of include/pnce.h under
+the same names, with argument marshalling only (no computation here).
+
+The library must be built in-tree (``python -m paper_2206_05506_amd.build``);
+importing this module without it raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpnce.so")
+
+PNCE_OK = 0
+PNCE_W_LAG_ALIAS = 1
+PNCE_E_INVALID = -1
+PNCE_E_UNSUPPORTED = -2
+PNCE_E_NOMEM = -3
+PNCE_E_HIP = -4
+
+PNCE_PREC_F32 = 0
+PNCE_PREC_F32S = 1
+PNCE_PREC_BF16 = 2
+PNCE_PREC_F64 = 3
+
+PNCE_FMT_BF16 = 1
+PNCE_FMT_F16 = 2
+PNCE_FMT_E4M3 = 3
+
+SYMBOLS = ("pnce_create", "pnce_destroy", "pnce_get_sequence", "pnce_get_shape",
+           "pnce_estimate", "pnce_pack", "pnce_estimate_packed", "pnce_adjoint",
+           "pnce_refine", "pnce_status_string", "pnce_last_error")
+
+
+class PnceError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpnce.so not built at {LIB_PATH}; run "
+                          "`python -m paper_2206_05506_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "pnce_create": ([ctypes.POINTER(_P), _I, _I, _I, _I], _I),
+        "pnce_destroy": ([_P], _I),
+        "pnce_get_sequence": ([_P, _P], _I),
+        "pnce_get_shape": ([_P, _P, _P, _P, _P], _I),
+        "pnce_estimate": ([_P, _P, _P, _P, _I, _I, _P, _D], _I),
+        "pnce_pack": ([_P, _P, _P, _P, _P, _I, _I], _I),
+        "pnce_estimate_packed": ([_P, _P, _P, _P, _P, _I, _I, _D], _I),
+        "pnce_adjoint": ([_P, _P, _P, _P, _P, _I, _I, _D, _D], _I),
+        "pnce_refine": ([_P, _P, _P, _P, _P, _I, _I], _I),
+        "pnce_status_string": ([_I], ctypes.c_char_p),
+        "pnce_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def check(status: int, where: str) -> int:
+    """Raise PnceError on a negative status; return warnings (> 0) as is."""
+    if status < 0:
+        detail = lib.pnce_last_error().decode() or lib.pnce_status_string(status).decode()
+        raise PnceError(status, where, detail)
+    return status
+
+
+def pnce_create(N: int, T: int, L: int, R: int):
+    """Returns (plan handle, status); status may be PNCE_W_LAG_ALIAS."""
+    h = _P()
+    st = check(lib.pnce_create(ctypes.byref(h), N, T, L, R), "pnce_create")
+    return h, st
+
+
+def pnce_destroy(plan) -> int:
+    return check(lib.pnce_destroy(plan), "pnce_destroy")
+
+
+def pnce_get_sequence(plan, out_ptr: int) -> int:
+    return check(lib.pnce_get_sequence(plan, out_ptr), "pnce_get_sequence")
+
+
+def pnce_get_shape(plan):
+    v = [_I() for _ in range(4)]
+    check(lib.pnce_get_shape(plan, *[ctypes.byref(x) for x in v]), "pnce_get_shape")
+    return tuple(x.value for x in v)
+
+
+def pnce_estimate(plan, stream, Y, H, batch, precision, scales, beta) -> int:
+    return check(lib.pnce_estimate(plan, stream, Y, H, batch, precision, scales, beta),
+                 "pnce_estimate")
+
+
+def pnce_pack(plan, stream, Y, Yq, scales, batch, fmt) -> int:
+    return check(lib.pnce_pack(plan, stream, Y, Yq, scales, batch, fmt), "pnce_pack")
+
+
+def pnce_estimate_packed(plan, stream, Yq, scales, H, batch, fmt, beta) -> int:
+    return check(lib.pnce_estimate_packed(plan, stream, Yq, scales, H, batch, fmt, beta),
+                 "pnce_estimate_packed")
+
+
+def pnce_adjoint(plan, stream, G, A, C, batch, precision, alpha, beta) -> int:
+    return check(lib.pnce_adjoint(plan, stream, G, A, C, batch, precision, alpha, beta),
+                 "pnce_adjoint")
+
+
+def pnce_refine(plan, stream, y, X, work, batch, steps) -> int:
+    return check(lib.pnce_refine(plan, stream, y, X, work, batch, steps), "pnce_refine")
+
+
+def pnce_status_string(status: int) -> str:
+    return lib.pnce_status_string(status).decode()
+
+
+def pnce_last_error() -> str:
+    return lib.pnce_last_error().decode()

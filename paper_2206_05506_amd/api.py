@@ -1,0 +1,150 @@
+"""Tensor-level wrapper of libpnce.so for PyTorch-ROCm callers.
+
+Each method checks shapes, dtypes and devices, then passes raw device
+pointers and the current HIP stream to the C entry point of the same name.
+All arithmetic runs in the library's kernels; nothing here computes.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (PNCE_FMT_BF16, PNCE_FMT_E4M3, PNCE_FMT_F16, PNCE_PREC_BF16,
+                   PNCE_PREC_F32, PNCE_PREC_F32S, PNCE_PREC_F64, PNCE_W_LAG_ALIAS)
+
+PRECISIONS = {"f32": PNCE_PREC_F32, "f32s": PNCE_PREC_F32S, "bf16": PNCE_PREC_BF16,
+              "f64": PNCE_PREC_F64}
+FORMATS = {"bf16": PNCE_FMT_BF16, "f16": PNCE_FMT_F16, "e4m3": PNCE_FMT_E4M3}
+_CODE_DTYPE = {"bf16": torch.int16, "f16": torch.int16, "e4m3": torch.uint8}
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _need(t: torch.Tensor, shape, dtype, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """A plan for sequence length N, T transmitters, L taps, R antennas."""
+
+    def __init__(self, N: int, T: int, L: int, R: int):
+        self.handle, self.status = _lib.pnce_create(N, T, L, R)
+        self.N, self.T, self.L, self.R = N, T, L, R
+        self.K = T * L
+        self.lag_alias = self.status == PNCE_W_LAG_ALIAS
+
+    def close(self):
+        if self.handle:
+            _lib.pnce_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- a1
+    def sequence(self) -> np.ndarray:
+        s = np.zeros(self.N, dtype=np.int8)
+        _lib.pnce_get_sequence(self.handle, s.ctypes.data)
+        return s
+
+    # ---------------------------------------------------------------- a4
+    def estimate(self, Y: torch.Tensor, precision: str = "f32s", out=None,
+                 scales=None, beta: float = 0.0) -> torch.Tensor:
+        """H = (scales/N) Y P + beta H; Y [B, R, N] complex64 (complex128 for
+        precision 'f64'). Returns H [B, R, T*L]."""
+        prec = PRECISIONS[precision]
+        cdt = torch.complex128 if prec == PNCE_PREC_F64 else torch.complex64
+        B = Y.shape[0]
+        _need(Y, (B, self.R, self.N), cdt, "Y")
+        if out is None:
+            out = torch.empty((B, self.R, self.K), dtype=cdt, device=Y.device)
+        _need(out, (B, self.R, self.K), cdt, "H")
+        if scales is not None:
+            _need(scales, (B,), torch.float32, "scales")
+        _lib.pnce_estimate(self.handle, _stream(), _ptr(Y), _ptr(out), B, prec,
+                           _ptr(scales), beta)
+        return out
+
+    # ---------------------------------------------------------------- a3
+    def pack(self, Y: torch.Tensor, fmt: str = "bf16", out=None, scales=None):
+        """Quantise Y [B, R, N] complex64 -> (codes [B, R, 2, N+1], scales [B])."""
+        B = Y.shape[0]
+        _need(Y, (B, self.R, self.N), torch.complex64, "Y")
+        if out is None:
+            out = torch.empty((B, self.R, 2, self.N + 1), dtype=_CODE_DTYPE[fmt],
+                              device=Y.device)
+        if scales is None:
+            scales = torch.empty((B,), dtype=torch.float32, device=Y.device)
+        _need(out, (B, self.R, 2, self.N + 1), _CODE_DTYPE[fmt], "Yq")
+        _need(scales, (B,), torch.float32, "scales")
+        _lib.pnce_pack(self.handle, _stream(), _ptr(Y), _ptr(out), _ptr(scales), B,
+                       FORMATS[fmt])
+        return out, scales
+
+    def estimate_packed(self, Yq: torch.Tensor, scales, fmt: str = "bf16", out=None,
+                        beta: float = 0.0) -> torch.Tensor:
+        B = Yq.shape[0]
+        _need(Yq, (B, self.R, 2, self.N + 1), _CODE_DTYPE[fmt], "Yq")
+        if scales is not None:
+            _need(scales, (B,), torch.float32, "scales")
+        if out is None:
+            out = torch.empty((B, self.R, self.K), dtype=torch.complex64, device=Yq.device)
+        _need(out, (B, self.R, self.K), torch.complex64, "H")
+        _lib.pnce_estimate_packed(self.handle, _stream(), _ptr(Yq), _ptr(scales), _ptr(out),
+                                  B, FORMATS[fmt], beta)
+        return out
+
+    # ---------------------------------------------------------------- a7
+    def adjoint(self, G: torch.Tensor, precision: str = "f32s", alpha=None, beta=0.0,
+                C=None, out=None) -> torch.Tensor:
+        """A = alpha G P^T + beta C (alpha defaults to 1/N: the transpose of
+        estimate). G [B, R, T*L] -> A [B, R, N]."""
+        prec = PRECISIONS[precision]
+        cdt = torch.complex128 if prec == PNCE_PREC_F64 else torch.complex64
+        B = G.shape[0]
+        _need(G, (B, self.R, self.K), cdt, "G")
+        if out is None:
+            out = torch.empty((B, self.R, self.N), dtype=cdt, device=G.device)
+        _need(out, (B, self.R, self.N), cdt, "A")
+        if C is not None:
+            _need(C, (B, self.R, self.N), cdt, "C")
+        a = 1.0 / self.N if alpha is None else float(alpha)
+        _lib.pnce_adjoint(self.handle, _stream(), _ptr(G), _ptr(out), _ptr(C), B, prec, a,
+                          float(beta))
+        return out
+
+    # ---------------------------------------------------------------- a6
+    def refine(self, y: torch.Tensor, X: torch.Tensor, steps: int, work=None) -> torch.Tensor:
+        """In place: `steps` LS refinement steps of X from the c64 frames y."""
+        B = y.shape[0]
+        _need(y, (B, self.R, self.N), torch.complex64, "y")
+        _need(X, (B, self.R, self.K), torch.complex64, "X")
+        if work is None and steps > 0:
+            work = torch.empty((B, self.R, self.N), dtype=torch.complex64, device=y.device)
+        _lib.pnce_refine(self.handle, _stream(), _ptr(y), _ptr(X), _ptr(work), B, steps)
+        return X

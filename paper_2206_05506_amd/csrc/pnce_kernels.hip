@@ -1,0 +1,617 @@
+// pnce_kernels.hip -- gfx950 kernels of the PN-sequence correlation channel
+// estimator (arXiv 2206.05506, Eq. 3 and Eq. 10) and of its adjoint.
+//
+// Both operations are Toeplitz +-1 contractions of complex rows:
+//   out[r][c] = alpha * sum_t in[r][t] * s'[(t - c) mod N] + beta * cin[r][c]
+// with s' the sequence (correlator: t = sample n, c = lag k) or the sequence
+// read backwards (adjoint: t = lag k, c = sample n). The +-1 operand is never
+// read from memory: every lane expands it from a bit stream held in LDS.
+//
+// Tiling (one workgroup = 4 wave64s):
+//  - tile = 32 antennas x (4 waves * 32*NC output columns);
+//  - the 32x(32-sample) input chunk of the tile is staged through LDS, already
+//    converted to the operand format of the matrix core, double-buffered with
+//    one barrier per chunk; all 4 waves read it (each owns 32*NC columns);
+//  - matrix-core A operand = input rows (real and imaginary planes), B operand
+//    = the +-1 Toeplitz tile, C = FP32 accumulators (2*NC 32x32 blocks);
+//  - Toeplitz reuse: the B fragment of column block c at k-step i equals the
+//    fragment of block 0 at k-step i - 2c, so a wave expands ONE new fragment
+//    per k-step and rotates 2*NC of them through registers.
+#include <type_traits>
+
+#include "pnce_internal.h"
+
+namespace pnce {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef float f2a8 __attribute__((ext_vector_type(2), aligned(8)));
+
+constexpr int kRows = 32;      // antennas per tile
+constexpr int kChunk = 32;     // samples per LDS stage (two 16-sample k-steps)
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+
+// ---------------------------------------------------------------------------
+// Operand formats of a stage: number of planes and dwords per plane row.
+// Rows are padded by 4 dwords so that the 16-byte fragment reads of 8
+// consecutive rows fall in distinct LDS banks.
+//   MODE_F32  : 2 fp32 planes (re, im), 32 samples + pad  -> 36 dwords
+//   MODE_F32S : 6 bf16 planes (re hi/mid/lo, im hi/mid/lo) -> 20 dwords
+//   MODE_BF16 : 2 bf16 (or f16 for IN_F16) planes          -> 20 dwords
+// ---------------------------------------------------------------------------
+template <int MODE> struct StageGeom;
+template <> struct StageGeom<MODE_F32> { static constexpr int planes = 2, rs = 36; };
+template <> struct StageGeom<MODE_F32S> { static constexpr int planes = 6, rs = 20; };
+template <> struct StageGeom<MODE_BF16> { static constexpr int planes = 2, rs = 20; };
+
+template <int MODE> constexpr int stage_dwords() {
+  return StageGeom<MODE>::planes * kRows * StageGeom<MODE>::rs;
+}
+
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x);
+}
+__device__ __forceinline__ float bf16_value(uint32_t b) {
+  return __builtin_bit_cast(float, b << 16);
+}
+__device__ __forceinline__ uint32_t pack2(uint32_t lo, uint32_t hi) {
+  return lo | (hi << 16);
+}
+
+// Exact three-way bf16 split of an FP32 value: x = hi + mid + lo up to
+// 2^-24 relative (each part rounds the remainder to nearest even; the
+// remainders are exact in FP32). Non-finite x keeps hi = x, mid = lo = 0.
+__device__ __forceinline__ void split3(float x, uint32_t &hi, uint32_t &mid,
+                                       uint32_t &lo) {
+  hi = bf16_bits(x);
+  float r1 = x - bf16_value(hi);
+  r1 = __builtin_isfinite(x) ? r1 : 0.0f;
+  mid = bf16_bits(r1);
+  float r2 = r1 - bf16_value(mid);
+  lo = bf16_bits(r2);
+}
+
+// ---------------------------------------------------------------------------
+// Global -> register loads of one stage: 32 rows x 32 samples.
+// c64 input: 512 sample pairs, thread t takes pairs t and t+256
+//   (row = pair >> 4, samples 2*(pair & 15) and +1): each wave instruction
+//   reads 4 rows x 256 contiguous bytes.
+// packed input: 32 rows x 2 planes x 64 bytes, thread t takes 16 bytes
+//   (row = t >> 3, plane = (t >> 2) & 1, 8 codes at 8*(t & 3)).
+// Samples at or beyond t_len and antennas at or beyond R read as zero.
+// ---------------------------------------------------------------------------
+struct RawC64 { f32x4 v[2]; };
+struct RawPacked { u32x4 v; };
+
+__device__ __forceinline__ void load_stage(RawC64 &raw, const float *in_frame,
+                                           int R, int a0, int ld_in, int t_len,
+                                           int n0, int tid) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int q = tid + kThreads * i;
+    const int row = q >> 4;
+    const int n = n0 + 2 * (q & 15);
+    const int a = a0 + row;
+    f32x4 x = {0.f, 0.f, 0.f, 0.f};
+    if (a < R) {
+      const float *p = in_frame + ((size_t)a * ld_in + n) * 2;
+      if (n + 1 < t_len) {
+        f4a8 t = *(const f4a8 *)p;
+        x = f32x4{t.x, t.y, t.z, t.w};
+      } else if (n < t_len) {
+        f2a8 t = *(const f2a8 *)p;
+        x.x = t.x;
+        x.y = t.y;
+      }
+    }
+    raw.v[i] = x;
+  }
+}
+
+__device__ __forceinline__ void load_stage(RawPacked &raw, const uint16_t *in_frame,
+                                           int R, int a0, int ld_in, int t_len,
+                                           int n0, int tid) {
+  const int row = tid >> 3;
+  const int plane = (tid >> 2) & 1;
+  const int n = n0 + 8 * (tid & 3);
+  const int a = a0 + row;
+  u32x4 x = {0u, 0u, 0u, 0u};
+  if (a < R) {
+    const uint16_t *p = in_frame + ((size_t)a * 2 + plane) * ld_in + n;
+    if (n + 8 <= t_len && (ld_in & 7) == 0) {
+      x = *(const u32x4 *)p;
+    } else {
+      uint32_t e[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) e[j] = (n + j < t_len) ? p[j] : 0u;
+      x = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]),
+                pack2(e[6], e[7])};
+    }
+  }
+  raw.v = x;
+}
+
+// Register -> LDS: convert to the operand format while storing.
+template <int MODE>
+__device__ __forceinline__ void store_stage(uint32_t *st, const RawC64 &raw, int tid) {
+  constexpr int RS = StageGeom<MODE>::rs;
+  constexpr int PS = kRows * RS;  // plane stride in dwords
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int q = tid + kThreads * i;
+    const int row = q >> 4;
+    const int pr = q & 15;
+    const f32x4 x = raw.v[i];  // re0, im0, re1, im1
+    if constexpr (MODE == MODE_F32) {
+      *(f2a8 *)(st + row * RS + 2 * pr) = f2a8{x.x, x.z};
+      *(f2a8 *)(st + PS + row * RS + 2 * pr) = f2a8{x.y, x.w};
+    } else if constexpr (MODE == MODE_BF16) {
+      st[row * RS + pr] = pack2(bf16_bits(x.x), bf16_bits(x.z));
+      st[PS + row * RS + pr] = pack2(bf16_bits(x.y), bf16_bits(x.w));
+    } else {  // MODE_F32S
+      uint32_t h0, m0, l0, h1, m1, l1;
+      split3(x.x, h0, m0, l0);
+      split3(x.z, h1, m1, l1);
+      st[0 * PS + row * RS + pr] = pack2(h0, h1);
+      st[1 * PS + row * RS + pr] = pack2(m0, m1);
+      st[2 * PS + row * RS + pr] = pack2(l0, l1);
+      split3(x.y, h0, m0, l0);
+      split3(x.w, h1, m1, l1);
+      st[3 * PS + row * RS + pr] = pack2(h0, h1);
+      st[4 * PS + row * RS + pr] = pack2(m0, m1);
+      st[5 * PS + row * RS + pr] = pack2(l0, l1);
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_stage(uint32_t *st, const RawPacked &raw, int tid) {
+  constexpr int RS = StageGeom<MODE>::rs;
+  constexpr int PS = kRows * RS;
+  const int row = tid >> 3;
+  const int plane = (tid >> 2) & 1;
+  *(u32x4 *)(st + plane * PS + row * RS + 4 * (tid & 3)) = raw.v;
+}
+
+// 8 bits of the periodic stream starting at bit p (p + 63 < 32 * nbw).
+__device__ __forceinline__ uint32_t window8(const uint32_t *sbits, int p) {
+  const uint32_t w0 = sbits[p >> 5];
+  const uint32_t w1 = sbits[(p >> 5) + 1];
+  return __builtin_amdgcn_alignbit(w1, w0, (uint32_t)(p & 31)) & 0xFFu;
+}
+
+// Expand 8 bits into 8 16-bit +-1 values (bit 1 -> sign set). ONE is the
+// 16-bit pattern of +1 in both halves: 0x3F803F80 (bf16), 0x3C003C00 (f16).
+template <uint32_t ONE>
+__device__ __forceinline__ u32x4 expand16(uint32_t x) {
+  u32x4 r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    r[e] = ONE | ((x << (15 - 2 * e)) & 0x8000u) | ((x << (30 - 2 * e)) & 0x80000000u);
+  return r;
+}
+
+// Window slot register file: 16-bit modes keep the expanded fragment, the
+// FP32 mode keeps the raw 8 bits and expands one bit per MFMA.
+template <int MODE> struct Win { u32x4 f; };
+template <> struct Win<MODE_F32> { uint32_t f; };
+
+template <int MODE, int IN>
+__device__ __forceinline__ void make_window(Win<MODE> &w, uint32_t bits8) {
+  if constexpr (MODE == MODE_F32) {
+    w.f = bits8;
+  } else if constexpr (IN == IN_F16) {
+    w.f = expand16<0x3C003C00u>(bits8);
+  } else {
+    w.f = expand16<0x3F803F80u>(bits8);
+  }
+}
+
+__device__ __forceinline__ int pos_mod(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------------------
+// The tiled kernel.
+// ---------------------------------------------------------------------------
+// Prefetch depth (register sets of in-flight stage data) per mode: deep for
+// the HBM-bound 16-bit modes, 2 where registers are scarce.
+template <int MODE, int NC> struct Prefetch { static constexpr int value = 2; };
+template <> struct Prefetch<MODE_BF16, 4> { static constexpr int value = 4; };
+template <> struct Prefetch<MODE_BF16, 2> { static constexpr int value = 4; };
+template <> struct Prefetch<MODE_BF16, 1> { static constexpr int value = 4; };
+
+template <int MODE, int IN, int NC>
+__global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, int tiles_c,
+                                                         int nbw_pad) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+  constexpr int NWIN = 2 * NC;
+  constexpr int RS = StageGeom<MODE>::rs;
+  constexpr int PS = kRows * RS;
+  constexpr int SDW = stage_dwords<MODE>();
+  constexpr int PF = Prefetch<MODE, NC>::value;
+  constexpr int CPB = (NWIN / 2 > PF) ? NWIN / 2 : PF;  // chunks per unrolled body
+  static_assert(CPB % PF == 0 && CPB % (NWIN / 2) == 0, "body must cover both rotations");
+  using Raw = typename std::conditional<IN == IN_C64, RawC64, RawPacked>::type;
+
+  uint32_t *sbits = smem;
+  uint32_t *stage = smem + nbw_pad;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m = lane & 31;
+  const int h = lane >> 5;
+
+  // Tile order: column groups of one (frame, antenna block) are consecutive,
+  // and consecutive tiles go to the same XCD (workgroups are dealt to the 8
+  // XCDs round robin), so a row block's input is fetched into one L2.
+  const int nt = a.batch * tiles_r * tiles_c;
+  const int bid = blockIdx.x;
+  const int t = (nt % 8 == 0) ? (bid % 8) * (nt / 8) + bid / 8 : bid;
+  const int cg = t % tiles_c;
+  const int rest = t / tiles_c;
+  const int rb = rest % tiles_r;
+  const int b = rest / tiles_r;
+  const int a0 = rb * kRows;
+  const int col0 = cg * (kWaves * 32 * NC) + wave * 32 * NC;
+
+  const int nchunks = (a.t_len + kChunk - 1) / kChunk;
+  auto load_chunk = [&](Raw &r, int chunk) {
+    if constexpr (IN == IN_C64) {
+      const float *fin = (const float *)a.in + (size_t)b * a.R * a.ld_in * 2;
+      load_stage(r, fin, a.R, a0, a.ld_in, a.t_len, chunk * kChunk, tid);
+    } else {
+      const uint16_t *fin = (const uint16_t *)a.in + (size_t)b * a.R * 2 * a.ld_in;
+      load_stage(r, fin, a.R, a0, a.ld_in, a.t_len, chunk * kChunk, tid);
+    }
+  };
+
+  // Pipeline: chunk j travels global -> raw[j % PF] (issued PF chunks ahead)
+  // -> LDS stage (j & 1), converted -> matrix-core fragments.
+  Raw raw[PF];
+#pragma unroll
+  for (int j = 0; j < PF; ++j)
+    if (j < nchunks) load_chunk(raw[j], j);
+  for (int i = tid; i < a.nbw; i += kThreads) sbits[i] = a.bits[i];
+  store_stage<MODE>(stage, raw[0], tid);
+  if (PF < nchunks) load_chunk(raw[0], PF);
+  __syncthreads();
+
+  // Bit position of this lane's B fragment for block 0 at k-step 0:
+  // reduction index t0 = 8h (+ e), output column col0 + m.
+  const int p_base = pos_mod(8 * h - m - col0, a.N);
+
+  Win<MODE> win[NWIN];
+  // Prologue: fragments of k-steps -(NWIN-2) .. -1 (used by blocks c >= 1
+  // during the first 2c k-steps).
+#pragma unroll
+  for (int j = 1; j <= NWIN - 2; ++j) {
+    const int p = pos_mod(p_base - 16 * j, a.N);
+    make_window<MODE, IN>(win[NWIN - j], window8(sbits, p));
+  }
+
+  f32x16 acc_re[NC], acc_im[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      acc_re[c][v] = 0.f;
+      acc_im[c][v] = 0.f;
+    }
+  }
+
+  const int nbodies = (nchunks + CPB - 1) / CPB;
+  for (int body = 0; body < nbodies; ++body) {
+#pragma unroll
+    for (int cc = 0; cc < CPB; ++cc) {
+      const int chunk = body * CPB + cc;
+      if (chunk < nchunks) {
+        const uint32_t *st = stage + (chunk & 1) * SDW;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int q = (2 * cc + u) % NWIN;  // slot of k-step i = 2*chunk + u
+          const int i = 2 * chunk + u;
+          make_window<MODE, IN>(win[q], window8(sbits, p_base + 16 * i));
+          if constexpr (MODE == MODE_F32) {
+            const float *pre = (const float *)st + m * RS + 16 * u + 8 * h;
+            const float *pim = pre + PS;
+            f32x4 r0 = *(const f32x4 *)pre, r1 = *(const f32x4 *)(pre + 4);
+            f32x4 i0 = *(const f32x4 *)pim, i1 = *(const f32x4 *)(pim + 4);
+            float are[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+            float aim[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+#pragma unroll
+              for (int c = 0; c < NC; ++c) {
+                const uint32_t x = win[(q - 2 * c + NWIN) % NWIN].f;
+                const float bv =
+                    __builtin_bit_cast(float, 0x3F800000u | ((x << (31 - j)) & 0x80000000u));
+                acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[j], bv, acc_re[c], 0, 0, 0);
+                acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[j], bv, acc_im[c], 0, 0, 0);
+              }
+            }
+          } else {
+            constexpr int NP = (MODE == MODE_F32S) ? 3 : 1;
+            u32x4 are[NP], aim[NP];
+#pragma unroll
+            for (int s = 0; s < NP; ++s) {
+              are[s] = *(const u32x4 *)(st + s * PS + m * RS + 8 * u + 4 * h);
+              aim[s] = *(const u32x4 *)(st + (NP + s) * PS + m * RS + 8 * u + 4 * h);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              const u32x4 bw = win[(q - 2 * c + NWIN) % NWIN].f;
+#pragma unroll
+              for (int s = 0; s < NP; ++s) {
+                if constexpr (IN == IN_F16) {
+                  acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                      __builtin_bit_cast(f16x8, are[s]), __builtin_bit_cast(f16x8, bw),
+                      acc_re[c], 0, 0, 0);
+                  acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                      __builtin_bit_cast(f16x8, aim[s]), __builtin_bit_cast(f16x8, bw),
+                      acc_im[c], 0, 0, 0);
+                } else {
+                  acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                      __builtin_bit_cast(bf16x8, are[s]), __builtin_bit_cast(bf16x8, bw),
+                      acc_re[c], 0, 0, 0);
+                  acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                      __builtin_bit_cast(bf16x8, aim[s]), __builtin_bit_cast(bf16x8, bw),
+                      acc_im[c], 0, 0, 0);
+                }
+              }
+            }
+          }
+        }
+        if (chunk + 1 < nchunks) {
+          // chunk + 1 arrived in raw[(chunk + 1) % PF]; refill that set.
+          store_stage<MODE>(stage + ((chunk + 1) & 1) * SDW, raw[(cc + 1) % PF], tid);
+          if (chunk + 1 + PF < nchunks) load_chunk(raw[(cc + 1) % PF], chunk + 1 + PF);
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // Epilogue: lane (m, h) holds, for block c, output column col0 + 32c + m
+  // and rows 8*(v/4) + 4*h + (v%4) of the 32x32 accumulator.
+  const float alpha = a.alpha * (a.scales ? a.scales[b] : 1.0f);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int col = col0 + 32 * c + m;
+    if (col < a.c_len) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int ant = a0 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (ant < a.R) {
+          const size_t o = ((size_t)(b * a.R + ant) * a.ld_out + col) * 2;
+          float re = alpha * acc_re[c][v];
+          float im = alpha * acc_im[c][v];
+          if (a.beta != 0.0f) {
+            const f2a8 old = *(const f2a8 *)(a.cin + o);
+            re += a.beta * old.x;
+            im += a.beta * old.y;
+          }
+          *(f2a8 *)(a.out + o) = f2a8{re, im};
+        }
+      }
+    }
+  }
+}
+
+template <int MODE, int IN, int NC>
+static hipError_t launch_tg_nc(const TgArgs &a, hipStream_t s) {
+  const int tiles_r = (a.R + kRows - 1) / kRows;
+  const int cols_per_tile = kWaves * 32 * NC;
+  const int tiles_c = (a.c_len + cols_per_tile - 1) / cols_per_tile;
+  const long nt = (long)a.batch * tiles_r * tiles_c;
+  if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
+  const int nbw_pad = (a.nbw + 3) & ~3;
+  const size_t lds = (size_t)(nbw_pad + 2 * stage_dwords<MODE>()) * 4;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)tg_kernel<MODE, IN, NC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((tg_kernel<MODE, IN, NC>), dim3((unsigned)nt), dim3(kThreads), lds, s, a,
+                     tiles_r, tiles_c, nbw_pad);
+  return hipGetLastError();
+}
+
+template <int MODE, int IN>
+static hipError_t launch_tg_mode(const TgArgs &a, hipStream_t s) {
+  if (a.c_len > 256) return launch_tg_nc<MODE, IN, 4>(a, s);
+  if (a.c_len > 128) return launch_tg_nc<MODE, IN, 2>(a, s);
+  return launch_tg_nc<MODE, IN, 1>(a, s);
+}
+
+hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s) {
+  if (in_fmt == IN_C64) {
+    switch (mode) {
+      case MODE_F32: return launch_tg_mode<MODE_F32, IN_C64>(a, s);
+      case MODE_F32S: return launch_tg_mode<MODE_F32S, IN_C64>(a, s);
+      case MODE_BF16: return launch_tg_mode<MODE_BF16, IN_C64>(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (in_fmt == IN_BF16) return launch_tg_mode<MODE_BF16, IN_BF16>(a, s);
+  if (in_fmt == IN_F16) return launch_tg_mode<MODE_BF16, IN_F16>(a, s);
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// FP64-accumulating vector kernel: one thread per output element, the sum
+// over t in natural order. Used for the FP64 path (c128 in and out) and for
+// the final residual of refinement (c64 in and out, FP64 sums).
+// ---------------------------------------------------------------------------
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void tg64_kernel(Tg64Args a, int cblocks) {
+  const long blk = blockIdx.x;
+  const long row = blk / cblocks;  // frame * R + antenna
+  const int col = (int)(blk - row * cblocks) * 256 + threadIdx.x;
+  if (col >= a.c_len) return;
+  const int b = (int)(row / a.R);
+  const TI *x = (const TI *)a.in + (size_t)row * a.ld_in * 2;
+  int p = (a.N - col % a.N) % a.N;  // (0 - col) mod N
+  double re = 0.0, im = 0.0;
+  for (int t = 0; t < a.t_len; ++t) {
+    const bool neg = (a.bits[p >> 5] >> (p & 31)) & 1u;
+    const double xr = (double)x[2 * t], xi = (double)x[2 * t + 1];
+    re += neg ? -xr : xr;
+    im += neg ? -xi : xi;
+    if (++p == a.N) p = 0;
+  }
+  const double alpha = a.alpha * (a.scales ? (double)a.scales[b] : 1.0);
+  re *= alpha;
+  im *= alpha;
+  const size_t o = ((size_t)row * a.ld_out + col) * 2;
+  if (a.beta != 0.0) {
+    const TO *c = (const TO *)a.cin;
+    re += a.beta * (double)c[o];
+    im += a.beta * (double)c[o + 1];
+  }
+  TO *out = (TO *)a.out;
+  out[o] = (TO)re;
+  out[o + 1] = (TO)im;
+}
+
+hipError_t launch_tg64(const Tg64Args &a, hipStream_t s) {
+  const long rows = (long)a.batch * a.R;
+  const int cblocks = (a.c_len + 255) / 256;
+  const long nblk = rows * cblocks;
+  if (nblk <= 0 || nblk > 0x7FFFFFFFL) return hipErrorInvalidValue;
+  if (a.in_f64 && a.out_f64)
+    hipLaunchKernelGGL((tg64_kernel<double, double>), dim3((unsigned)nblk), dim3(256), 0, s, a,
+                       cblocks);
+  else if (!a.in_f64 && !a.out_f64)
+    hipLaunchKernelGGL((tg64_kernel<float, float>), dim3((unsigned)nblk), dim3(256), 0, s, a,
+                       cblocks);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Quantiser.
+// ---------------------------------------------------------------------------
+// Smallest power of two 2^e with m <= target * 2^e (m finite, > 0).
+__device__ float pow2_scale(float m, float target) {
+  int e;
+  (void)frexpf(m / target, &e);
+  while ((double)m > (double)target * ldexp(1.0, e)) ++e;
+  while ((double)m <= (double)target * ldexp(1.0, e - 1)) --e;
+  return ldexpf(1.0f, e);
+}
+
+// One workgroup per frame: max |re|, |im| over R*N samples, then the scale.
+__global__ __launch_bounds__(256) void frame_scale_kernel(const float *y, float *scales,
+                                                          long n_floats, float target) {
+  __shared__ float smax[256];
+  __shared__ int snan[256];
+  const float *f = y + (size_t)blockIdx.x * n_floats;
+  float mx = 0.0f;
+  int nan = 0;
+  for (long i = threadIdx.x; i < n_floats; i += 256) {
+    const float v = fabsf(f[i]);
+    nan |= (v != v);
+    mx = fmaxf(mx, v);
+  }
+  smax[threadIdx.x] = mx;
+  snan[threadIdx.x] = nan;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + s]);
+      snan[threadIdx.x] |= snan[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float m = smax[0];
+    float sc = 1.0f;
+    if (!snan[0] && m > 0.0f && __builtin_isfinite(m)) sc = pow2_scale(m, target);
+    scales[blockIdx.x] = sc;
+  }
+}
+
+// float -> OCP e4m3fn code, round to nearest even, saturating at +-448;
+// NaN -> 0x7F with the sign bit.
+__device__ __forceinline__ uint32_t e4m3_code(float x) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, x);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const float ax = fabsf(x);
+  if (ax != ax) return sign | 0x7Fu;
+  if (ax >= 448.0f) return sign | 0x7Eu;
+  if (ax < 0.015625f) {  // below 2^-6: subnormal grid of step 2^-9
+    return sign | (uint32_t)__builtin_rintf(ax * 512.0f);
+  }
+  int E = (int)((__builtin_bit_cast(uint32_t, ax) >> 23) & 0xFF) - 127;  // -6 .. 8
+  uint32_t q = (uint32_t)__builtin_rintf(ldexpf(ax, 3 - E));              // 8 .. 16
+  if (q == 16u) {
+    q = 8u;
+    ++E;
+  }
+  return sign | ((uint32_t)(E + 7) << 3) | (q - 8u);
+}
+
+// One thread per (row, sample) of the padded planar output.
+template <int FMT>
+__global__ __launch_bounds__(256) void pack_kernel(const float *y, void *yq, const float *scales,
+                                                   int R, int N, long total) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int Np = N + 1;
+  const long row = i / Np;  // frame * R + antenna
+  const int n = (int)(i - row * Np);
+  const int b = (int)(row / R);
+  float re = 0.0f, im = 0.0f;
+  if (n < N) {
+    const float inv = 1.0f / scales[b];
+    const f2a8 v = *(const f2a8 *)(y + (row * N + n) * 2);
+    re = v.x * inv;
+    im = v.y * inv;
+  }
+  const size_t o = (size_t)row * 2 * Np + n;
+  if constexpr (FMT == 3) {
+    uint8_t *q = (uint8_t *)yq;
+    q[o] = (uint8_t)(n < N ? e4m3_code(re) : 0u);
+    q[o + Np] = (uint8_t)(n < N ? e4m3_code(im) : 0u);
+  } else {
+    uint16_t *q = (uint16_t *)yq;
+    if constexpr (FMT == 1) {
+      q[o] = (uint16_t)bf16_bits(re);
+      q[o + Np] = (uint16_t)bf16_bits(im);
+    } else {
+      q[o] = __builtin_bit_cast(uint16_t, (_Float16)re);
+      q[o + Np] = __builtin_bit_cast(uint16_t, (_Float16)im);
+    }
+  }
+}
+
+hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R, int N,
+                       int fmt, hipStream_t s) {
+  const float target = (fmt == 3) ? 448.0f : 1.0f;
+  hipLaunchKernelGGL(frame_scale_kernel, dim3(batch), dim3(256), 0, s, y, scales,
+                     (long)R * N * 2, target);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long total = (long)batch * R * (N + 1);
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (fmt == 1)
+    hipLaunchKernelGGL((pack_kernel<1>), grid, dim3(256), 0, s, y, yq, scales, R, N, total);
+  else if (fmt == 2)
+    hipLaunchKernelGGL((pack_kernel<2>), grid, dim3(256), 0, s, y, yq, scales, R, N, total);
+  else if (fmt == 3)
+    hipLaunchKernelGGL((pack_kernel<3>), grid, dim3(256), 0, s, y, yq, scales, R, N, total);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace pnce

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI (no GPU needed): every symbol that
+include/pnce.h declares is exported, and argument validation answers before
+any HIP call."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pnce.h")
+LIB = os.path.join(ROOT, "paper_2206_05506_amd", "libpnce.so")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pnce_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libpnce.so is not built (run python -m paper_2206_05506_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("pnce_create", "pnce_destroy", "pnce_estimate", "pnce_adjoint", "pnce_pack",
+              "pnce_estimate_packed", "pnce_refine", "pnce_get_sequence"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (pnce_\w+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        getattr(lib, n)
+
+
+def test_python_binding_names_match_header():
+    sys.path.insert(0, ROOT)
+    from paper_2206_05506_amd import _lib
+    for n in declared_functions():
+        assert hasattr(_lib, n), n
+    assert set(_lib.SYMBOLS) == set(declared_functions())
+
+
+def _create(lib, N, T, L, R):
+    h = ctypes.c_void_p()
+    lib.pnce_create.argtypes = [ctypes.POINTER(ctypes.c_void_p)] + [ctypes.c_int] * 4
+    st = lib.pnce_create(ctypes.byref(h), N, T, L, R)
+    return st, h
+
+
+@pytest.mark.parametrize("N,T,L,R,want", [
+    (1000, 4, 16, 16, -2),    # not 2^d - 1
+    (1, 1, 1, 1, -2),         # d = 1
+    (131071, 1, 1, 1, -2),    # d = 17
+    (0, 1, 1, 1, -2),
+    (127, 0, 16, 16, -1),
+    (127, 4, -1, 16, -1),
+    (127, 4, 16, 0, -1),
+    (127, 4, 16, 70000, -1),  # R above 65535
+    (127, 200, 16, 1, -1),    # T*L > 16 N
+])
+def test_create_validates_before_touching_the_device(lib, N, T, L, R, want):
+    st, h = _create(lib, N, T, L, R)
+    assert st == want
+    assert not h.value
+
+
+def test_create_null_output_pointer(lib):
+    lib.pnce_create.argtypes = [ctypes.c_void_p] + [ctypes.c_int] * 4
+    assert lib.pnce_create(None, 127, 4, 16, 16) == -1
+
+
+def test_null_plan_is_rejected_everywhere(lib):
+    P = ctypes.c_void_p
+    lib.pnce_estimate.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_double]
+    assert lib.pnce_estimate(None, None, None, None, 1, 0, None, 0.0) == -1
+    lib.pnce_adjoint.argtypes = [P, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double]
+    assert lib.pnce_adjoint(None, None, None, None, None, 1, 0, 1.0, 0.0) == -1
+    lib.pnce_refine.argtypes = [P, P, P, P, P, ctypes.c_int, ctypes.c_int]
+    assert lib.pnce_refine(None, None, None, None, None, 1, 1) == -1
+    lib.pnce_pack.argtypes = [P, P, P, P, P, ctypes.c_int, ctypes.c_int]
+    assert lib.pnce_pack(None, None, None, None, None, 1, 1) == -1
+    lib.pnce_destroy.argtypes = [P]
+    assert lib.pnce_destroy(None) == 0
+    lib.pnce_get_sequence.argtypes = [P, P]
+    assert lib.pnce_get_sequence(None, None) == -1
+
+
+def test_status_strings(lib):
+    lib.pnce_status_string.restype = ctypes.c_char_p
+    for st in (0, 1, -1, -2, -3, -4):
+        assert lib.pnce_status_string(st)
+    assert lib.pnce_status_string(99) == b"unknown status"
+
+
+def test_alloc_fault_hook():
+    code = ("import ctypes,sys; l=ctypes.CDLL(sys.argv[1]); h=ctypes.c_void_p();"
+            "l.pnce_last_error.restype=ctypes.c_char_p;"
+            "st=l.pnce_create(ctypes.byref(h),127,4,16,16);"
+            "print(st, l.pnce_last_error().decode())")
+    env = dict(os.environ, PNCE_FAULT="alloc")
+    out = subprocess.run([sys.executable, "-c", code, LIB], capture_output=True, text=True,
+                         env=env, check=True).stdout.split(None, 1)
+    assert out[0] == "-3" and "PNCE_FAULT" in out[1]

@@ -1,0 +1,219 @@
+"""GPU parity of libpnce.so against the FP64 oracle, through the C ABI.
+
+Tolerances (written here, derived in the design notes):
+  * FP32-accurate contractions (f32, f32s): normwise relative error per frame
+    <= 1e-5 against the FP64 oracle on the same input.
+  * bf16 in-register rounding: the oracle correlates the same bf16-rounded
+    input, so only FP32 accumulation differs: the same 1e-5 bound.
+  * f64: 1e-12.
+  * integer/byte work (sequence, quantised codes, scales): bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import bf16_round, dev, frames, host
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-12
+
+# (N, T, L, R, B): several tiles, ragged antenna blocks and column groups,
+# tiny degenerate sizes, the lag-alias case (T*L > N) and the plain workload.
+SHAPES = [
+    (3, 1, 2, 1, 1),        # d = 2: one-chunk reduction, K < 32
+    (7, 2, 3, 5, 2),        # d = 3
+    (31, 2, 4, 2, 1),       # gradient-check instance
+    (31, 3, 5, 7, 3),       # ragged R and K
+    (63, 5, 16, 9, 2),      # T*L = 80 > N = 63: lag alias
+    (127, 4, 16, 16, 1),    # plain workload
+    (255, 4, 32, 40, 2),    # K = 128, two antenna blocks (ragged)
+    (511, 8, 32, 33, 2),    # K = 256, NC = 2 tiles, 33 antennas
+    (1023, 16, 32, 64, 3),  # FP32-baseline frame shape
+    (2047, 16, 64, 32, 1),  # K = 1024: two column groups
+    (4095, 32, 64, 32, 1),  # precision-study frame shape (R reduced)
+]
+
+
+def _plan(N, T, L, R):
+    from paper_2206_05506_amd import Plan
+    return Plan(N, T, L, R)
+
+
+def _rand_frames(N, R, B, seed):
+    return synth.gaussian((B, R, N), seed).astype(np.complex64)
+
+
+@pytest.mark.parametrize("d", list(range(2, 17)))
+def test_sequence_bit_exact(d):
+    N = (1 << d) - 1
+    with _plan(N, 1, 1, 1) as p:
+        assert np.array_equal(p.sequence(), oracle.mseq(d))
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
+@pytest.mark.parametrize("prec", ["f32", "f32s", "bf16"])
+def test_estimate_parity(shape, prec):
+    N, T, L, R, B = shape
+    K = T * L
+    y = _rand_frames(N, R, B, seed=N + K + R)
+    with _plan(N, T, L, R) as p:
+        s = p.sequence()
+        H = host(p.estimate(dev(y), prec))
+        torch.cuda.synchronize()
+    x = bf16_round(y) if prec == "bf16" else y.astype(np.complex128)
+    ref = oracle.correlate(x, s, K)
+    err = oracle.relerr(H, ref)
+    print(f"estimate {prec} N={N} K={K} R={R} B={B}: relerr {err:.3e}")
+    assert err <= TOL32
+
+
+@pytest.mark.parametrize("shape", [SHAPES[2], SHAPES[4], SHAPES[6]],
+                         ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
+def test_estimate_f64_parity(shape):
+    N, T, L, R, B = shape
+    y = synth.gaussian((B, R, N), 5)
+    with _plan(N, T, L, R) as p:
+        H = host(p.estimate(dev(y, torch.complex128), "f64"))
+        ref = oracle.correlate(y, p.sequence(), T * L)
+    assert oracle.relerr(H, ref) <= TOL64
+
+
+def test_estimate_plain_workload_structured():
+    """Plain workload (N=127, T=4, L=16, R=16, SNR 10 dB) on the seeded
+    multiplexed frame, and the noiseless bias closed form on the GPU."""
+    cfg = synth.PLAIN
+    y, h, s = frames(cfg)
+    with _plan(cfg.N, cfg.T, cfg.L, cfg.R) as p:
+        H = host(p.estimate(dev(y), "f32s"))
+        y0, _ = oracle.received(s, h, np.zeros_like(y), np.array([300.0]))
+        H0 = host(p.estimate(dev(y0.astype(np.complex64)), "f32"))
+    assert oracle.relerr(H, oracle.correlate(y, s, cfg.K)) <= TOL32
+    hs = h.reshape(1, cfg.R, cfg.K)
+    expect = hs + (hs - hs.sum(axis=-1, keepdims=True)) / cfg.N
+    assert oracle.relerr(H0, expect) <= TOL32
+
+
+def test_estimate_scales_and_beta():
+    N, T, L, R, B = 255, 4, 16, 8, 3
+    y = _rand_frames(N, R, B, 7)
+    H0 = synth.gaussian((B, R, T * L), 8).astype(np.complex64)
+    sc = np.array([0.5, 2.0, 3.0], dtype=np.float32)
+    with _plan(N, T, L, R) as p:
+        Hd = dev(H0)
+        p.estimate(dev(y), "f32s", out=Hd, scales=torch.from_numpy(sc).cuda(), beta=0.25)
+        H = host(Hd)
+        ref = sc[:, None, None] * oracle.correlate(y, p.sequence(), T * L) + 0.25 * H0
+    assert oracle.relerr(H, ref) <= TOL32
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
+@pytest.mark.parametrize("prec", ["f32", "f32s"])
+def test_adjoint_parity(shape, prec):
+    N, T, L, R, B = shape
+    K = T * L
+    G = synth.gaussian((B, R, K), K + R).astype(np.complex64)
+    C = synth.gaussian((B, R, N), N).astype(np.complex64)
+    with _plan(N, T, L, R) as p:
+        s = p.sequence()
+        A = host(p.adjoint(dev(G), prec))
+        A2 = host(p.adjoint(dev(G), prec, alpha=-1.0, beta=1.0, C=dev(C)))
+    ref = oracle.adjoint(G, s)
+    assert oracle.relerr(A, ref) <= TOL32
+    ref2 = C.astype(np.complex128) - N * ref
+    assert oracle.relerr(A2, ref2) <= TOL32
+
+
+def test_adjoint_f64_and_dot_identity():
+    N, T, L, R, B = 63, 3, 8, 4, 2
+    G = synth.gaussian((B, R, T * L), 1)
+    Y = synth.gaussian((B, R, N), 2)
+    with _plan(N, T, L, R) as p:
+        A = host(p.adjoint(dev(G, torch.complex128), "f64"))
+        H = host(p.estimate(dev(Y, torch.complex128), "f64"))
+        assert oracle.relerr(A, oracle.adjoint(G, p.sequence())) <= TOL64
+    assert abs(np.vdot(G, H) - np.vdot(A, Y)) < 1e-10 * abs(np.vdot(G, H))
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "e4m3"])
+@pytest.mark.parametrize("shape", [(31, 2, 4, 3, 2), (255, 4, 32, 40, 2), (1023, 16, 32, 64, 2)],
+                         ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
+def test_pack_bit_exact(shape, fmt):
+    N, T, L, R, B = shape
+    y = _rand_frames(N, R, B, 3) * np.array([1e-3, 40.0])[:B, None, None].astype(np.float32)
+    y[0, 0, 0] = 0.0
+    with _plan(N, T, L, R) as p:
+        q, sc = p.pack(dev(y), fmt)
+        q = host(q)
+        sc = host(sc)
+    ref_q, ref_sc = oracle.quantize(y, fmt)
+    assert np.array_equal(sc, ref_sc)
+    assert np.array_equal(q.view(ref_q.dtype), ref_q)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
+def test_estimate_packed_parity(shape, fmt):
+    N, T, L, R, B = shape
+    y = _rand_frames(N, R, B, 11)
+    with _plan(N, T, L, R) as p:
+        q, sc = p.pack(dev(y), fmt)
+        H = host(p.estimate_packed(q, sc, fmt))
+        s = p.sequence()
+        qh, sch = host(q), host(sc)
+    x = oracle.dequantize(qh.view(np.uint16), sch, fmt, N)
+    ref = oracle.correlate(x, s, T * L)
+    assert oracle.relerr(H, ref) <= TOL32
+
+
+@pytest.mark.parametrize("shape", [(127, 4, 16, 16, 1), (1023, 16, 32, 64, 2), (255, 4, 16, 8, 2)],
+                         ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
+def test_refine_tracks_fp64_iterates(shape):
+    """Each refinement iterate within 1e-5 of the FP64 oracle iterate with the
+    same step count (started from the FP64 correlation of the same y)."""
+    N, T, L, R, B = shape
+    cfg = synth.Config("t", oracle.degree_of(N), T, L, R, B, 8.0, 0.0, 20.0, 9)
+    y, h, s = frames(cfg)
+    its = oracle.refine(y, s, cfg.K, 5)
+    with _plan(N, T, L, R) as p:
+        yd = dev(y)
+        for k in range(6):
+            X = p.estimate(yd, "f32s")
+            p.refine(yd, X, k)
+            err = oracle.relerr(host(X), its[k])
+            print(f"refine k={k}: relerr vs FP64 iterate {err:.3e}")
+            assert err <= TOL32
+
+
+def test_fp32_baseline_full_batch_sampled():
+    """Full FP32-baseline workload (N=1023, T=16, L=32, R=64, B=256) in the
+    benchmark's launch configuration; sampled frames checked by the oracle."""
+    cfg = synth.FP32
+    y, _, s = frames(cfg)
+    with _plan(cfg.N, cfg.T, cfg.L, cfg.R) as p:
+        yd = dev(y)
+        Hs = host(p.estimate(yd, "f32s"))
+        Hb = host(p.estimate(yd, "bf16"))
+        Hf = host(p.estimate(yd, "f32"))
+    pick = [0, 1, 97, 128, 255]
+    ref = oracle.correlate(y[pick], s, cfg.K)
+    assert oracle.relerr(Hs[pick], ref) <= TOL32
+    assert oracle.relerr(Hf[pick], ref) <= TOL32
+    refb = oracle.correlate(bf16_round(y[pick]), s, cfg.K)
+    assert oracle.relerr(Hb[pick], refb) <= TOL32
+
+
+def test_nonfinite_inputs_propagate():
+    N, T, L, R = 63, 2, 8, 2
+    y = _rand_frames(N, R, 1, 4)
+    y[0, 0, 5] = np.nan
+    y[0, 1, 7] = np.inf
+    with _plan(N, T, L, R) as p:
+        for prec in ("f32", "f32s", "bf16"):
+            H = host(p.estimate(dev(y), prec))
+            assert np.all(np.isnan(H[0, 0].real))
+            assert np.all(~np.isfinite(H[0, 1].real))
+            assert np.all(np.isfinite(H[0, 1].imag))
