@@ -92,14 +92,19 @@ pnce_status pnce_get_shape(const pnce_plan *plan, int *N, int *T, int *L, int *R
 
 /*
  * Correlator (Eq. 3, Eq. 10) on complex input.
- *   H = alpha_b * (Y P) + beta * H,  alpha_b = (scales ? scales[b] : 1) / N.
+ *   H = alpha * s_b * (Y P) + beta * H,  s_b = scales ? scales[b] : 1,
+ *   (Y P)[b][r][k] = sum_{n<N} Y[b][r][n] s[(n - k) mod N].
+ * alpha = 1/N is the correlator of Eq. 3; alpha = 1 gives P^T applied to Y
+ * (the backward of the receive model P x). alpha and beta are applied in
+ * FP32 (FP64 for PNCE_PREC_F64).
  * Y: [batch][R][N] c64 (c128 when precision == PNCE_PREC_F64);
  * H: [batch][R][T*L] c64 (c128 for PNCE_PREC_F64), read only if beta != 0;
  * scales: NULL or `batch` device floats. Y and H must not overlap.
+ * precision: PNCE_PREC_F32, _F32S, _BF16 or _F64.
  * Errors: null Y/H, batch <= 0, unknown precision -> PNCE_E_INVALID.
  */
 pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y,
-                          void *H, int batch, int precision,
+                          void *H, int batch, int precision, double alpha,
                           const float *scales, double beta);
 
 /*

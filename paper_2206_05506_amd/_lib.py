@@ -54,7 +54,7 @@ def _load() -> ctypes.CDLL:
         "pnce_destroy": ([_P], _I),
         "pnce_get_sequence": ([_P, _P], _I),
         "pnce_get_shape": ([_P, _P, _P, _P, _P], _I),
-        "pnce_estimate": ([_P, _P, _P, _P, _I, _I, _P, _D], _I),
+        "pnce_estimate": ([_P, _P, _P, _P, _I, _I, _D, _P, _D], _I),
         "pnce_pack": ([_P, _P, _P, _P, _P, _I, _I], _I),
         "pnce_estimate_packed": ([_P, _P, _P, _P, _P, _I, _I, _D], _I),
         "pnce_adjoint": ([_P, _P, _P, _P, _P, _I, _I, _D, _D], _I),
@@ -101,8 +101,8 @@ def pnce_get_shape(plan):
     return tuple(x.value for x in v)
 
 
-def pnce_estimate(plan, stream, Y, H, batch, precision, scales, beta) -> int:
-    return check(lib.pnce_estimate(plan, stream, Y, H, batch, precision, scales, beta),
+def pnce_estimate(plan, stream, Y, H, batch, precision, alpha, scales, beta) -> int:
+    return check(lib.pnce_estimate(plan, stream, Y, H, batch, precision, alpha, scales, beta),
                  "pnce_estimate")
 
 

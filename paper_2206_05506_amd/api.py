@@ -74,9 +74,10 @@ class Plan:
 
     # ---------------------------------------------------------------- a4
     def estimate(self, Y: torch.Tensor, precision: str = "f32s", out=None,
-                 scales=None, beta: float = 0.0) -> torch.Tensor:
-        """H = (scales/N) Y P + beta H; Y [B, R, N] complex64 (complex128 for
-        precision 'f64'). Returns H [B, R, T*L]."""
+                 scales=None, beta: float = 0.0, alpha=None) -> torch.Tensor:
+        """H = alpha * scales_b * (Y P) + beta H with alpha = 1/N by default
+        (the correlator); Y [B, R, N] complex64 (complex128 for precision
+        'f64'). Returns H [B, R, T*L]."""
         prec = PRECISIONS[precision]
         cdt = torch.complex128 if prec == PNCE_PREC_F64 else torch.complex64
         B = Y.shape[0]
@@ -86,8 +87,9 @@ class Plan:
         _need(out, (B, self.R, self.K), cdt, "H")
         if scales is not None:
             _need(scales, (B,), torch.float32, "scales")
-        _lib.pnce_estimate(self.handle, _stream(), _ptr(Y), _ptr(out), B, prec,
-                           _ptr(scales), beta)
+        a = 1.0 / self.N if alpha is None else float(alpha)
+        _lib.pnce_estimate(self.handle, _stream(), _ptr(Y), _ptr(out), B, prec, a,
+                           _ptr(scales), float(beta))
         return out
 
     # ---------------------------------------------------------------- a3
@@ -116,7 +118,7 @@ class Plan:
             out = torch.empty((B, self.R, self.K), dtype=torch.complex64, device=Yq.device)
         _need(out, (B, self.R, self.K), torch.complex64, "H")
         _lib.pnce_estimate_packed(self.handle, _stream(), _ptr(Yq), _ptr(scales), _ptr(out),
-                                  B, FORMATS[fmt], beta)
+                                  B, FORMATS[fmt], float(beta))
         return out
 
     # ---------------------------------------------------------------- a7

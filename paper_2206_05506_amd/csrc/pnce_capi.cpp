@@ -251,14 +251,14 @@ pnce_status pnce_get_shape(const pnce_plan *plan, int *N, int *T, int *L, int *R
 }
 
 pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y, void *H,
-                          int batch, int precision, const float *scales, double beta) {
+                          int batch, int precision, double alpha, const float *scales,
+                          double beta) {
   if (pnce_status st = check_plan(plan)) return st;
   if (!Y || !H) return fail(PNCE_E_INVALID, "Y and H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
   if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
   return run_tg(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
-                plan->K, beta != 0.0 ? H : nullptr, plan->d_fwd, scales, batch,
-                1.0 / plan->N, beta);
+                plan->K, beta != 0.0 ? H : nullptr, plan->d_fwd, scales, batch, alpha, beta);
 }
 
 pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y, void *Yq,
@@ -280,8 +280,9 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream, const void
   if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
   if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
-  if (format == PNCE_FMT_E4M3) return fail(PNCE_E_UNSUPPORTED, "e4m3 correlation not built");
-  const int in_fmt = format == PNCE_FMT_BF16 ? pnce::IN_BF16 : pnce::IN_F16;
+  const int in_fmt = format == PNCE_FMT_BF16  ? pnce::IN_BF16
+                     : format == PNCE_FMT_F16 ? pnce::IN_F16
+                                              : pnce::IN_E4M3;
   const int Np = plan->N + 1;
   // The zero pad sample is part of the reduction (it contributes nothing).
   return run_tg(plan, (hipStream_t)stream, pnce::MODE_BF16, in_fmt, Yq, Np, Np, H, plan->K,

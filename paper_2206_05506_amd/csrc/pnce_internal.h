@@ -10,7 +10,7 @@ namespace pnce {
 enum Mode { MODE_F32 = 0, MODE_F32S = 1, MODE_BF16 = 2, MODE_F64 = 3 };
 
 // Input encodings of the tiled kernel.
-enum InFmt { IN_C64 = 0, IN_BF16 = 1, IN_F16 = 2 };
+enum InFmt { IN_C64 = 0, IN_BF16 = 1, IN_F16 = 2, IN_E4M3 = 3 };
 
 // One Toeplitz +-1 contraction over a batch of row blocks:
 //   out[b][r][c] = alpha_b * sum_{t < t_len} in[b][r][t] * sgn(bits[(t - c) mod N])

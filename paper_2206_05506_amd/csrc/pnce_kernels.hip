@@ -405,6 +405,198 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP8 (OCP e4m3fn) correlator on quantised planes, v_mfma_f32_32x32x64_f8f6f4.
+// Same tiling as tg_kernel; one 64-sample k-step per LDS chunk (32 rows x
+// 2 planes x 64 codes). Lane (m, h) supplies codes n0 + 32h .. +31 of row m
+// and the matching 32 sequence bits; +-1 in e4m3 is 0x38 / 0xB8. The B
+// fragment of lag block c at k-step i is the 32-bit window at bit
+// p_base + 32(2i - c), so two new windows per k-step serve all blocks.
+// ---------------------------------------------------------------------------
+typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8;
+
+// 32 bits of the periodic stream starting at bit p.
+__device__ __forceinline__ uint32_t window32(const uint32_t *sbits, int p) {
+  const uint32_t w0 = sbits[p >> 5];
+  const uint32_t w1 = sbits[(p >> 5) + 1];
+  return __builtin_amdgcn_alignbit(w1, w0, (uint32_t)(p & 31));
+}
+
+// 32 bits -> 32 e4m3 codes of +-1 (bit i -> byte i; 1 -> sign set).
+__device__ __forceinline__ i32x8 expand_e4m3(uint32_t x) {
+  i32x8 r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t n4 = (x >> (4 * j)) & 0xFu;
+    // copies of the nibble at bits 7, 14, 21, 28 put nibble bit j at 8j + 7
+    r[j] = (int)(0x38383838u | ((n4 * 0x10204080u) & 0x80808080u));
+  }
+  return r;
+}
+
+template <int NC>
+__global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles_r, int tiles_c,
+                                                             int nbw_pad) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+  constexpr int NW = 2 * NC;       // window slots (32-sample granularity)
+  constexpr int RS = 20;           // dwords per plane row: 64 codes + pad
+  constexpr int PS = kRows * RS;
+  constexpr int SDW = 2 * PS;
+  constexpr int CH = 64;           // samples per chunk = one k-step
+  constexpr int PF = 4;
+  constexpr int CPB = (NC > PF) ? NC : PF;  // chunks per unrolled body
+  static_assert(CPB % PF == 0 && CPB % NC == 0, "body must cover both rotations");
+
+  uint32_t *sbits = smem;
+  uint32_t *stage = smem + nbw_pad;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m = lane & 31;
+  const int h = lane >> 5;
+
+  const int nt = a.batch * tiles_r * tiles_c;
+  const int bid = blockIdx.x;
+  const int t = (nt % 8 == 0) ? (bid % 8) * (nt / 8) + bid / 8 : bid;
+  const int cg = t % tiles_c;
+  const int rest = t / tiles_c;
+  const int rb = rest % tiles_r;
+  const int b = rest / tiles_r;
+  const int a0 = rb * kRows;
+  const int col0 = cg * (kWaves * 32 * NC) + wave * 32 * NC;
+
+  const int nchunks = (a.t_len + CH - 1) / CH;
+  const uint8_t *fin = (const uint8_t *)a.in + (size_t)b * a.R * 2 * a.ld_in;
+  // thread t loads 16 codes: row t >> 3, plane (t >> 2) & 1, codes 16*(t & 3)
+  const int lrow = tid >> 3, lplane = (tid >> 2) & 1, lpart = tid & 3;
+  auto load_chunk = [&](u32x4 &r, int chunk) {
+    const int n = chunk * CH + 16 * lpart;
+    const int arow = a0 + lrow;
+    u32x4 x = {0u, 0u, 0u, 0u};
+    if (arow < a.R) {
+      const uint8_t *p = fin + ((size_t)arow * 2 + lplane) * a.ld_in + n;
+      if (n + 16 <= a.t_len && (a.ld_in & 15) == 0) {
+        x = *(const u32x4 *)p;
+      } else {
+        uint32_t e[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) e[j] = (n + j < a.t_len) ? p[j] : 0u;
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+          x[w] = e[4 * w] | (e[4 * w + 1] << 8) | (e[4 * w + 2] << 16) | (e[4 * w + 3] << 24);
+      }
+    }
+    r = x;
+  };
+  auto store_chunk = [&](uint32_t *st, const u32x4 &r) {
+    *(u32x4 *)(st + lplane * PS + lrow * RS + 4 * lpart) = r;
+  };
+
+  u32x4 raw[PF];
+#pragma unroll
+  for (int j = 0; j < PF; ++j)
+    if (j < nchunks) load_chunk(raw[j], j);
+  for (int i = tid; i < a.nbw; i += kThreads) sbits[i] = a.bits[i];
+  store_chunk(stage, raw[0]);
+  if (PF < nchunks) load_chunk(raw[0], PF);
+  __syncthreads();
+
+  const int p_base = pos_mod(32 * h - m - col0, a.N);
+  i32x8 win[NW];
+  // windows W(j), j = -(NC-1) .. -1, for blocks c >= 1 of the first k-steps
+#pragma unroll
+  for (int j = 1; j <= NC - 1; ++j)
+    win[NW - j] = expand_e4m3(window32(sbits, pos_mod(p_base - 32 * j, a.N)));
+
+  f32x16 acc_re[NC], acc_im[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      acc_re[c][v] = 0.f;
+      acc_im[c][v] = 0.f;
+    }
+  }
+
+  const int nbodies = (nchunks + CPB - 1) / CPB;
+  for (int body = 0; body < nbodies; ++body) {
+#pragma unroll
+    for (int cc = 0; cc < CPB; ++cc) {
+      const int i = body * CPB + cc;  // chunk = k-step
+      if (i < nchunks) {
+        const uint32_t *st = stage + (i & 1) * SDW;
+        const int q = (2 * cc) % NW;  // slot of W(2i)
+        win[q] = expand_e4m3(window32(sbits, p_base + 64 * i));
+        win[(q + 1) % NW] = expand_e4m3(window32(sbits, p_base + 64 * i + 32));
+        const u32x4 r0 = *(const u32x4 *)(st + m * RS + 8 * h);
+        const u32x4 r1 = *(const u32x4 *)(st + m * RS + 8 * h + 4);
+        const u32x4 i0 = *(const u32x4 *)(st + PS + m * RS + 8 * h);
+        const u32x4 i1 = *(const u32x4 *)(st + PS + m * RS + 8 * h + 4);
+        const i32x8 are = {(int)r0.x, (int)r0.y, (int)r0.z, (int)r0.w,
+                           (int)r1.x, (int)r1.y, (int)r1.z, (int)r1.w};
+        const i32x8 aim = {(int)i0.x, (int)i0.y, (int)i0.z, (int)i0.w,
+                           (int)i1.x, (int)i1.y, (int)i1.z, (int)i1.w};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const i32x8 bw = win[(q - c + NW) % NW];
+          acc_re[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(are, bw, acc_re[c], 0, 0,
+                                                                      0, 0, 0, 0);
+          acc_im[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(aim, bw, acc_im[c], 0, 0,
+                                                                      0, 0, 0, 0);
+        }
+        if (i + 1 < nchunks) {
+          store_chunk(stage + ((i + 1) & 1) * SDW, raw[(cc + 1) % PF]);
+          if (i + 1 + PF < nchunks) load_chunk(raw[(cc + 1) % PF], i + 1 + PF);
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  const float alpha = a.alpha * (a.scales ? a.scales[b] : 1.0f);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int col = col0 + 32 * c + m;
+    if (col < a.c_len) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int ant = a0 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (ant < a.R) {
+          const size_t o = ((size_t)(b * a.R + ant) * a.ld_out + col) * 2;
+          float re = alpha * acc_re[c][v];
+          float im = alpha * acc_im[c][v];
+          if (a.beta != 0.0f) {
+            const f2a8 old = *(const f2a8 *)(a.cin + o);
+            re += a.beta * old.x;
+            im += a.beta * old.y;
+          }
+          *(f2a8 *)(a.out + o) = f2a8{re, im};
+        }
+      }
+    }
+  }
+}
+
+template <int NC>
+static hipError_t launch_fp8_nc(const TgArgs &a, hipStream_t s) {
+  const int tiles_r = (a.R + kRows - 1) / kRows;
+  const int cols_per_tile = kWaves * 32 * NC;
+  const int tiles_c = (a.c_len + cols_per_tile - 1) / cols_per_tile;
+  const long nt = (long)a.batch * tiles_r * tiles_c;
+  if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
+  const int nbw_pad = (a.nbw + 3) & ~3;
+  const size_t lds = (size_t)(nbw_pad + 2 * 2 * kRows * 20) * 4;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)tg_fp8_kernel<NC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((tg_fp8_kernel<NC>), dim3((unsigned)nt), dim3(kThreads), lds, s, a,
+                     tiles_r, tiles_c, nbw_pad);
+  return hipGetLastError();
+}
+
 template <int MODE, int IN, int NC>
 static hipError_t launch_tg_nc(const TgArgs &a, hipStream_t s) {
   const int tiles_r = (a.R + kRows - 1) / kRows;
@@ -442,6 +634,11 @@ hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s) {
   }
   if (in_fmt == IN_BF16) return launch_tg_mode<MODE_BF16, IN_BF16>(a, s);
   if (in_fmt == IN_F16) return launch_tg_mode<MODE_BF16, IN_F16>(a, s);
+  if (in_fmt == IN_E4M3) {
+    if (a.c_len > 256) return launch_fp8_nc<4>(a, s);
+    if (a.c_len > 128) return launch_fp8_nc<2>(a, s);
+    return launch_fp8_nc<1>(a, s);
+  }
   return hipErrorInvalidValue;
 }
 

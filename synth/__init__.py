@@ -120,3 +120,24 @@ def varlen_shapes(nframes: int = 4096, seed: int = 3):
                 break
         out[f] = (R, d, T, L)
     return out
+
+
+def device_draws(cfg: Config, torch, device="cuda", frames=None, seed_offset=1000):
+    """Seeded draws made on the GPU with torch's generator, for workloads too
+    large to draw on the host (the precision study holds 537M samples).
+    Same distributions as ``frame_draws``; a different stream (seed
+    cfg.seed + seed_offset). Returns dict(snr_db [F], h [F,R,T,L], w [F,R,N])
+    as float32 / complex64 device tensors."""
+    F = cfg.B if frames is None else frames
+    g = torch.Generator(device=device)
+    g.manual_seed(cfg.seed + seed_offset)
+    snr = cfg.snr_lo + (cfg.snr_hi - cfg.snr_lo) * torch.rand(F, generator=g, device=device)
+    pdp = torch.exp(-torch.arange(cfg.L, device=device, dtype=torch.float32) / cfg.tau)
+    h = torch.complex(torch.randn((F, cfg.R, cfg.T, cfg.L), generator=g, device=device),
+                      torch.randn((F, cfg.R, cfg.T, cfg.L), generator=g, device=device))
+    h = h * torch.sqrt(pdp / 2.0)
+    h = h / torch.sqrt((h.abs() ** 2).sum(dim=-1, keepdim=True))
+    w = torch.complex(torch.randn((F, cfg.R, cfg.N), generator=g, device=device),
+                      torch.randn((F, cfg.R, cfg.N), generator=g, device=device))
+    w = w / (2.0 ** 0.5)
+    return {"snr_db": snr, "h": h, "w": w}

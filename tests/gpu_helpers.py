@@ -31,3 +31,33 @@ def bf16_round(y):
     re = oracle.decode(oracle._bf16_bits(y.real.astype(np.float32)), "bf16")
     im = oracle.decode(oracle._bf16_bits(y.imag.astype(np.float32)), "bf16")
     return re + 1j * im
+
+
+def device_frames(cfg, s):
+    """Large seeded workloads built on the GPU without the library: seeded
+    torch draws, then y = P h + sigma w by torch's FFT circular convolution
+    with the oracle's sequence s (the receive model of Eq. 9).
+    Returns (y complex64 [B,R,N], h complex64 [B,R,T,L]) on the device."""
+    d = synth.device_draws(cfg, torch)
+    h = d["h"]
+    B, R, T, L = h.shape
+    K = T * L
+    N = cfg.N
+    hs = torch.zeros((B, R, N), dtype=torch.complex64, device="cuda")
+    idx = torch.arange(K, device="cuda") % N
+    hs.index_add_(2, idx, h.reshape(B, R, K))
+    S = torch.fft.fft(torch.from_numpy(s.astype(np.float32)).cuda().to(torch.complex64))
+    y = torch.empty((B, R, N), dtype=torch.complex64, device="cuda")
+    for b0 in range(0, B, 64):
+        b1 = min(B, b0 + 64)
+        yc = torch.fft.ifft(torch.fft.fft(hs[b0:b1], dim=-1) * S, dim=-1)
+        p = (yc.abs() ** 2).mean(dim=(1, 2))
+        sigma = torch.sqrt(p / 10.0 ** (d["snr_db"][b0:b1] / 10.0))
+        y[b0:b1] = yc + sigma[:, None, None] * d["w"][b0:b1]
+    del hs, d
+    return y.contiguous(), h
+
+
+def rows_of(x, rows):
+    """Gather (frame, antenna) rows of a [B, R, ...] array into [1, n, ...]."""
+    return np.stack([x[b, r] for b, r in rows])[None]

@@ -83,8 +83,9 @@ def test_create_null_output_pointer(lib):
 
 def test_null_plan_is_rejected_everywhere(lib):
     P = ctypes.c_void_p
-    lib.pnce_estimate.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_double]
-    assert lib.pnce_estimate(None, None, None, None, 1, 0, None, 0.0) == -1
+    lib.pnce_estimate.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, P,
+                                  ctypes.c_double]
+    assert lib.pnce_estimate(None, None, None, None, 1, 0, 1.0, None, 0.0) == -1
     lib.pnce_adjoint.argtypes = [P, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_double]
     assert lib.pnce_adjoint(None, None, None, None, None, 1, 0, 1.0, 0.0) == -1

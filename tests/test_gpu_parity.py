@@ -154,7 +154,7 @@ def test_pack_bit_exact(shape, fmt):
     assert np.array_equal(q.view(ref_q.dtype), ref_q)
 
 
-@pytest.mark.parametrize("fmt", ["bf16", "f16"])
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "e4m3"])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
 def test_estimate_packed_parity(shape, fmt):
     N, T, L, R, B = shape
@@ -164,7 +164,7 @@ def test_estimate_packed_parity(shape, fmt):
         H = host(p.estimate_packed(q, sc, fmt))
         s = p.sequence()
         qh, sch = host(q), host(sc)
-    x = oracle.dequantize(qh.view(np.uint16), sch, fmt, N)
+    x = oracle.dequantize(qh.view(np.uint8 if fmt == "e4m3" else np.uint16), sch, fmt, N)
     ref = oracle.correlate(x, s, T * L)
     assert oracle.relerr(H, ref) <= TOL32
 
