@@ -163,6 +163,80 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
 pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y,
                         void *X, void *work, int batch, int steps);
 
+/* ---------------------------------------------------------------------------
+ * Uneven batches (the batching form): frames of different (R, N, T, L) drawn
+ * from the ranges of Table I, estimated in ONE persistent launch whose work
+ * list is built on the host, with tile widths chosen by an autotuner.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int R, N, T, L;     /* frame shape; N = 2^d - 1 with 2 <= d <= 16          */
+  long long y_off;    /* first code of the frame in Yq, in codes; a multiple  */
+                      /* of 8. The frame holds [R][2][N+1] codes (the layout  */
+                      /* of pnce_pack for one frame)                          */
+  long long h_off;    /* first complex64 element of the frame's CIRs in H,    */
+                      /* which hold [R][T*L] values                           */
+} pnce_frame_desc;
+
+typedef struct pnce_varlen_plan pnce_varlen_plan;   /* opaque */
+
+/*
+ * Build a plan for `nframes` frames described by the host array `frames`
+ * (copied). format: PNCE_FMT_BF16 or PNCE_FMT_F16. Builds one m-sequence per
+ * distinct N, the frame table and a work list: units of (frame, 32-antenna
+ * block) carrying all their column tiles, dealt to persistent workgroups
+ * longest-first. Column width per (N, T*L) class defaults to 128, 64 or 32
+ * lags per wave by T*L; pnce_varlen_tune replaces it with measured choices.
+ * Synchronous (uploads the tables). Errors: PNCE_E_INVALID for a bad frame,
+ * offset or format, PNCE_E_UNSUPPORTED for a bad N. Warning
+ * PNCE_W_LAG_ALIAS if some frame has T*L > N.
+ */
+pnce_status pnce_varlen_create(pnce_varlen_plan **vplan, const pnce_frame_desc *frames,
+                               int nframes, int format);
+
+/* Free a varlen plan. NULL is a no-op. */
+pnce_status pnce_varlen_destroy(pnce_varlen_plan *vplan);
+
+/*
+ * The correlator of Eq. 3 / Eq. 10 for every frame, one persistent launch:
+ *   H_f = (scales[f] / N_f) * (Yq_f P_f), scales may be NULL (all 1).
+ * Yq: device codes of all frames (at their y_off); H: device complex64 (at
+ * their h_off); the caller keeps the frames' regions disjoint. The launch
+ * reads only plan-owned static tables, so it can be captured in a hipGraph.
+ */
+pnce_status pnce_varlen_estimate(const pnce_varlen_plan *vplan, void *stream, const void *Yq,
+                                 const float *scales, void *H);
+
+/* The same result through one launch per frame (the reference schedule);
+ * each frame uses the column width of the plan, so results are identical. */
+pnce_status pnce_varlen_estimate_each(const pnce_varlen_plan *vplan, void *stream,
+                                      const void *Yq, const float *scales, void *H);
+
+/*
+ * Autotuner: for each (N, T*L) class, times the column widths 32, 64 and 128
+ * lags per wave on up to 16 frames of that class (`reps` timed launches
+ * each, HIP events on `stream`), keeps the fastest, uses its measured time
+ * per (frame, 32-antenna) unit as the scheduling cost and rebuilds the work
+ * list. Synchronous. Writes H of the sampled frames.
+ */
+pnce_status pnce_varlen_tune(pnce_varlen_plan *vplan, void *stream, const void *Yq,
+                             const float *scales, void *H, int reps);
+
+/*
+ * Read (n_classes only when the arrays are NULL) or install the per-class
+ * choice: sequence length N, T*L, lags per wave / 32 (1, 2 or 4) and cost in
+ * microseconds per unit. set_tuning rebuilds the work list; classes not
+ * listed keep their choice. Lets a caller cache tuning results.
+ */
+pnce_status pnce_varlen_get_tuning(const pnce_varlen_plan *vplan, int *n_classes, int *N,
+                                   int *K, int *nc, float *us_per_unit);
+pnce_status pnce_varlen_set_tuning(pnce_varlen_plan *vplan, int n_classes, const int *N,
+                                   const int *K, const int *nc, const float *us_per_unit);
+
+/* Work-list statistics: persistent workgroups, tiles, and the largest and
+ * mean per-workgroup cost (microseconds, by the plan's cost model). */
+pnce_status pnce_varlen_stats(const pnce_varlen_plan *vplan, int *n_workgroups, int *n_tiles,
+                              float *max_cost, float *mean_cost);
+
 /* Text of a status code (static storage). */
 const char *pnce_status_string(pnce_status status);
 

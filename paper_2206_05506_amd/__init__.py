@@ -11,6 +11,6 @@ marshals arguments. It raises ImportError when the library is not built.
 """
 from . import _lib
 from ._lib import PnceError
-from .api import FORMATS, PRECISIONS, Plan
+from .api import FORMATS, PRECISIONS, Plan, VarlenPlan
 
-__all__ = ["Plan", "PnceError", "PRECISIONS", "FORMATS", "_lib"]
+__all__ = ["Plan", "VarlenPlan", "PnceError", "PRECISIONS", "FORMATS", "_lib"]

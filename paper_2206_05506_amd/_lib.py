@@ -30,7 +30,15 @@ PNCE_FMT_E4M3 = 3
 
 SYMBOLS = ("pnce_create", "pnce_destroy", "pnce_get_sequence", "pnce_get_shape",
            "pnce_estimate", "pnce_pack", "pnce_estimate_packed", "pnce_adjoint",
-           "pnce_refine", "pnce_status_string", "pnce_last_error")
+           "pnce_refine", "pnce_varlen_create", "pnce_varlen_destroy", "pnce_varlen_estimate",
+           "pnce_varlen_estimate_each", "pnce_varlen_tune", "pnce_varlen_get_tuning",
+           "pnce_varlen_set_tuning", "pnce_varlen_stats", "pnce_status_string",
+           "pnce_last_error")
+
+
+class pnce_frame_desc(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int), ("N", ctypes.c_int), ("T", ctypes.c_int),
+                ("L", ctypes.c_int), ("y_off", ctypes.c_longlong), ("h_off", ctypes.c_longlong)]
 
 
 class PnceError(RuntimeError):
@@ -59,6 +67,15 @@ def _load() -> ctypes.CDLL:
         "pnce_estimate_packed": ([_P, _P, _P, _P, _P, _I, _I, _D], _I),
         "pnce_adjoint": ([_P, _P, _P, _P, _P, _I, _I, _D, _D], _I),
         "pnce_refine": ([_P, _P, _P, _P, _P, _I, _I], _I),
+        "pnce_varlen_create": ([ctypes.POINTER(_P), ctypes.POINTER(pnce_frame_desc), _I, _I],
+                               _I),
+        "pnce_varlen_destroy": ([_P], _I),
+        "pnce_varlen_estimate": ([_P, _P, _P, _P, _P], _I),
+        "pnce_varlen_estimate_each": ([_P, _P, _P, _P, _P], _I),
+        "pnce_varlen_tune": ([_P, _P, _P, _P, _P, _I], _I),
+        "pnce_varlen_get_tuning": ([_P, _P, _P, _P, _P, _P], _I),
+        "pnce_varlen_set_tuning": ([_P, _I, _P, _P, _P, _P], _I),
+        "pnce_varlen_stats": ([_P, _P, _P, _P, _P], _I),
         "pnce_status_string": ([_I], ctypes.c_char_p),
         "pnce_last_error": ([], ctypes.c_char_p),
     }
@@ -122,6 +139,64 @@ def pnce_adjoint(plan, stream, G, A, C, batch, precision, alpha, beta) -> int:
 
 def pnce_refine(plan, stream, y, X, work, batch, steps) -> int:
     return check(lib.pnce_refine(plan, stream, y, X, work, batch, steps), "pnce_refine")
+
+
+def pnce_varlen_create(frames, fmt: int):
+    """frames: sequence of (R, N, T, L, y_off, h_off). Returns (handle, status)."""
+    arr = (pnce_frame_desc * len(frames))(*[pnce_frame_desc(*f) for f in frames])
+    h = _P()
+    st = check(lib.pnce_varlen_create(ctypes.byref(h), arr, len(frames), fmt),
+               "pnce_varlen_create")
+    return h, st
+
+
+def pnce_varlen_destroy(vplan) -> int:
+    return check(lib.pnce_varlen_destroy(vplan), "pnce_varlen_destroy")
+
+
+def pnce_varlen_estimate(vplan, stream, Yq, scales, H) -> int:
+    return check(lib.pnce_varlen_estimate(vplan, stream, Yq, scales, H), "pnce_varlen_estimate")
+
+
+def pnce_varlen_estimate_each(vplan, stream, Yq, scales, H) -> int:
+    return check(lib.pnce_varlen_estimate_each(vplan, stream, Yq, scales, H),
+                 "pnce_varlen_estimate_each")
+
+
+def pnce_varlen_tune(vplan, stream, Yq, scales, H, reps: int) -> int:
+    return check(lib.pnce_varlen_tune(vplan, stream, Yq, scales, H, reps), "pnce_varlen_tune")
+
+
+def pnce_varlen_get_tuning(vplan):
+    """Returns a list of (N, K, nc, us_per_unit) per class."""
+    n = _I()
+    check(lib.pnce_varlen_get_tuning(vplan, ctypes.byref(n), None, None, None, None),
+          "pnce_varlen_get_tuning")
+    N = (_I * n.value)()
+    K = (_I * n.value)()
+    nc = (_I * n.value)()
+    us = (ctypes.c_float * n.value)()
+    check(lib.pnce_varlen_get_tuning(vplan, ctypes.byref(n), N, K, nc, us),
+          "pnce_varlen_get_tuning")
+    return [(N[i], K[i], nc[i], us[i]) for i in range(n.value)]
+
+
+def pnce_varlen_set_tuning(vplan, entries) -> int:
+    n = len(entries)
+    N = (_I * n)(*[e[0] for e in entries])
+    K = (_I * n)(*[e[1] for e in entries])
+    nc = (_I * n)(*[e[2] for e in entries])
+    us = (ctypes.c_float * n)(*[e[3] for e in entries])
+    return check(lib.pnce_varlen_set_tuning(vplan, n, N, K, nc, us), "pnce_varlen_set_tuning")
+
+
+def pnce_varlen_stats(vplan):
+    nw, nt = _I(), _I()
+    mx, mean = ctypes.c_float(), ctypes.c_float()
+    check(lib.pnce_varlen_stats(vplan, ctypes.byref(nw), ctypes.byref(nt), ctypes.byref(mx),
+                                ctypes.byref(mean)), "pnce_varlen_stats")
+    return {"workgroups": nw.value, "tiles": nt.value, "max_cost_us": mx.value,
+            "mean_cost_us": mean.value}
 
 
 def pnce_status_string(status: int) -> str:

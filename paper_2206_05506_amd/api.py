@@ -150,3 +150,84 @@ class Plan:
             work = torch.empty((B, self.R, self.N), dtype=torch.complex64, device=y.device)
         _lib.pnce_refine(self.handle, _stream(), _ptr(y), _ptr(X), _ptr(work), B, steps)
         return X
+
+
+class VarlenPlan:
+    """Uneven batch: frames with their own (R, N, T, L) in one buffer of
+    planar codes ([R][2][N+1] per frame) and one buffer of complex64 CIRs
+    ([R][T*L] per frame), estimated by one persistent launch."""
+
+    def __init__(self, shapes, fmt: str = "bf16"):
+        """shapes: iterable of (R, N, T, L). Offsets are laid out back to back."""
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.fmt = fmt
+        y_off, h_off = [], []
+        yo = ho = 0
+        for R, N, T, L in self.shapes:
+            y_off.append(yo)
+            h_off.append(ho)
+            yo += R * 2 * (N + 1)
+            ho += R * T * L
+        self.y_off, self.h_off = y_off, h_off
+        self.n_codes, self.n_out = yo, ho
+        frames = [(R, N, T, L, y_off[i], h_off[i]) for i, (R, N, T, L) in enumerate(self.shapes)]
+        self.handle, self.status = _lib.pnce_varlen_create(frames, FORMATS[fmt])
+
+    def close(self):
+        if self.handle:
+            _lib.pnce_varlen_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, Yq, scales, H):
+        _need(Yq, (self.n_codes,), torch.int16, "Yq")
+        _need(H, (self.n_out,), torch.complex64, "H")
+        if scales is not None:
+            _need(scales, (len(self.shapes),), torch.float32, "scales")
+
+    def estimate(self, Yq, scales=None, out=None):
+        if out is None:
+            out = torch.empty((self.n_out,), dtype=torch.complex64, device=Yq.device)
+        self._check(Yq, scales, out)
+        _lib.pnce_varlen_estimate(self.handle, _stream(), _ptr(Yq), _ptr(scales), _ptr(out))
+        return out
+
+    def estimate_each(self, Yq, scales=None, out=None):
+        if out is None:
+            out = torch.empty((self.n_out,), dtype=torch.complex64, device=Yq.device)
+        self._check(Yq, scales, out)
+        _lib.pnce_varlen_estimate_each(self.handle, _stream(), _ptr(Yq), _ptr(scales),
+                                       _ptr(out))
+        return out
+
+    def tune(self, Yq, scales=None, out=None, reps: int = 5):
+        if out is None:
+            out = torch.empty((self.n_out,), dtype=torch.complex64, device=Yq.device)
+        self._check(Yq, scales, out)
+        _lib.pnce_varlen_tune(self.handle, _stream(), _ptr(Yq), _ptr(scales), _ptr(out), reps)
+        return self.tuning()
+
+    def tuning(self):
+        return _lib.pnce_varlen_get_tuning(self.handle)
+
+    def set_tuning(self, entries):
+        _lib.pnce_varlen_set_tuning(self.handle, entries)
+
+    def stats(self):
+        return _lib.pnce_varlen_stats(self.handle)
+
+    def frame_view(self, H, f):
+        """CIRs of frame f as [R, T, L] (the de-multiplexed view of Eq. 10)."""
+        R, N, T, L = self.shapes[f]
+        return H[self.h_off[f]:self.h_off[f] + R * T * L].view(R, T, L)

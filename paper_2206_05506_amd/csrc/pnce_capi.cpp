@@ -3,11 +3,16 @@
 // in include/pnce.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <new>
+#include <queue>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/pnce.h"
@@ -339,6 +344,420 @@ pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void
                                 X, plan->K, X, plan->d_fwd, nullptr, batch, 1.0 / plan->N, 1.0))
       return st;
   }
+  return PNCE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Uneven batches.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct pnce_varlen_plan {
+  int in_fmt;
+  int n_cu;
+  std::vector<pnce_frame_desc> desc;
+  std::vector<pnce::VFrame> frames;
+  // per (N, K) class: chosen lags-per-wave / 32 and cost per unit (us)
+  std::map<std::pair<int, int>, std::pair<int, float>> cls;
+  std::vector<pnce::VTile> tiles;
+  std::vector<int> wg_start;
+  std::vector<float> wg_cost;
+  uint32_t *d_bits = nullptr;
+  int nbw_max = 0;
+  pnce::VFrame *d_frames = nullptr;
+  pnce::VTile *d_tiles = nullptr;
+  int *d_wg_start = nullptr;
+  size_t cap_tiles = 0, cap_wg = 0;
+};
+
+namespace {
+
+int default_nc(int K) { return K > 256 ? 4 : (K > 128 ? 2 : 1); }
+
+// Default cost of one (frame, 32-antenna) unit: streaming its rows (~N) plus
+// matrix-core work over the padded lag width.
+float default_cost(int N, int K, int nc) {
+  const int w = 128 * nc;
+  const int groups = (K + w - 1) / w;
+  return (float)N * (1.0f + (float)(groups * w) / 256.0f) * 1e-3f;
+}
+
+struct Unit {
+  int frame, a0;
+  float cost;
+};
+
+// Units of the listed frames with their class choices (or a forced width).
+std::vector<Unit> make_units(const pnce_varlen_plan *v, const std::vector<int> &frames,
+                             int force_nc) {
+  std::vector<Unit> u;
+  for (int f : frames) {
+    const pnce::VFrame &fr = v->frames[(size_t)f];
+    const auto &c = v->cls.at({fr.N, fr.K});
+    const float cost = force_nc ? 1.0f : c.second;
+    for (int a0 = 0; a0 < fr.R; a0 += 32) u.push_back({f, a0, cost});
+  }
+  return u;
+}
+
+// Longest-processing-time-first assignment of units to `n_wg` workgroups;
+// fills tiles / wg_start / wg_cost.
+void schedule(const pnce_varlen_plan *v, std::vector<Unit> units, int n_wg, int force_nc,
+              std::vector<pnce::VTile> &tiles, std::vector<int> &wg_start,
+              std::vector<float> &wg_cost) {
+  std::stable_sort(units.begin(), units.end(),
+                   [](const Unit &x, const Unit &y) { return x.cost > y.cost; });
+  typedef std::pair<float, int> Load;
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int w = 0; w < n_wg; ++w) heap.push({0.0f, w});
+  std::vector<std::vector<int>> per(n_wg);
+  wg_cost.assign((size_t)n_wg, 0.0f);
+  for (size_t i = 0; i < units.size(); ++i) {
+    Load l = heap.top();
+    heap.pop();
+    per[(size_t)l.second].push_back((int)i);
+    l.first += units[i].cost;
+    wg_cost[(size_t)l.second] = l.first;
+    heap.push(l);
+  }
+  tiles.clear();
+  wg_start.assign((size_t)n_wg + 1, 0);
+  for (int w = 0; w < n_wg; ++w) {
+    wg_start[(size_t)w] = (int)tiles.size();
+    for (int i : per[(size_t)w]) {
+      const Unit &un = units[(size_t)i];
+      const pnce::VFrame &fr = v->frames[(size_t)un.frame];
+      const int nc = force_nc ? force_nc : v->cls.at({fr.N, fr.K}).first;
+      const int width = 128 * nc;
+      for (int colg = 0; colg < fr.K; colg += width) tiles.push_back({un.frame, un.a0, colg, nc});
+    }
+  }
+  wg_start[(size_t)n_wg] = (int)tiles.size();
+}
+
+pnce_status upload_list(pnce_varlen_plan *v, const std::vector<pnce::VTile> &tiles,
+                        const std::vector<int> &wg_start) {
+  hipError_t e;
+  if (tiles.size() > v->cap_tiles) {
+    (void)hipFree(v->d_tiles);
+    v->d_tiles = nullptr;
+    e = hipMalloc((void **)&v->d_tiles, tiles.size() * sizeof(pnce::VTile));
+    if (e != hipSuccess) return fail(PNCE_E_NOMEM, "hipMalloc work list");
+    v->cap_tiles = tiles.size();
+  }
+  if (wg_start.size() > v->cap_wg) {
+    (void)hipFree(v->d_wg_start);
+    v->d_wg_start = nullptr;
+    e = hipMalloc((void **)&v->d_wg_start, wg_start.size() * sizeof(int));
+    if (e != hipSuccess) return fail(PNCE_E_NOMEM, "hipMalloc work list");
+    v->cap_wg = wg_start.size();
+  }
+  e = hipMemcpy(v->d_tiles, tiles.data(), tiles.size() * sizeof(pnce::VTile),
+                hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(v->d_wg_start, wg_start.data(), wg_start.size() * sizeof(int),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy work list");
+  return PNCE_OK;
+}
+
+pnce_status rebuild(pnce_varlen_plan *v) {
+  std::vector<int> all(v->frames.size());
+  for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
+  std::vector<Unit> units = make_units(v, all, 0);
+  const int n_wg = (int)std::min<size_t>(units.size(), (size_t)v->n_cu * 2);
+  schedule(v, units, n_wg, 0, v->tiles, v->wg_start, v->wg_cost);
+  return upload_list(v, v->tiles, v->wg_start);
+}
+
+pnce::VArgs varlen_args(const pnce_varlen_plan *v, const void *Yq, const float *scales, void *H,
+                        const pnce::VTile *tiles, const int *wg_start) {
+  pnce::VArgs a{};
+  a.in = Yq;
+  a.out = (float *)H;
+  a.scales = scales;
+  a.frames = v->d_frames;
+  a.tiles = tiles;
+  a.wg_start = wg_start;
+  a.bits = v->d_bits;
+  a.nbw_max = v->nbw_max;
+  return a;
+}
+
+void free_varlen(pnce_varlen_plan *v) {
+  (void)hipFree(v->d_bits);
+  (void)hipFree(v->d_frames);
+  (void)hipFree(v->d_tiles);
+  (void)hipFree(v->d_wg_start);
+  delete v;
+}
+
+}  // namespace
+
+extern "C" {
+
+pnce_status pnce_varlen_create(pnce_varlen_plan **vplan, const pnce_frame_desc *frames,
+                               int nframes, int format) {
+  try {
+    if (!vplan) return fail(PNCE_E_INVALID, "vplan output pointer is NULL");
+    *vplan = nullptr;
+    if (!frames || nframes <= 0) return fail(PNCE_E_INVALID, "frames must be a non-empty array");
+    if (format != PNCE_FMT_BF16 && format != PNCE_FMT_F16)
+      return fail(PNCE_E_INVALID, "varlen format must be PNCE_FMT_BF16 or PNCE_FMT_F16");
+    bool alias = false;
+    std::map<int, int> kmax;  // N -> largest T*L
+    for (int f = 0; f < nframes; ++f) {
+      const pnce_frame_desc &d = frames[f];
+      int deg = 0;
+      while (deg <= 16 && (1 << deg) - 1 < d.N) ++deg;
+      if (d.N <= 0 || deg < 2 || deg > 16 || (1 << deg) - 1 != d.N)
+        return fail(PNCE_E_UNSUPPORTED, "frame " + std::to_string(f) + ": N must be 2^d - 1");
+      if (d.R <= 0 || d.T <= 0 || d.L <= 0 || d.R > 65535 || (long)d.T * d.L > 16L * d.N)
+        return fail(PNCE_E_INVALID, "frame " + std::to_string(f) + ": bad R, T or L");
+      if (d.y_off < 0 || d.h_off < 0 || (d.y_off & 7))
+        return fail(PNCE_E_INVALID,
+                    "frame " + std::to_string(f) + ": offsets must be >= 0, y_off a multiple of 8");
+      alias |= d.T * d.L > d.N;
+      kmax[d.N] = std::max(kmax[d.N], d.T * d.L);
+    }
+    pnce_varlen_plan *v = new (std::nothrow) pnce_varlen_plan();
+    if (!v) return fail(PNCE_E_NOMEM, "host allocation failed");
+    v->in_fmt = format == PNCE_FMT_BF16 ? pnce::IN_BF16 : pnce::IN_F16;
+    v->desc.assign(frames, frames + nframes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&v->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+      delete v;
+      return hip_fail(e, "device query");
+    }
+    // one forward bit stream per distinct N
+    std::vector<uint32_t> bits;
+    std::map<int, std::pair<int, int>> boff;  // N -> (offset, words)
+    for (const auto &kv : kmax) {
+      int deg = 0;
+      while ((1 << deg) - 1 < kv.first) ++deg;
+      const std::vector<signed char> s = make_sequence(deg);
+      const int nbw = (int)(((long)kv.first + std::max(kv.first, kv.second) + 160 + 31) / 32);
+      const std::vector<uint32_t> w = bit_stream(s, nbw, +1);
+      boff[kv.first] = {(int)bits.size(), nbw};
+      bits.insert(bits.end(), w.begin(), w.end());
+      v->nbw_max = std::max(v->nbw_max, nbw);
+    }
+    v->frames.resize((size_t)nframes);
+    for (int f = 0; f < nframes; ++f) {
+      const pnce_frame_desc &d = frames[f];
+      pnce::VFrame &fr = v->frames[(size_t)f];
+      fr.y_off = d.y_off;
+      fr.h_off = d.h_off;
+      fr.R = d.R;
+      fr.N = d.N;
+      fr.K = d.T * d.L;
+      fr.bits_off = boff[d.N].first;
+      fr.nbw = boff[d.N].second;
+      auto key = std::make_pair(fr.N, fr.K);
+      if (!v->cls.count(key)) {
+        const int nc = default_nc(fr.K);
+        v->cls[key] = {nc, default_cost(fr.N, fr.K, nc)};
+      }
+    }
+    e = hipMalloc((void **)&v->d_bits, bits.size() * 4);
+    if (e == hipSuccess)
+      e = hipMalloc((void **)&v->d_frames, v->frames.size() * sizeof(pnce::VFrame));
+    if (e != hipSuccess) {
+      free_varlen(v);
+      return fail(PNCE_E_NOMEM, "hipMalloc varlen tables");
+    }
+    e = hipMemcpy(v->d_bits, bits.data(), bits.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(v->d_frames, v->frames.data(), v->frames.size() * sizeof(pnce::VFrame),
+                    hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_varlen(v);
+      return hip_fail(e, "hipMemcpy varlen tables");
+    }
+    if (pnce_status st = rebuild(v)) {
+      free_varlen(v);
+      return st;
+    }
+    *vplan = v;
+    if (alias) {
+      g_last_error = "some frame has T*L > N: lags alias mod N";
+      return PNCE_W_LAG_ALIAS;
+    }
+    return PNCE_OK;
+  } catch (...) {
+    return fail(PNCE_E_NOMEM, "exception during varlen plan creation");
+  }
+}
+
+pnce_status pnce_varlen_destroy(pnce_varlen_plan *vplan) {
+  if (vplan) free_varlen(vplan);
+  return PNCE_OK;
+}
+
+pnce_status pnce_varlen_estimate(const pnce_varlen_plan *vplan, void *stream, const void *Yq,
+                                 const float *scales, void *H) {
+  if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
+  if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
+  const pnce::VArgs a = varlen_args(vplan, Yq, scales, H, vplan->d_tiles, vplan->d_wg_start);
+  hipError_t e = pnce::launch_varlen(vplan->in_fmt, a, (int)vplan->wg_start.size() - 1,
+                                     (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "varlen launch");
+  return PNCE_OK;
+}
+
+pnce_status pnce_varlen_estimate_each(const pnce_varlen_plan *vplan, void *stream,
+                                      const void *Yq, const float *scales, void *H) {
+  if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
+  if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
+  for (size_t f = 0; f < vplan->frames.size(); ++f) {
+    const pnce::VFrame &fr = vplan->frames[f];
+    pnce::TgArgs a{};
+    a.in = (const uint16_t *)Yq + fr.y_off;
+    a.out = (float *)H + fr.h_off * 2;
+    a.cin = nullptr;
+    a.bits = vplan->d_bits + fr.bits_off;
+    a.scales = scales ? scales + f : nullptr;
+    a.R = fr.R;
+    a.batch = 1;
+    a.t_len = fr.N + 1;
+    a.ld_in = fr.N + 1;
+    a.c_len = fr.K;
+    a.ld_out = fr.K;
+    a.N = fr.N;
+    a.nbw = fr.nbw;
+    a.alpha = 1.0f / (float)fr.N;
+    a.beta = 0.0f;
+    const int nc = vplan->cls.at({fr.N, fr.K}).first;
+    hipError_t e = pnce::launch_tg_frame(vplan->in_fmt, nc, a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "per-frame launch");
+  }
+  return PNCE_OK;
+}
+
+pnce_status pnce_varlen_tune(pnce_varlen_plan *vplan, void *stream, const void *Yq,
+                             const float *scales, void *H, int reps) {
+  if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
+  if (!Yq || !H || reps <= 0) return fail(PNCE_E_INVALID, "Yq, H and reps > 0 required");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  pnce::VTile *d_t = nullptr;
+  int *d_w = nullptr;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(d_t);
+    (void)hipFree(d_w);
+  };
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "hipEventCreate");
+  }
+  for (auto &kv : vplan->cls) {
+    std::vector<int> sample;
+    for (size_t f = 0; f < vplan->frames.size() && sample.size() < 16; ++f)
+      if (vplan->frames[f].N == kv.first.first && vplan->frames[f].K == kv.first.second)
+        sample.push_back((int)f);
+    float best = 0.0f;
+    int best_nc = kv.second.first;
+    for (int nc : {1, 2, 4}) {
+      std::vector<Unit> units = make_units(vplan, sample, nc);
+      const int n_wg = (int)std::min<size_t>(units.size(), (size_t)vplan->n_cu * 2);
+      std::vector<pnce::VTile> tiles;
+      std::vector<int> wg_start;
+      std::vector<float> wg_cost;
+      schedule(vplan, units, n_wg, nc, tiles, wg_start, wg_cost);
+      (void)hipFree(d_t);
+      (void)hipFree(d_w);
+      d_t = nullptr;
+      d_w = nullptr;
+      e = hipMalloc((void **)&d_t, tiles.size() * sizeof(pnce::VTile));
+      if (e == hipSuccess) e = hipMalloc((void **)&d_w, wg_start.size() * sizeof(int));
+      if (e == hipSuccess)
+        e = hipMemcpy(d_t, tiles.data(), tiles.size() * sizeof(pnce::VTile),
+                      hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(d_w, wg_start.data(), wg_start.size() * sizeof(int),
+                      hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "tuning buffers");
+      }
+      const pnce::VArgs a = varlen_args(vplan, Yq, scales, H, d_t, d_w);
+      e = pnce::launch_varlen(vplan->in_fmt, a, n_wg, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = pnce::launch_varlen(vplan->in_fmt, a, n_wg, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "tuning launch");
+      }
+      const float us = ms * 1000.0f / reps;
+      const size_t nu = units.size();
+      const float per_unit = us * (float)std::min<size_t>(nu, (size_t)n_wg) / (float)nu;
+      if (best == 0.0f || per_unit < best) {
+        best = per_unit;
+        best_nc = nc;
+      }
+    }
+    kv.second = {best_nc, best};
+  }
+  cleanup();
+  return rebuild(vplan);
+}
+
+pnce_status pnce_varlen_get_tuning(const pnce_varlen_plan *vplan, int *n_classes, int *N,
+                                   int *K, int *nc, float *us_per_unit) {
+  if (!vplan || !n_classes) return fail(PNCE_E_INVALID, "vplan and n_classes required");
+  *n_classes = (int)vplan->cls.size();
+  if (!N && !K && !nc && !us_per_unit) return PNCE_OK;
+  if (!N || !K || !nc || !us_per_unit) return fail(PNCE_E_INVALID, "all arrays or none");
+  int i = 0;
+  for (const auto &kv : vplan->cls) {
+    N[i] = kv.first.first;
+    K[i] = kv.first.second;
+    nc[i] = kv.second.first;
+    us_per_unit[i] = kv.second.second;
+    ++i;
+  }
+  return PNCE_OK;
+}
+
+pnce_status pnce_varlen_set_tuning(pnce_varlen_plan *vplan, int n_classes, const int *N,
+                                   const int *K, const int *nc, const float *us_per_unit) {
+  if (!vplan || n_classes < 0 || (n_classes > 0 && (!N || !K || !nc || !us_per_unit)))
+    return fail(PNCE_E_INVALID, "bad tuning arrays");
+  for (int i = 0; i < n_classes; ++i) {
+    if (nc[i] != 1 && nc[i] != 2 && nc[i] != 4) return fail(PNCE_E_INVALID, "nc must be 1, 2 or 4");
+    if (!(us_per_unit[i] > 0.0f)) return fail(PNCE_E_INVALID, "cost must be positive");
+  }
+  for (int i = 0; i < n_classes; ++i) {
+    auto it = vplan->cls.find({N[i], K[i]});
+    if (it != vplan->cls.end()) it->second = {nc[i], us_per_unit[i]};
+  }
+  return rebuild(vplan);
+}
+
+pnce_status pnce_varlen_stats(const pnce_varlen_plan *vplan, int *n_workgroups, int *n_tiles,
+                              float *max_cost, float *mean_cost) {
+  if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
+  const int nw = (int)vplan->wg_start.size() - 1;
+  float mx = 0.0f, sum = 0.0f;
+  for (float c : vplan->wg_cost) {
+    mx = std::max(mx, c);
+    sum += c;
+  }
+  if (n_workgroups) *n_workgroups = nw;
+  if (n_tiles) *n_tiles = (int)vplan->tiles.size();
+  if (max_cost) *max_cost = mx;
+  if (mean_cost) *mean_cost = nw > 0 ? sum / nw : 0.0f;
   return PNCE_OK;
 }
 

@@ -49,6 +49,30 @@ struct Tg64Args {
 };
 hipError_t launch_tg64(const Tg64Args &a, hipStream_t s);
 
+// Uneven batch: one persistent launch over a host-built work list.
+struct VFrame {           // one frame of the batch (device copy)
+  long long y_off;        // first code of the frame in the input buffer
+  long long h_off;        // first complex output of the frame
+  int R, N, K;
+  int bits_off, nbw;      // the frame's bit stream inside the bits table
+};
+struct VTile {            // one workgroup tile
+  int frame, a0, colg, nc;
+};
+struct VArgs {
+  const void *in;         // planar codes of every frame
+  float *out;             // complex64 CIRs of every frame
+  const float *scales;    // per-frame scale (or null)
+  const VFrame *frames;
+  const VTile *tiles;
+  const int *wg_start;    // tiles of workgroup w: [wg_start[w], wg_start[w+1])
+  const uint32_t *bits;   // concatenated bit streams, one per sequence length
+  int nbw_max;            // largest bit stream (LDS words)
+};
+hipError_t launch_varlen(int in_fmt, const VArgs &a, int n_wg, hipStream_t s);
+// One frame through the uniform kernel with a forced column width.
+hipError_t launch_tg_frame(int in_fmt, int nc, const TgArgs &a, hipStream_t s);
+
 // Quantiser: per-frame scale, then conversion into planar codes.
 hipError_t launch_pack(const float *y, void *yq, float *scales, int batch,
                        int R, int N, int fmt, hipStream_t s);

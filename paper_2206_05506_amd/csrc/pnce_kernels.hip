@@ -227,10 +227,21 @@ template <> struct Prefetch<MODE_BF16, 4> { static constexpr int value = 4; };
 template <> struct Prefetch<MODE_BF16, 2> { static constexpr int value = 4; };
 template <> struct Prefetch<MODE_BF16, 1> { static constexpr int value = 4; };
 
+// One workgroup tile of the contraction: 32 antennas from a0, 4 waves x
+// 32*NC output columns from colg, of one frame whose rows start at `in`
+// (input) and `out` / `cin` (output). The sequence bits must already be in
+// LDS (sbits); the first barrier below publishes them.
+struct Tile {
+  const void *in;
+  float *out;
+  const float *cin;
+  int R, t_len, ld_in, c_len, ld_out, N;
+  int a0, colg;
+  float alpha, beta;
+};
+
 template <int MODE, int IN, int NC>
-__global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, int tiles_c,
-                                                         int nbw_pad) {
-  extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+__device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits, uint32_t *stage) {
   constexpr int NWIN = 2 * NC;
   constexpr int RS = StageGeom<MODE>::rs;
   constexpr int PS = kRows * RS;
@@ -240,36 +251,20 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
   static_assert(CPB % PF == 0 && CPB % (NWIN / 2) == 0, "body must cover both rotations");
   using Raw = typename std::conditional<IN == IN_C64, RawC64, RawPacked>::type;
 
-  uint32_t *sbits = smem;
-  uint32_t *stage = smem + nbw_pad;
-
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int m = lane & 31;
   const int h = lane >> 5;
+  const int a0 = tl.a0;
+  const int col0 = tl.colg + wave * 32 * NC;
 
-  // Tile order: column groups of one (frame, antenna block) are consecutive,
-  // and consecutive tiles go to the same XCD (workgroups are dealt to the 8
-  // XCDs round robin), so a row block's input is fetched into one L2.
-  const int nt = a.batch * tiles_r * tiles_c;
-  const int bid = blockIdx.x;
-  const int t = (nt % 8 == 0) ? (bid % 8) * (nt / 8) + bid / 8 : bid;
-  const int cg = t % tiles_c;
-  const int rest = t / tiles_c;
-  const int rb = rest % tiles_r;
-  const int b = rest / tiles_r;
-  const int a0 = rb * kRows;
-  const int col0 = cg * (kWaves * 32 * NC) + wave * 32 * NC;
-
-  const int nchunks = (a.t_len + kChunk - 1) / kChunk;
+  const int nchunks = (tl.t_len + kChunk - 1) / kChunk;
   auto load_chunk = [&](Raw &r, int chunk) {
     if constexpr (IN == IN_C64) {
-      const float *fin = (const float *)a.in + (size_t)b * a.R * a.ld_in * 2;
-      load_stage(r, fin, a.R, a0, a.ld_in, a.t_len, chunk * kChunk, tid);
+      load_stage(r, (const float *)tl.in, tl.R, a0, tl.ld_in, tl.t_len, chunk * kChunk, tid);
     } else {
-      const uint16_t *fin = (const uint16_t *)a.in + (size_t)b * a.R * 2 * a.ld_in;
-      load_stage(r, fin, a.R, a0, a.ld_in, a.t_len, chunk * kChunk, tid);
+      load_stage(r, (const uint16_t *)tl.in, tl.R, a0, tl.ld_in, tl.t_len, chunk * kChunk, tid);
     }
   };
 
@@ -279,21 +274,20 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
 #pragma unroll
   for (int j = 0; j < PF; ++j)
     if (j < nchunks) load_chunk(raw[j], j);
-  for (int i = tid; i < a.nbw; i += kThreads) sbits[i] = a.bits[i];
   store_stage<MODE>(stage, raw[0], tid);
   if (PF < nchunks) load_chunk(raw[0], PF);
   __syncthreads();
 
   // Bit position of this lane's B fragment for block 0 at k-step 0:
   // reduction index t0 = 8h (+ e), output column col0 + m.
-  const int p_base = pos_mod(8 * h - m - col0, a.N);
+  const int p_base = pos_mod(8 * h - m - col0, tl.N);
 
   Win<MODE> win[NWIN];
   // Prologue: fragments of k-steps -(NWIN-2) .. -1 (used by blocks c >= 1
   // during the first 2c k-steps).
 #pragma unroll
   for (int j = 1; j <= NWIN - 2; ++j) {
-    const int p = pos_mod(p_base - 16 * j, a.N);
+    const int p = pos_mod(p_base - 16 * j, tl.N);
     make_window<MODE, IN>(win[NWIN - j], window8(sbits, p));
   }
 
@@ -381,28 +375,134 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
 
   // Epilogue: lane (m, h) holds, for block c, output column col0 + 32c + m
   // and rows 8*(v/4) + 4*h + (v%4) of the 32x32 accumulator.
-  const float alpha = a.alpha * (a.scales ? a.scales[b] : 1.0f);
+  const float alpha = tl.alpha;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int col = col0 + 32 * c + m;
-    if (col < a.c_len) {
+    if (col < tl.c_len) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int ant = a0 + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (ant < a.R) {
-          const size_t o = ((size_t)(b * a.R + ant) * a.ld_out + col) * 2;
+        if (ant < tl.R) {
+          const size_t o = ((size_t)ant * tl.ld_out + col) * 2;
           float re = alpha * acc_re[c][v];
           float im = alpha * acc_im[c][v];
-          if (a.beta != 0.0f) {
-            const f2a8 old = *(const f2a8 *)(a.cin + o);
-            re += a.beta * old.x;
-            im += a.beta * old.y;
+          if (tl.beta != 0.0f) {
+            const f2a8 old = *(const f2a8 *)(tl.cin + o);
+            re += tl.beta * old.x;
+            im += tl.beta * old.y;
           }
-          *(f2a8 *)(a.out + o) = f2a8{re, im};
+          *(f2a8 *)(tl.out + o) = f2a8{re, im};
         }
       }
     }
   }
+}
+
+
+// One tile per workgroup over a uniform batch.
+template <int MODE, int IN, int NC>
+__global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, int tiles_c,
+                                                         int nbw_pad) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+  // Tile order: column groups of one (frame, antenna block) are consecutive,
+  // and consecutive tiles go to the same XCD (workgroups are dealt to the 8
+  // XCDs round robin), so a row block's input is fetched into one L2.
+  const int nt = a.batch * tiles_r * tiles_c;
+  const int bid = blockIdx.x;
+  const int t = (nt % 8 == 0) ? (bid % 8) * (nt / 8) + bid / 8 : bid;
+  const int cg = t % tiles_c;
+  const int rest = t / tiles_c;
+  const int rb = rest % tiles_r;
+  const int b = rest / tiles_r;
+
+  for (int i = threadIdx.x; i < a.nbw; i += kThreads) smem[i] = a.bits[i];
+  Tile tl;
+  if constexpr (IN == IN_C64)
+    tl.in = (const float *)a.in + (size_t)b * a.R * a.ld_in * 2;
+  else
+    tl.in = (const uint16_t *)a.in + (size_t)b * a.R * 2 * a.ld_in;
+  tl.out = a.out + (size_t)b * a.R * a.ld_out * 2;
+  tl.cin = a.cin ? a.cin + (size_t)b * a.R * a.ld_out * 2 : nullptr;
+  tl.R = a.R;
+  tl.t_len = a.t_len;
+  tl.ld_in = a.ld_in;
+  tl.c_len = a.c_len;
+  tl.ld_out = a.ld_out;
+  tl.N = a.N;
+  tl.a0 = rb * kRows;
+  tl.colg = cg * (kWaves * 32 * NC);
+  tl.alpha = a.alpha * (a.scales ? a.scales[b] : 1.0f);
+  tl.beta = a.beta;
+  run_tile<MODE, IN, NC>(tl, smem, smem + nbw_pad);
+}
+
+// Persistent kernel over an uneven batch: workgroup w walks its slice of a
+// host-built work list; each tile names its frame (shape, sequence length,
+// offsets) and its column width (32*nc lags per wave), so frames of any
+// (R, N, T*L) share one launch. The bit stream is reloaded only when the
+// sequence length changes between consecutive tiles.
+template <int MODE, int IN>
+__global__ __launch_bounds__(kThreads, 2) void varlen_kernel(VArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+  const int nbw_pad = (a.nbw_max + 3) & ~3;
+  uint32_t *stage = smem + nbw_pad;
+  int cur_bits = -1;
+  const int end = a.wg_start[blockIdx.x + 1];
+  for (int i = a.wg_start[blockIdx.x]; i < end; ++i) {
+    const VTile vt = a.tiles[i];
+    const VFrame f = a.frames[vt.frame];
+    if (f.bits_off != cur_bits) {
+      for (int j = threadIdx.x; j < f.nbw; j += kThreads) smem[j] = a.bits[f.bits_off + j];
+      cur_bits = f.bits_off;
+    }
+    Tile tl;
+    tl.in = (const uint16_t *)a.in + f.y_off;
+    tl.out = a.out + f.h_off * 2;
+    tl.cin = nullptr;
+    tl.R = f.R;
+    tl.t_len = f.N + 1;
+    tl.ld_in = f.N + 1;
+    tl.c_len = f.K;
+    tl.ld_out = f.K;
+    tl.N = f.N;
+    tl.a0 = vt.a0;
+    tl.colg = vt.colg;
+    tl.alpha = (a.scales ? a.scales[vt.frame] : 1.0f) / (float)f.N;
+    tl.beta = 0.0f;
+    if (vt.nc == 4)
+      run_tile<MODE, IN, 4>(tl, smem, stage);
+    else if (vt.nc == 2)
+      run_tile<MODE, IN, 2>(tl, smem, stage);
+    else
+      run_tile<MODE, IN, 1>(tl, smem, stage);
+  }
+}
+
+hipError_t launch_varlen(int in_fmt, const VArgs &a, int n_wg, hipStream_t s) {
+  if (n_wg <= 0) return hipErrorInvalidValue;
+  const int nbw_pad = (a.nbw_max + 3) & ~3;
+  const size_t lds = (size_t)(nbw_pad + 2 * stage_dwords<MODE_BF16>()) * 4;
+  if (in_fmt == IN_BF16) {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void *)varlen_kernel<MODE_BF16, IN_BF16>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((varlen_kernel<MODE_BF16, IN_BF16>), dim3(n_wg), dim3(kThreads), lds, s,
+                       a);
+  } else if (in_fmt == IN_F16) {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void *)varlen_kernel<MODE_BF16, IN_F16>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((varlen_kernel<MODE_BF16, IN_F16>), dim3(n_wg), dim3(kThreads), lds, s,
+                       a);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -621,6 +721,20 @@ static hipError_t launch_tg_mode(const TgArgs &a, hipStream_t s) {
   if (a.c_len > 256) return launch_tg_nc<MODE, IN, 4>(a, s);
   if (a.c_len > 128) return launch_tg_nc<MODE, IN, 2>(a, s);
   return launch_tg_nc<MODE, IN, 1>(a, s);
+}
+
+hipError_t launch_tg_frame(int in_fmt, int nc, const TgArgs &a, hipStream_t s) {
+  if (in_fmt == IN_BF16) {
+    if (nc == 4) return launch_tg_nc<MODE_BF16, IN_BF16, 4>(a, s);
+    if (nc == 2) return launch_tg_nc<MODE_BF16, IN_BF16, 2>(a, s);
+    return launch_tg_nc<MODE_BF16, IN_BF16, 1>(a, s);
+  }
+  if (in_fmt == IN_F16) {
+    if (nc == 4) return launch_tg_nc<MODE_BF16, IN_F16, 4>(a, s);
+    if (nc == 2) return launch_tg_nc<MODE_BF16, IN_F16, 2>(a, s);
+    return launch_tg_nc<MODE_BF16, IN_F16, 1>(a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s) {
