@@ -32,6 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+
+# HBM bytes per launch of the bf16 estimate measured with rocprofv3 --pmc
+# FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
+# for the kernel source with this sha256; any other source reports null.
+TRAFFIC = {"source_sha256": "21ae562ad810b171b76cc77e251cb2039825bc63b2c92f9362757732c671e8ea",
+           "bytes_per_launch": 203393399}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix
 
@@ -44,7 +50,20 @@ def parse():
     ap.add_argument("--latency-iters", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only 3 bf16 estimates and 3 plain copies of the frames (for "
+                         "rocprofv3 --pmc byte counters and their copy-kernel calibration)")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the quantiser/adjoint/refinement/uneven-batch timings")
     return ap.parse_args()
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2206_05506_amd", "csrc", "pnce_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return TRAFFIC["bytes_per_launch"] if sha == TRAFFIC["source_sha256"] else None
 
 
 def make_inputs(plan, cfg, torch):
@@ -125,6 +144,60 @@ def cpu_baseline(y_dev, cfg, target_s):
                       f"R={cfg.R}), FP64 direct correlation, {dt:.1f} s"}
 
 
+def other_rows(plan, cfg, y, H, torch, args):
+    """Timings of the other forms of the path on the same frames (and, for
+    the uneven batch, on its own 4096-frame workload)."""
+    B, R, N, K = cfg.B, cfg.R, cfg.N, cfg.K
+    res = {}
+    q = torch.empty((B, R, 2, N + 1), dtype=torch.int16, device="cuda")
+    sc = torch.empty((B,), dtype=torch.float32, device="cuda")
+    ms, _ = time_steps(lambda: plan.pack(y, "bf16", out=q, scales=sc), args.steps, 2, torch)
+    byt = B * R * N * 8 * 2 + B * R * 2 * (N + 1) * 2
+    res["pack_bf16"] = {"ms": ms, "GB/s": byt / ms / 1e6, "note": "two passes: max, convert"}
+    Hq = torch.empty_like(H)
+    ms, _ = time_steps(lambda: plan.estimate_packed(q, sc, "bf16", out=Hq), args.steps, 2, torch)
+    byt = B * R * 2 * (N + 1) * 2 + B * R * K * 8
+    res["estimate_packed_bf16"] = {"ms": ms, "GB/s": byt / ms / 1e6}
+    A = torch.empty_like(y)
+    ms, _ = time_steps(lambda: plan.adjoint(H, "f32s", out=A), args.steps, 2, torch)
+    res["adjoint_f32s"] = {"ms": ms, "TFLOP/s": 4.0 * B * R * N * K / ms / 1e9}
+    X = H.clone()
+    work = torch.empty_like(y)
+    ms, _ = time_steps(lambda: plan.refine(y, X, 1, work=work), max(2, args.steps // 4), 1, torch)
+    res["refine_1_step"] = {"ms": ms, "note": "FP64-accumulated residual + f32s correlation"}
+    del q, Hq, A, X, work
+    res["uneven_batch"] = uneven_batch(torch, args)
+    return res
+
+
+def uneven_batch(torch, args):
+    """4096 frames of uneven (R, N, T, L) (seed 3), bf16 codes: one persistent
+    launch (autotuned) against one launch per frame."""
+    import synth
+    from paper_2206_05506_amd import VarlenPlan
+    shapes = [(int(R), (1 << int(d)) - 1, int(T), int(L))
+              for R, d, T, L in synth.varlen_shapes(4096, 3)]
+    vp = VarlenPlan(shapes)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    Yq = torch.randn((vp.n_codes,), generator=g, device="cuda").to(torch.bfloat16)
+    Yq = Yq.view(torch.int16).contiguous()
+    H = torch.empty((vp.n_out,), dtype=torch.complex64, device="cuda")
+    vp.tune(Yq, None, out=H, reps=3)
+    ms_p, _ = time_steps(lambda: vp.estimate(Yq, None, out=H), args.steps, 2, torch)
+    ms_e, _ = time_steps(lambda: vp.estimate_each(Yq, None, out=H), 3, 1, torch)
+    cirs = sum(R * T for R, N, T, L in shapes)
+    byt = vp.n_codes * 2 + vp.n_out * 8
+    flops = sum(4.0 * R * N * T * L for R, N, T, L in shapes)
+    st = vp.stats()
+    vp.close()
+    return {"frames": len(shapes), "persistent_ms": ms_p, "per_frame_launches_ms": ms_e,
+            "speedup": ms_e / ms_p, "CIR/s": cirs / (ms_p * 1e-3),
+            "GB/s": byt / ms_p / 1e6, "hbm_frac": byt / ms_p / 1e6 / HBM_PEAK_GBS,
+            "mfma_frac": flops / ms_p / 1e9 / BF16_PEAK_TFLOPS,
+            "workgroups": st["workgroups"], "tiles": st["tiles"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -141,6 +214,18 @@ def main():
     plan = Plan(cfg.N, cfg.T, cfg.L, cfg.R)
     y, h = make_inputs(plan, cfg, torch)
     H_bf = torch.empty((cfg.B, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
+    if args.pmc_probe:
+        y2 = torch.empty_like(y)
+        for _ in range(3):
+            plan.estimate(y, "bf16", out=H_bf)
+        for _ in range(3):
+            y2.copy_(y)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": True, "estimate_bytes_read": cfg.B * cfg.R * cfg.N * 8,
+                          "estimate_bytes_written": cfg.B * cfg.R * cfg.K * 8,
+                          "copy_bytes_each_way": y.numel() * 8}), flush=True)
+        plan.close()
+        return
     H_32 = torch.empty_like(H_bf)
     H_mf = torch.empty_like(H_bf)
 
@@ -200,10 +285,12 @@ def main():
                     "delta_bf16_fp32": nmse_bf - nmse_32},
         "wall_ms_per_step": wall_bf,
         "roofline": {"bound": "hbm", "achieved": ach_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": ach_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": ach_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "tg_kernel<BF16, c64 in, NC=4>",
                      "mfma_frac": flops / (ms_bf * 1e-3) / 1e12 / BF16_PEAK_TFLOPS},
     }
+    if not args.no_rows:
+        out["rows"] = other_rows(plan, cfg, y, H_32, torch, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(y, cfg, args.cpu_seconds)
     plan.close()

@@ -339,11 +339,13 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits, 
               are[s] = *(const u32x4 *)(st + s * PS + m * RS + 8 * u + 4 * h);
               aim[s] = *(const u32x4 *)(st + (NP + s) * PS + m * RS + 8 * u + 4 * h);
             }
+            // split part outer, lag block inner: the dependent updates of one
+            // accumulator are 2*NC matrix-core ops apart
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              const u32x4 bw = win[(q - 2 * c + NWIN) % NWIN].f;
+            for (int s = 0; s < NP; ++s) {
 #pragma unroll
-              for (int s = 0; s < NP; ++s) {
+              for (int c = 0; c < NC; ++c) {
+                const u32x4 bw = win[(q - 2 * c + NWIN) % NWIN].f;
                 if constexpr (IN == IN_F16) {
                   acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                       __builtin_bit_cast(f16x8, are[s]), __builtin_bit_cast(f16x8, bw),
