@@ -60,6 +60,8 @@ typedef int pnce_status;
                           /* even), bf16 matrix cores, FP32 accumulation      */
 #define PNCE_PREC_F64 3   /* FP64 vector ALU on c128 buffers (for gradient    */
                           /* checks; not a throughput path)                   */
+#define PNCE_PREC_F64ACC 4 /* c64 buffers, FP64 sums on FP64 matrix cores    */
+                           /* (v_mfma_f64_16x16x4_f64), one rounding to FP32  */
 
 /* Reduced-precision storage formats of Y (the half-precision conversion
  * before correlation, Section III-B). */
@@ -100,7 +102,7 @@ pnce_status pnce_get_shape(const pnce_plan *plan, int *N, int *T, int *L, int *R
  * Y: [batch][R][N] c64 (c128 when precision == PNCE_PREC_F64);
  * H: [batch][R][T*L] c64 (c128 for PNCE_PREC_F64), read only if beta != 0;
  * scales: NULL or `batch` device floats. Y and H must not overlap.
- * precision: PNCE_PREC_F32, _F32S, _BF16 or _F64.
+ * precision: PNCE_PREC_F32, _F32S, _BF16, _F64 or _F64ACC.
  * Errors: null Y/H, batch <= 0, unknown precision -> PNCE_E_INVALID.
  */
 pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y,
@@ -144,7 +146,7 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream,
  * the residual y - P h of the receive model of Eq. 9.
  * G: [batch][R][T*L]; A, C: [batch][R][N]; c64, or c128 for
  * PNCE_PREC_F64. C may equal A, or be NULL when beta == 0. G must not
- * overlap A. precision: PNCE_PREC_F32, _F32S, _BF16 or _F64.
+ * overlap A. precision: PNCE_PREC_F32, _F32S, _BF16, _F64 or _F64ACC.
  */
 pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
                          void *A, const void *C, int batch, int precision,
@@ -155,7 +157,7 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
  * comes from the -1/M term of Eq. 1; each step removes part of it):
  *   repeat `steps` times:  r = y - P x;  x = x + P^T r / N.
  * Both contractions are FP32-accurate (PNCE_PREC_F32S); the residual of the
- * last step is accumulated in FP64 (FP64 matrix cores).
+ * last step is accumulated in FP64 (PNCE_PREC_F64ACC).
  * y: [batch][R][N] c64 (the original, unquantised frames);
  * X: [batch][R][T*L] c64, in: the starting estimate, out: refined;
  * work: device scratch of batch*R*N*8 bytes (the residual). steps >= 0.

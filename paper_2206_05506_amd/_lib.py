@@ -10,7 +10,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpnce.so")
+# PNCE_LIBRARY may name another build of the library (e.g. a tuned variant).
+LIB_PATH = os.environ.get("PNCE_LIBRARY") or os.path.join(_HERE, "libpnce.so")
 
 PNCE_OK = 0
 PNCE_W_LAG_ALIAS = 1
@@ -23,6 +24,7 @@ PNCE_PREC_F32 = 0
 PNCE_PREC_F32S = 1
 PNCE_PREC_BF16 = 2
 PNCE_PREC_F64 = 3
+PNCE_PREC_F64ACC = 4
 
 PNCE_FMT_BF16 = 1
 PNCE_FMT_F16 = 2

@@ -15,7 +15,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/pnce.h"
+#include "pnce.h"
 #include "pnce_internal.h"
 
 struct pnce_plan {
@@ -94,7 +94,7 @@ std::vector<uint32_t> bit_stream(const std::vector<signed char> &s, int len_word
 
 bool valid_prec(int p) {
   return p == PNCE_PREC_F32 || p == PNCE_PREC_F32S || p == PNCE_PREC_BF16 ||
-         p == PNCE_PREC_F64;
+         p == PNCE_PREC_F64 || p == PNCE_PREC_F64ACC;
 }
 
 bool valid_fmt(int f) {
@@ -119,7 +119,9 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
                    const void *cin, const uint32_t *bits, const float *scales,
                    int batch, double alpha, double beta) {
   hipError_t e;
-  if (precision == PNCE_PREC_F64) {
+  if (precision == PNCE_PREC_F64 || (in_fmt == pnce::IN_C64 && t_len < 2)) {
+    // FP64 vector kernel: the FP64 path, and complex64 rows of one term
+    // (the tiled loaders read sample pairs).
     pnce::Tg64Args a{};
     a.in = in;
     a.out = out;
@@ -135,8 +137,8 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.N = p->N;
     a.alpha = alpha;
     a.beta = beta;
-    a.in_f64 = true;
-    a.out_f64 = true;
+    a.in_f64 = precision == PNCE_PREC_F64;
+    a.out_f64 = precision == PNCE_PREC_F64;
     e = pnce::launch_tg64(a, s);
   } else {
     pnce::TgArgs a{};
@@ -155,7 +157,8 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.nbw = p->nbw;
     a.alpha = (float)alpha;
     a.beta = (float)beta;
-    e = pnce::launch_tg(precision, in_fmt, a, s);
+    e = precision == PNCE_PREC_F64ACC ? pnce::launch_f64mm(a, s)
+                                      : pnce::launch_tg(precision, in_fmt, a, s);
   }
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return PNCE_OK;
@@ -314,31 +317,10 @@ pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void
   hipStream_t s = (hipStream_t)stream;
   for (int j = 0; j < steps; ++j) {
     // r = y - P x   (P x = sum_k x[k] s[(n-k) mod N]: adjoint stream, alpha -1)
-    if (j + 1 < steps) {
-      if (pnce_status st = run_tg(plan, s, PNCE_PREC_F32S, pnce::IN_C64, X, plan->K, plan->K,
-                                  work, plan->N, y, plan->d_rev, nullptr, batch, -1.0, 1.0))
-        return st;
-    } else {
-      pnce::Tg64Args a{};
-      a.in = X;
-      a.out = work;
-      a.cin = y;
-      a.bits = plan->d_rev;
-      a.scales = nullptr;
-      a.R = plan->R;
-      a.batch = batch;
-      a.t_len = plan->K;
-      a.ld_in = plan->K;
-      a.c_len = plan->N;
-      a.ld_out = plan->N;
-      a.N = plan->N;
-      a.alpha = -1.0;
-      a.beta = 1.0;
-      a.in_f64 = false;
-      a.out_f64 = false;
-      hipError_t e = pnce::launch_tg64(a, s);
-      if (e != hipSuccess) return hip_fail(e, "residual launch");
-    }
+    const int prec = (j + 1 < steps) ? PNCE_PREC_F32S : PNCE_PREC_F64ACC;
+    if (pnce_status st = run_tg(plan, s, prec, pnce::IN_C64, X, plan->K, plan->K, work, plan->N,
+                                y, plan->d_rev, nullptr, batch, -1.0, 1.0))
+      return st;
     // x = x + P^T r / N
     if (pnce_status st = run_tg(plan, s, PNCE_PREC_F32S, pnce::IN_C64, work, plan->N, plan->N,
                                 X, plan->K, X, plan->d_fwd, nullptr, batch, 1.0 / plan->N, 1.0))

@@ -33,6 +33,10 @@ struct TgArgs {
 
 hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s);
 
+// Same contraction on complex64 rows with FP64 sums on FP64 matrix cores;
+// alpha and beta are applied in FP64 before the single rounding to FP32.
+hipError_t launch_f64mm(const TgArgs &a, hipStream_t s);
+
 // FP64-accumulating vector kernel; element types selected by the flags.
 struct Tg64Args {
   const void *in;

@@ -32,22 +32,25 @@ typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
 typedef float f2a8 __attribute__((ext_vector_type(2), aligned(8)));
 
 constexpr int kRows = 32;      // antennas per tile
-constexpr int kChunk = 32;     // samples per LDS stage (two 16-sample k-steps)
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 
 // ---------------------------------------------------------------------------
-// Operand formats of a stage: number of planes and dwords per plane row.
+// Samples per LDS stage (one barrier each) and operand formats of a stage.
+// The bf16 mode runs 4 k-steps (64 samples) per stage so that its short
+// matrix-core work per k-step amortises the stage's barrier and LDS round
+// trips; the FP32-accurate and FP32 modes already do 3x / 4x more matrix
+// work per k-step and use 32-sample stages.
 // Rows are padded by 4 dwords so that the 16-byte fragment reads of 8
 // consecutive rows fall in distinct LDS banks.
 //   MODE_F32  : 2 fp32 planes (re, im), 32 samples + pad  -> 36 dwords
 //   MODE_F32S : 6 bf16 planes (re hi/mid/lo, im hi/mid/lo) -> 20 dwords
-//   MODE_BF16 : 2 bf16 (or f16 for IN_F16) planes          -> 20 dwords
+//   MODE_BF16 : 2 bf16 (or f16) planes, 64 samples + pad   -> 36 dwords
 // ---------------------------------------------------------------------------
 template <int MODE> struct StageGeom;
-template <> struct StageGeom<MODE_F32> { static constexpr int planes = 2, rs = 36; };
-template <> struct StageGeom<MODE_F32S> { static constexpr int planes = 6, rs = 20; };
-template <> struct StageGeom<MODE_BF16> { static constexpr int planes = 2, rs = 20; };
+template <> struct StageGeom<MODE_F32> { static constexpr int ch = 32, planes = 2, rs = 36; };
+template <> struct StageGeom<MODE_F32S> { static constexpr int ch = 32, planes = 6, rs = 20; };
+template <> struct StageGeom<MODE_BF16> { static constexpr int ch = 64, planes = 2, rs = 36; };
 
 template <int MODE> constexpr int stage_dwords() {
   return StageGeom<MODE>::planes * kRows * StageGeom<MODE>::rs;
@@ -85,97 +88,231 @@ __device__ __forceinline__ void split3(float x, uint32_t &hi, uint32_t &mid,
 //   (row = t >> 3, plane = (t >> 2) & 1, 8 codes at 8*(t & 3)).
 // Samples at or beyond t_len and antennas at or beyond R read as zero.
 // ---------------------------------------------------------------------------
-struct RawC64 { f32x4 v[2]; };
-struct RawPacked { u32x4 v; };
+// One thread's share of a CH-sample stage held in registers (plain loads,
+// waited for by the compiler): complex64 input, CH/16 sample pairs; packed
+// input, CH/32 pieces of 8 codes.
+template <int CH> struct RawC64 {
+  f32x4 v[CH / 16];
+};
+template <int CH> struct RawPacked {
+  u32x4 v[CH / 32];
+};
 
-__device__ __forceinline__ void load_stage(RawC64 &raw, const float *in_frame,
+// Where the 16 bytes of sample pair (row a, samples n, n+1) are read from:
+// a whole pair is read in place; a pair cut by the end of its row (n + 1 ==
+// t_len) is read one sample early and shifted; anything outside the rows
+// reads row 0 and is zeroed. Returns the mode (1 whole, 2 cut, 0 outside)
+// and the in-bounds element offset. Needs t_len >= 2 (the host routes
+// one-term rows to the vector kernel).
+__device__ __forceinline__ uint32_t pair_source(int a, int n, int R, int ld_in, int t_len,
+                                                size_t &off) {
+  const bool row_ok = a < R;
+  const bool full = row_ok && (n + 1 < t_len);
+  const bool cut = row_ok && (n + 1 == t_len);
+  const int na = full ? n : (cut ? n - 1 : 0);
+  const int aa = row_ok ? a : 0;
+  off = ((size_t)aa * ld_in + na) * 2;
+  return full ? 1u : (cut ? 2u : 0u);
+}
+
+__device__ __forceinline__ f32x4 pair_apply(uint32_t md, f32x4 v) {
+  f32x4 x;
+  x.x = md == 1u ? v.x : (md == 2u ? v.z : 0.f);
+  x.y = md == 1u ? v.y : (md == 2u ? v.w : 0.f);
+  x.z = md == 1u ? v.z : 0.f;
+  x.w = md == 1u ? v.w : 0.f;
+  return x;
+}
+
+// c64 rows into registers: pair q = t + 256 i (row q / (CH/2), samples
+// 2 (q % (CH/2)) and +1); each wave instruction reads 64 consecutive pairs.
+template <int CH>
+__device__ __forceinline__ void load_stage(RawC64<CH> &raw, const float *in_frame,
                                            int R, int a0, int ld_in, int t_len,
                                            int n0, int tid) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < CH / 16; ++i) {
     const int q = tid + kThreads * i;
-    const int row = q >> 4;
-    const int n = n0 + 2 * (q & 15);
-    const int a = a0 + row;
-    f32x4 x = {0.f, 0.f, 0.f, 0.f};
-    if (a < R) {
-      const float *p = in_frame + ((size_t)a * ld_in + n) * 2;
-      if (n + 1 < t_len) {
-        f4a8 t = *(const f4a8 *)p;
-        x = f32x4{t.x, t.y, t.z, t.w};
-      } else if (n < t_len) {
-        f2a8 t = *(const f2a8 *)p;
-        x.x = t.x;
-        x.y = t.y;
-      }
-    }
-    raw.v[i] = x;
+    size_t off;
+    const uint32_t md =
+        pair_source(a0 + q / (CH / 2), n0 + 2 * (q % (CH / 2)), R, ld_in, t_len, off);
+    const f4a8 v = *(const f4a8 *)(in_frame + off);
+    raw.v[i] = pair_apply(md, f32x4{v.x, v.y, v.z, v.w});
   }
 }
 
-__device__ __forceinline__ void load_stage(RawPacked &raw, const uint16_t *in_frame,
+// Packed rows: 32 rows x 2 planes x CH codes in 16-byte pieces; piece
+// q = t + 256 i covers row q / (CH/4), plane (q / (CH/8)) & 1, codes
+// 8 (q % (CH/8)) .. +7.
+// AL: rows are 8-code aligned and t_len is a multiple of 8 (N + 1 = 2^d with
+// d >= 3), so one branch-free 16-byte load per piece is exact; otherwise
+// codes are read one by one.
+template <bool AL, int CH>
+__device__ __forceinline__ void load_stage(RawPacked<CH> &raw, const uint16_t *in_frame,
                                            int R, int a0, int ld_in, int t_len,
                                            int n0, int tid) {
-  const int row = tid >> 3;
-  const int plane = (tid >> 2) & 1;
-  const int n = n0 + 8 * (tid & 3);
-  const int a = a0 + row;
-  u32x4 x = {0u, 0u, 0u, 0u};
-  if (a < R) {
-    const uint16_t *p = in_frame + ((size_t)a * 2 + plane) * ld_in + n;
-    if (n + 8 <= t_len && (ld_in & 7) == 0) {
-      x = *(const u32x4 *)p;
-    } else {
-      uint32_t e[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) e[j] = (n + j < t_len) ? p[j] : 0u;
-      x = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]),
-                pack2(e[6], e[7])};
+  for (int i = 0; i < CH / 32; ++i) {
+    const int q = tid + kThreads * i;
+    const int row = q / (CH / 4);
+    const int plane = (q / (CH / 8)) & 1;
+    const int n = n0 + 8 * (q % (CH / 8));
+    const int a = a0 + row;
+    if constexpr (AL) {
+      const bool ok = (a < R) && (n < t_len);
+      const int aa = ok ? a : 0;
+      const int nn = ok ? n : 0;
+      const u32x4 v = *(const u32x4 *)(in_frame + ((size_t)aa * 2 + plane) * ld_in + nn);
+      raw.v[i] = ok ? v : u32x4{0u, 0u, 0u, 0u};
+    } else {
+      u32x4 x = {0u, 0u, 0u, 0u};
+      if (a < R) {
+        const uint16_t *p = in_frame + ((size_t)a * 2 + plane) * ld_in + n;
+        uint32_t e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) e[j] = (n + j < t_len) ? p[j] : 0u;
+        x = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
+      }
+      raw.v[i] = x;
     }
   }
-  raw.v = x;
 }
 
-// Register -> LDS: convert to the operand format while storing.
+// Register -> LDS: one sample pair (re0, im0, re1, im1) of stage row `row`,
+// pair `pr`, converted to the operand format while stored.
 template <int MODE>
-__device__ __forceinline__ void store_stage(uint32_t *st, const RawC64 &raw, int tid) {
+__device__ __forceinline__ void store_pair(uint32_t *st, int row, int pr, f32x4 x) {
   constexpr int RS = StageGeom<MODE>::rs;
   constexpr int PS = kRows * RS;  // plane stride in dwords
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int q = tid + kThreads * i;
-    const int row = q >> 4;
-    const int pr = q & 15;
-    const f32x4 x = raw.v[i];  // re0, im0, re1, im1
-    if constexpr (MODE == MODE_F32) {
-      *(f2a8 *)(st + row * RS + 2 * pr) = f2a8{x.x, x.z};
-      *(f2a8 *)(st + PS + row * RS + 2 * pr) = f2a8{x.y, x.w};
-    } else if constexpr (MODE == MODE_BF16) {
-      st[row * RS + pr] = pack2(bf16_bits(x.x), bf16_bits(x.z));
-      st[PS + row * RS + pr] = pack2(bf16_bits(x.y), bf16_bits(x.w));
-    } else {  // MODE_F32S
-      uint32_t h0, m0, l0, h1, m1, l1;
-      split3(x.x, h0, m0, l0);
-      split3(x.z, h1, m1, l1);
-      st[0 * PS + row * RS + pr] = pack2(h0, h1);
-      st[1 * PS + row * RS + pr] = pack2(m0, m1);
-      st[2 * PS + row * RS + pr] = pack2(l0, l1);
-      split3(x.y, h0, m0, l0);
-      split3(x.w, h1, m1, l1);
-      st[3 * PS + row * RS + pr] = pack2(h0, h1);
-      st[4 * PS + row * RS + pr] = pack2(m0, m1);
-      st[5 * PS + row * RS + pr] = pack2(l0, l1);
-    }
+  if constexpr (MODE == MODE_F32) {
+    *(f2a8 *)(st + row * RS + 2 * pr) = f2a8{x.x, x.z};
+    *(f2a8 *)(st + PS + row * RS + 2 * pr) = f2a8{x.y, x.w};
+  } else if constexpr (MODE == MODE_BF16) {
+    st[row * RS + pr] = pack2(bf16_bits(x.x), bf16_bits(x.z));
+    st[PS + row * RS + pr] = pack2(bf16_bits(x.y), bf16_bits(x.w));
+  } else {  // MODE_F32S
+    uint32_t h0, m0, l0, h1, m1, l1;
+    split3(x.x, h0, m0, l0);
+    split3(x.z, h1, m1, l1);
+    st[0 * PS + row * RS + pr] = pack2(h0, h1);
+    st[1 * PS + row * RS + pr] = pack2(m0, m1);
+    st[2 * PS + row * RS + pr] = pack2(l0, l1);
+    split3(x.y, h0, m0, l0);
+    split3(x.w, h1, m1, l1);
+    st[3 * PS + row * RS + pr] = pack2(h0, h1);
+    st[4 * PS + row * RS + pr] = pack2(m0, m1);
+    st[5 * PS + row * RS + pr] = pack2(l0, l1);
   }
 }
 
-template <int MODE>
-__device__ __forceinline__ void store_stage(uint32_t *st, const RawPacked &raw, int tid) {
+template <int MODE, int CH>
+__device__ __forceinline__ void store_stage(uint32_t *st, const RawC64<CH> &raw, int tid) {
+#pragma unroll
+  for (int i = 0; i < CH / 16; ++i) {
+    const int q = tid + kThreads * i;
+    store_pair<MODE>(st, q / (CH / 2), q % (CH / 2), raw.v[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Complex64 input through LDS by direct global->LDS loads (the pipeline of
+// the tiled kernel). Each wave issues two global_load_lds_dwordx4 per chunk:
+// lane i of wave w, load j fetches sample pair Q = 128w + 64j + i (row Q >> 4,
+// pair Q & 15) into ring bytes 16Q. A wave later converts exactly the pairs
+// it fetched, so only its own outstanding-load count matters (vmcnt), and no
+// register holds in-flight data. The compiler does not track these loads,
+// so waits are explicit; barriers are bare s_barrier with LDS waits.
+// ---------------------------------------------------------------------------
+// Ring slot of one CH-sample chunk: 32 rows x CH samples x 8 bytes.
+template <int CH> constexpr int ring_dwords() { return kRows * CH * 2; }
+
+// DMA mapping: wave w, load j (j < CH/16), lane i fetches pair
+// q = 64 (CH/16) w + 64 j + i (row q / (CH/2), pair q % (CH/2)) to bytes 16q.
+template <int CH>
+__device__ __forceinline__ int dma_pair(int wave, int j, int lane) {
+  return 64 * (CH / 16) * wave + 64 * j + lane;
+}
+
+template <int CH>
+__device__ __forceinline__ void dma_chunk(uint32_t *slot, const float *in_frame, int R, int a0,
+                                          int ld_in, int t_len, int n0, int wave, int lane) {
+#pragma unroll
+  for (int j = 0; j < CH / 16; ++j) {
+    const int q = dma_pair<CH>(wave, j, lane);
+    size_t off;
+    (void)pair_source(a0 + q / (CH / 2), n0 + 2 * (q % (CH / 2)), R, ld_in, t_len, off);
+    __builtin_amdgcn_global_load_lds(
+        (const void *)(in_frame + off),
+        (__attribute__((address_space(3))) void *)(slot + 4 * dma_pair<CH>(wave, j, 0)), 16, 0,
+        0);
+  }
+}
+
+template <int MODE, int CH>
+__device__ __forceinline__ void convert_chunk(uint32_t *st, const uint32_t *slot, int R, int a0,
+                                              int ld_in, int t_len, int n0, int wave, int lane) {
+#pragma unroll
+  for (int j = 0; j < CH / 16; ++j) {
+    const int q = dma_pair<CH>(wave, j, lane);
+    size_t off;
+    const uint32_t md =
+        pair_source(a0 + q / (CH / 2), n0 + 2 * (q % (CH / 2)), R, ld_in, t_len, off);
+    const f32x4 v = *(const f32x4 *)(slot + 4 * q);
+    store_pair<MODE>(st, q / (CH / 2), q % (CH / 2), pair_apply(md, v));
+  }
+}
+
+// Steady-state chunks (every chunk but the last) need no masking: the pair
+// lies inside its row, and rows at or beyond R were clamped to row 0 once
+// per tile (their outputs are never stored).
+template <int CH>
+__device__ __forceinline__ void dma_chunk_fast(uint32_t *slot, const float *const *src, int n0,
+                                               int wave) {
+#pragma unroll
+  for (int j = 0; j < CH / 16; ++j)
+    __builtin_amdgcn_global_load_lds(
+        (const void *)(src[j] + 2 * n0),
+        (__attribute__((address_space(3))) void *)(slot + 4 * dma_pair<CH>(wave, j, 0)), 16, 0,
+        0);
+}
+
+template <int MODE, int CH>
+__device__ __forceinline__ void convert_chunk_fast(uint32_t *st, const uint32_t *slot, int wave,
+                                                   int lane) {
+#pragma unroll
+  for (int j = 0; j < CH / 16; ++j) {
+    const int q = dma_pair<CH>(wave, j, lane);
+    store_pair<MODE>(st, q / (CH / 2), q % (CH / 2), *(const f32x4 *)(slot + 4 * q));
+  }
+}
+
+// s_waitcnt with only one counter constrained (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Workgroup barrier that does not drain outstanding global->LDS loads.
+__device__ __forceinline__ void bar_lds() {
+  wait_lds();
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int MODE, int CH>
+__device__ __forceinline__ void store_stage(uint32_t *st, const RawPacked<CH> &raw, int tid) {
   constexpr int RS = StageGeom<MODE>::rs;
   constexpr int PS = kRows * RS;
-  const int row = tid >> 3;
-  const int plane = (tid >> 2) & 1;
-  *(u32x4 *)(st + plane * PS + row * RS + 4 * (tid & 3)) = raw.v;
+#pragma unroll
+  for (int i = 0; i < CH / 32; ++i) {
+    const int q = tid + kThreads * i;
+    const int row = q / (CH / 4);
+    const int plane = (q / (CH / 8)) & 1;
+    *(u32x4 *)(st + plane * PS + row * RS + 4 * (q % (CH / 8))) = raw.v[i];
+  }
 }
 
 // 8 bits of the periodic stream starting at bit p (p + 63 < 32 * nbw).
@@ -183,6 +320,13 @@ __device__ __forceinline__ uint32_t window8(const uint32_t *sbits, int p) {
   const uint32_t w0 = sbits[p >> 5];
   const uint32_t w1 = sbits[(p >> 5) + 1];
   return __builtin_amdgcn_alignbit(w1, w0, (uint32_t)(p & 31)) & 0xFFu;
+}
+
+// 32 bits of the periodic stream starting at bit p.
+__device__ __forceinline__ uint32_t window32(const uint32_t *sbits, int p) {
+  const uint32_t w0 = sbits[p >> 5];
+  const uint32_t w1 = sbits[(p >> 5) + 1];
+  return __builtin_amdgcn_alignbit(w1, w0, (uint32_t)(p & 31));
 }
 
 // Expand 8 bits into 8 16-bit +-1 values (bit 1 -> sign set). ONE is the
@@ -201,15 +345,25 @@ __device__ __forceinline__ u32x4 expand16(uint32_t x) {
 template <int MODE> struct Win { u32x4 f; };
 template <> struct Win<MODE_F32> { uint32_t f; };
 
+// 16-bit modes read the expanded fragment of an 8-bit window from a 256-entry
+// LDS table (4 KiB, filled once per workgroup by fill_lut).
 template <int MODE, int IN>
-__device__ __forceinline__ void make_window(Win<MODE> &w, uint32_t bits8) {
+__device__ __forceinline__ void make_window(Win<MODE> &w, uint32_t bits8, const uint32_t *lut) {
   if constexpr (MODE == MODE_F32) {
     w.f = bits8;
-  } else if constexpr (IN == IN_F16) {
-    w.f = expand16<0x3C003C00u>(bits8);
   } else {
-    w.f = expand16<0x3F803F80u>(bits8);
+    w.f = *(const u32x4 *)(lut + 4 * bits8);
   }
+}
+
+constexpr int kLutDw = 256 * 4;
+
+template <int IN>
+__device__ __forceinline__ void fill_lut(uint32_t *lut) {
+  const int e = threadIdx.x;  // kThreads == 256 entries
+  const u32x4 v = (IN == IN_F16) ? expand16<0x3C003C00u>((uint32_t)e)
+                                 : expand16<0x3F803F80u>((uint32_t)e);
+  *(u32x4 *)(lut + 4 * e) = v;
 }
 
 __device__ __forceinline__ int pos_mod(int a, int n) {
@@ -220,12 +374,27 @@ __device__ __forceinline__ int pos_mod(int a, int n) {
 // ---------------------------------------------------------------------------
 // The tiled kernel.
 // ---------------------------------------------------------------------------
-// Prefetch depth (register sets of in-flight stage data) per mode: deep for
-// the HBM-bound 16-bit modes, 2 where registers are scarce.
-template <int MODE, int NC> struct Prefetch { static constexpr int value = 2; };
-template <> struct Prefetch<MODE_BF16, 4> { static constexpr int value = 4; };
-template <> struct Prefetch<MODE_BF16, 2> { static constexpr int value = 4; };
-template <> struct Prefetch<MODE_BF16, 1> { static constexpr int value = 4; };
+// Global->LDS load depth (chunks in flight) per mode: deep for the
+// HBM-bound bf16 mode, shallower where the stage itself is large.
+template <int MODE> struct DmaDepth { static constexpr int value = 4; };
+template <> struct DmaDepth<MODE_BF16> { static constexpr int value = 2; };
+template <> struct DmaDepth<MODE_F32S> { static constexpr int value = 3; };
+
+// LDS dwords of one workgroup tile: bit stream + two stages (+ ring).
+template <int MODE, int IN>
+constexpr int tile_lds_dwords(int nbw_pad) {
+  return nbw_pad + kLutDw + 2 * stage_dwords<MODE>() +
+         (IN == IN_C64 ? (DmaDepth<MODE>::value + 1) * ring_dwords<StageGeom<MODE>::ch>() : 0);
+}
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 // One workgroup tile of the contraction: 32 antennas from a0, 4 waves x
 // 32*NC output columns from colg, of one frame whose rows start at `in`
@@ -240,16 +409,26 @@ struct Tile {
   float alpha, beta;
 };
 
-template <int MODE, int IN, int NC>
-__device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits, uint32_t *stage) {
+template <int MODE, int IN, int NC, bool AL>
+__device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
+                                         const uint32_t *lut, uint32_t *stage) {
   constexpr int NWIN = 2 * NC;
   constexpr int RS = StageGeom<MODE>::rs;
   constexpr int PS = kRows * RS;
   constexpr int SDW = stage_dwords<MODE>();
-  constexpr int PF = Prefetch<MODE, NC>::value;
-  constexpr int CPB = (NWIN / 2 > PF) ? NWIN / 2 : PF;  // chunks per unrolled body
-  static_assert(CPB % PF == 0 && CPB % (NWIN / 2) == 0, "body must cover both rotations");
-  using Raw = typename std::conditional<IN == IN_C64, RawC64, RawPacked>::type;
+  constexpr int CH = StageGeom<MODE>::ch;    // samples per stage
+  constexpr int KS = CH / 16;                // k-steps per stage
+  constexpr bool DMA = IN == IN_C64;
+  constexpr int LPC = CH / 16;               // DMA loads per wave and chunk
+  // Chunks in flight: DMA depth (complex64) or register sets (packed).
+  constexpr int PF = DMA ? DmaDepth<MODE>::value : (CH == 64 ? 2 : 4);
+  constexpr int RING = PF + 1;
+  constexpr int RDW = ring_dwords<CH>();
+  // Chunks per unrolled body: the window rotation (NWIN k-steps) and, for
+  // register sets, the set rotation (PF) both repeat after CPB chunks.
+  constexpr int CPW = (NWIN > KS) ? NWIN / KS : 1;
+  constexpr int CPB = DMA ? CPW : ((CPW > PF) ? CPW : PF);
+  static_assert((CPB * KS) % NWIN == 0 && (DMA || CPB % PF == 0), "body must cover rotations");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -259,24 +438,58 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits, 
   const int a0 = tl.a0;
   const int col0 = tl.colg + wave * 32 * NC;
 
-  const int nchunks = (tl.t_len + kChunk - 1) / kChunk;
-  auto load_chunk = [&](Raw &r, int chunk) {
-    if constexpr (IN == IN_C64) {
-      load_stage(r, (const float *)tl.in, tl.R, a0, tl.ld_in, tl.t_len, chunk * kChunk, tid);
+  const int nchunks = (tl.t_len + CH - 1) / CH;
+  const int last = nchunks - 1;
+  // complex64: global -> LDS ring (PF chunks ahead) -> converted LDS stage;
+  // packed: global -> registers (PF chunks ahead) -> LDS stage.
+  uint32_t *ring = stage + 2 * SDW;
+  const float *fin = (const float *)tl.in;
+  RawPacked<CH> raw[DMA ? 1 : PF];
+  // This thread's c64 sample pairs of chunk 0 (rows past R clamped to 0).
+  const float *src[LPC];
+#pragma unroll
+  for (int j = 0; j < LPC; ++j) {
+    const int q = dma_pair<CH>(wave, j, lane);
+    const int a = a0 + q / (CH / 2);
+    src[j] = fin + ((size_t)(a < tl.R ? a : 0) * tl.ld_in + 2 * (q % (CH / 2))) * 2;
+  }
+  // chunk -> ring slot `slot` (complex64) or register set ISET (packed)
+  auto fetch = [&](int chunk, int slot, auto iset) {
+    constexpr int S = decltype(iset)::value;
+    const int c = chunk < last ? chunk : last;  // past the end: re-read the last chunk
+    if constexpr (DMA) {
+      if (c < last)
+        dma_chunk_fast<CH>(ring + slot * RDW, src, c * CH, wave);
+      else
+        dma_chunk<CH>(ring + slot * RDW, fin, tl.R, a0, tl.ld_in, tl.t_len, c * CH, wave, lane);
     } else {
-      load_stage(r, (const uint16_t *)tl.in, tl.R, a0, tl.ld_in, tl.t_len, chunk * kChunk, tid);
+      load_stage<AL>(raw[S], (const uint16_t *)tl.in, tl.R, a0, tl.ld_in, tl.t_len, c * CH,
+                     tid);
     }
   };
+  // stage chunk `chunk` from ring slot `slot` / register set ISET into st
+  auto land = [&](int chunk, int slot, auto iset, uint32_t *st) {
+    constexpr int S = decltype(iset)::value;
+    if constexpr (DMA) {
+      if (chunk < last)
+        convert_chunk_fast<MODE, CH>(st, ring + slot * RDW, wave, lane);
+      else
+        convert_chunk<MODE, CH>(st, ring + slot * RDW, tl.R, a0, tl.ld_in, tl.t_len, chunk * CH,
+                                wave, lane);
+    } else {
+      store_stage<MODE>(st, raw[S], tid);
+    }
+  };
+  using I0 = std::integral_constant<int, 0>;
 
-  // Pipeline: chunk j travels global -> raw[j % PF] (issued PF chunks ahead)
-  // -> LDS stage (j & 1), converted -> matrix-core fragments.
-  Raw raw[PF];
-#pragma unroll
-  for (int j = 0; j < PF; ++j)
-    if (j < nchunks) load_chunk(raw[j], j);
-  store_stage<MODE>(stage, raw[0], tid);
-  if (PF < nchunks) load_chunk(raw[0], PF);
-  __syncthreads();
+  static_for<0, PF>([&](auto ij) { fetch(decltype(ij)::value, decltype(ij)::value, ij); });
+  if constexpr (DMA) wait_vm<LPC * (PF - 1)>();
+  land(0, 0, I0{}, stage);
+  fetch(PF, PF % RING, I0{});
+  if constexpr (DMA)
+    bar_lds();
+  else
+    __syncthreads();
 
   // Bit position of this lane's B fragment for block 0 at k-step 0:
   // reduction index t0 = 8h (+ e), output column col0 + m.
@@ -288,7 +501,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits, 
 #pragma unroll
   for (int j = 1; j <= NWIN - 2; ++j) {
     const int p = pos_mod(p_base - 16 * j, tl.N);
-    make_window<MODE, IN>(win[NWIN - j], window8(sbits, p));
+    make_window<MODE, IN>(win[NWIN - j], window8(sbits, p), lut);
   }
 
   f32x16 acc_re[NC], acc_im[NC];
@@ -301,79 +514,94 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits, 
     }
   }
 
-  const int nbodies = (nchunks + CPB - 1) / CPB;
-  for (int body = 0; body < nbodies; ++body) {
-#pragma unroll
-    for (int cc = 0; cc < CPB; ++cc) {
-      const int chunk = body * CPB + cc;
-      if (chunk < nchunks) {
-        const uint32_t *st = stage + (chunk & 1) * SDW;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int q = (2 * cc + u) % NWIN;  // slot of k-step i = 2*chunk + u
-          const int i = 2 * chunk + u;
-          make_window<MODE, IN>(win[q], window8(sbits, p_base + 16 * i));
-          if constexpr (MODE == MODE_F32) {
-            const float *pre = (const float *)st + m * RS + 16 * u + 8 * h;
-            const float *pim = pre + PS;
-            f32x4 r0 = *(const f32x4 *)pre, r1 = *(const f32x4 *)(pre + 4);
-            f32x4 i0 = *(const f32x4 *)pim, i1 = *(const f32x4 *)(pim + 4);
-            float are[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-            float aim[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-#pragma unroll
-              for (int c = 0; c < NC; ++c) {
-                const uint32_t x = win[(q - 2 * c + NWIN) % NWIN].f;
-                const float bv =
-                    __builtin_bit_cast(float, 0x3F800000u | ((x << (31 - j)) & 0x80000000u));
-                acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[j], bv, acc_re[c], 0, 0, 0);
-                acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[j], bv, acc_im[c], 0, 0, 0);
-              }
+  // One chunk of matrix-core work from LDS stage (chunk & 1); cc is the
+  // chunk's position in the unrolled body, which fixes the window slots.
+  auto do_chunk = [&](auto icc, int chunk) {
+    constexpr int cc = decltype(icc)::value;
+      const uint32_t *st = stage + (chunk & 1) * SDW;
+  #pragma unroll
+      for (int u = 0; u < KS; ++u) {
+        const int q = (KS * cc + u) % NWIN;  // slot of k-step i = KS*chunk + u
+        const int i = KS * chunk + u;
+        make_window<MODE, IN>(win[q], window8(sbits, p_base + 16 * i), lut);
+        if constexpr (MODE == MODE_F32) {
+          const float *pre = (const float *)st + m * RS + 16 * u + 8 * h;
+          const float *pim = pre + PS;
+          f32x4 r0 = *(const f32x4 *)pre, r1 = *(const f32x4 *)(pre + 4);
+          f32x4 i0 = *(const f32x4 *)pim, i1 = *(const f32x4 *)(pim + 4);
+          float are[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+          float aim[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
+  #pragma unroll
+          for (int j = 0; j < 8; ++j) {
+  #pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              const uint32_t x = win[(q - 2 * c + NWIN) % NWIN].f;
+              const float bv =
+                  __builtin_bit_cast(float, 0x3F800000u | ((x << (31 - j)) & 0x80000000u));
+              acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[j], bv, acc_re[c], 0, 0, 0);
+              acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[j], bv, acc_im[c], 0, 0, 0);
             }
-          } else {
-            constexpr int NP = (MODE == MODE_F32S) ? 3 : 1;
-            u32x4 are[NP], aim[NP];
-#pragma unroll
-            for (int s = 0; s < NP; ++s) {
-              are[s] = *(const u32x4 *)(st + s * PS + m * RS + 8 * u + 4 * h);
-              aim[s] = *(const u32x4 *)(st + (NP + s) * PS + m * RS + 8 * u + 4 * h);
-            }
-            // split part outer, lag block inner: the dependent updates of one
-            // accumulator are 2*NC matrix-core ops apart
-#pragma unroll
-            for (int s = 0; s < NP; ++s) {
-#pragma unroll
-              for (int c = 0; c < NC; ++c) {
-                const u32x4 bw = win[(q - 2 * c + NWIN) % NWIN].f;
-                if constexpr (IN == IN_F16) {
-                  acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                      __builtin_bit_cast(f16x8, are[s]), __builtin_bit_cast(f16x8, bw),
-                      acc_re[c], 0, 0, 0);
-                  acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                      __builtin_bit_cast(f16x8, aim[s]), __builtin_bit_cast(f16x8, bw),
-                      acc_im[c], 0, 0, 0);
-                } else {
-                  acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                      __builtin_bit_cast(bf16x8, are[s]), __builtin_bit_cast(bf16x8, bw),
-                      acc_re[c], 0, 0, 0);
-                  acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                      __builtin_bit_cast(bf16x8, aim[s]), __builtin_bit_cast(bf16x8, bw),
-                      acc_im[c], 0, 0, 0);
-                }
+          }
+        } else {
+          constexpr int NP = (MODE == MODE_F32S) ? 3 : 1;
+          u32x4 are[NP], aim[NP];
+  #pragma unroll
+          for (int s = 0; s < NP; ++s) {
+            are[s] = *(const u32x4 *)(st + s * PS + m * RS + 8 * u + 4 * h);
+            aim[s] = *(const u32x4 *)(st + (NP + s) * PS + m * RS + 8 * u + 4 * h);
+          }
+          // split part outer, lag block inner: the dependent updates of one
+          // accumulator are 2*NC matrix-core ops apart
+  #pragma unroll
+          for (int s = 0; s < NP; ++s) {
+  #pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              const u32x4 bw = win[(q - 2 * c + NWIN) % NWIN].f;
+              if constexpr (IN == IN_F16) {
+                acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                    __builtin_bit_cast(f16x8, are[s]), __builtin_bit_cast(f16x8, bw),
+                    acc_re[c], 0, 0, 0);
+                acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                    __builtin_bit_cast(f16x8, aim[s]), __builtin_bit_cast(f16x8, bw),
+                    acc_im[c], 0, 0, 0);
+              } else {
+                acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, are[s]), __builtin_bit_cast(bf16x8, bw),
+                    acc_re[c], 0, 0, 0);
+                acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, aim[s]), __builtin_bit_cast(bf16x8, bw),
+                    acc_im[c], 0, 0, 0);
               }
             }
           }
         }
-        if (chunk + 1 < nchunks) {
-          // chunk + 1 arrived in raw[(chunk + 1) % PF]; refill that set.
-          store_stage<MODE>(stage + ((chunk + 1) & 1) * SDW, raw[(cc + 1) % PF], tid);
-          if (chunk + 1 + PF < nchunks) load_chunk(raw[(cc + 1) % PF], chunk + 1 + PF);
-        }
-        __syncthreads();
       }
-    }
+  };
+
+  // Chunk c: matrix-core work on stage (c & 1); then chunk c + 1, fetched PF
+  // chunks ago into set (c + 1), is staged, set (c + 1) is refilled with
+  // chunk c + 1 + PF, and one barrier publishes the stage. DMA waits count
+  // this wave's loads: LPC per chunk, the PF - 1 younger chunks may remain.
+  const int nbodies = (nchunks + CPB - 1) / CPB;
+  for (int body = 0; body < nbodies; ++body) {
+    static_for<0, CPB>([&](auto icc) {
+      constexpr int cc = decltype(icc)::value;
+      const int chunk = body * CPB + cc;
+      if (chunk < nchunks) {
+        do_chunk(icc, chunk);
+        using IS = std::integral_constant<int, (cc + 1) % PF>;  // set of chunk + 1
+        if constexpr (DMA) wait_vm<LPC * (PF - 1)>();
+        if (chunk + 1 < nchunks)
+          land(chunk + 1, (chunk + 1) % RING, IS{}, stage + ((chunk + 1) & 1) * SDW);
+        fetch(chunk + 1 + PF, (chunk + 1 + PF) % RING, IS{});
+        if constexpr (DMA)
+          bar_lds();
+        else
+          __syncthreads();
+      }
+    });
   }
+  if constexpr (DMA) wait_vm<0>();  // no global->LDS load outlives the tile
 
   // Epilogue: lane (m, h) holds, for block c, output column col0 + 32c + m
   // and rows 8*(v/4) + 4*h + (v%4) of the 32x32 accumulator.
@@ -403,7 +631,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits, 
 
 
 // One tile per workgroup over a uniform batch.
-template <int MODE, int IN, int NC>
+template <int MODE, int IN, int NC, bool AL>
 __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, int tiles_c,
                                                          int nbw_pad) {
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
@@ -419,6 +647,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
   const int b = rest / tiles_r;
 
   for (int i = threadIdx.x; i < a.nbw; i += kThreads) smem[i] = a.bits[i];
+  fill_lut<IN>(smem + nbw_pad);
   Tile tl;
   if constexpr (IN == IN_C64)
     tl.in = (const float *)a.in + (size_t)b * a.R * a.ld_in * 2;
@@ -436,7 +665,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
   tl.colg = cg * (kWaves * 32 * NC);
   tl.alpha = a.alpha * (a.scales ? a.scales[b] : 1.0f);
   tl.beta = a.beta;
-  run_tile<MODE, IN, NC>(tl, smem, smem + nbw_pad);
+  run_tile<MODE, IN, NC, AL>(tl, smem, smem + nbw_pad, smem + nbw_pad + kLutDw);
 }
 
 // Persistent kernel over an uneven batch: workgroup w walks its slice of a
@@ -448,7 +677,9 @@ template <int MODE, int IN>
 __global__ __launch_bounds__(kThreads, 2) void varlen_kernel(VArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
   const int nbw_pad = (a.nbw_max + 3) & ~3;
-  uint32_t *stage = smem + nbw_pad;
+  const uint32_t *lut = smem + nbw_pad;
+  uint32_t *stage = smem + nbw_pad + kLutDw;
+  fill_lut<IN>(smem + nbw_pad);
   int cur_bits = -1;
   const int end = a.wg_start[blockIdx.x + 1];
   for (int i = a.wg_start[blockIdx.x]; i < end; ++i) {
@@ -472,19 +703,23 @@ __global__ __launch_bounds__(kThreads, 2) void varlen_kernel(VArgs a) {
     tl.colg = vt.colg;
     tl.alpha = (a.scales ? a.scales[vt.frame] : 1.0f) / (float)f.N;
     tl.beta = 0.0f;
-    if (vt.nc == 4)
-      run_tile<MODE, IN, 4>(tl, smem, stage);
-    else if (vt.nc == 2)
-      run_tile<MODE, IN, 2>(tl, smem, stage);
-    else
-      run_tile<MODE, IN, 1>(tl, smem, stage);
+    if (f.N >= 7) {  // N + 1 = 2^d, d >= 3: rows 8-code aligned
+      if (vt.nc == 4)
+        run_tile<MODE, IN, 4, true>(tl, smem, lut, stage);
+      else if (vt.nc == 2)
+        run_tile<MODE, IN, 2, true>(tl, smem, lut, stage);
+      else
+        run_tile<MODE, IN, 1, true>(tl, smem, lut, stage);
+    } else {
+      run_tile<MODE, IN, 1, false>(tl, smem, lut, stage);
+    }
   }
 }
 
 hipError_t launch_varlen(int in_fmt, const VArgs &a, int n_wg, hipStream_t s) {
   if (n_wg <= 0) return hipErrorInvalidValue;
   const int nbw_pad = (a.nbw_max + 3) & ~3;
-  const size_t lds = (size_t)(nbw_pad + 2 * stage_dwords<MODE_BF16>()) * 4;
+  const size_t lds = (size_t)tile_lds_dwords<MODE_BF16, IN_BF16>(nbw_pad) * 4;
   if (in_fmt == IN_BF16) {
     if (lds > 64 * 1024) {
       hipError_t e = hipFuncSetAttribute((const void *)varlen_kernel<MODE_BF16, IN_BF16>,
@@ -508,6 +743,159 @@ hipError_t launch_varlen(int in_fmt, const VArgs &a, int n_wg, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// FP64-accumulating contraction on FP64 matrix cores (v_mfma_f64_16x16x4_f64)
+// for complex64 rows: the last residual of least-squares refinement. Inputs
+// are FP32, products with +-1 are exact in FP64 and every sum is FP64; the
+// result is rounded to FP32 once.
+// Tile: 32 antennas (two 16-row blocks) x 4 waves x 16*NB columns; the
+// input is staged through LDS in 32-term chunks as FP32 planes (the MODE_F32
+// stage layout). Lane (j, g) = (lane % 16, lane / 16) supplies reduction
+// index t0 + g for row j (A) and column j (B); the B bit of column block c
+// at k-step i (4 terms) sits at p_base + 4i - 16c.
+// ---------------------------------------------------------------------------
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
+
+template <int NB>
+__global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int tiles_r,
+                                                               int tiles_c, int nbw_pad) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+  constexpr int RS = StageGeom<MODE_F32>::rs;
+  constexpr int PS = kRows * RS;
+  constexpr int SDW = stage_dwords<MODE_F32>();
+  constexpr int PF = 2;
+  uint32_t *sbits = smem;
+  uint32_t *stage = smem + nbw_pad;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int j16 = lane & 15;
+  const int g = lane >> 4;
+
+  const int nt = a.batch * tiles_r * tiles_c;
+  const int bid = blockIdx.x;
+  const int t = (nt % 8 == 0) ? (bid % 8) * (nt / 8) + bid / 8 : bid;
+  const int cg = t % tiles_c;
+  const int rest = t / tiles_c;
+  const int rb = rest % tiles_r;
+  const int b = rest / tiles_r;
+  const int a0 = rb * kRows;
+  const int col0 = cg * (kWaves * 16 * NB) + wave * 16 * NB;
+
+  const float *fin = (const float *)a.in + (size_t)b * a.R * a.ld_in * 2;
+  constexpr int CH = 32;  // 8 k-steps of 4 terms per stage
+  const int nchunks = (a.t_len + CH - 1) / CH;
+  RawC64<CH> raw[PF];
+#pragma unroll
+  for (int c = 0; c < PF; ++c)
+    if (c < nchunks) load_stage(raw[c], fin, a.R, a0, a.ld_in, a.t_len, c * CH, tid);
+  for (int i = tid; i < a.nbw; i += kThreads) sbits[i] = a.bits[i];
+  store_stage<MODE_F32>(stage, raw[0], tid);
+  if (PF < nchunks) load_stage(raw[0], fin, a.R, a0, a.ld_in, a.t_len, PF * CH, tid);
+  __syncthreads();
+
+  const int p_base = pos_mod(g - j16 - col0, a.N);
+  f64x4 acc[2][2][NB];  // [row block][re, im][column block]
+#pragma unroll
+  for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc[r2][ri][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  for (int chunk0 = 0; chunk0 < nchunks; chunk0 += PF) {
+#pragma unroll
+    for (int cc = 0; cc < PF; ++cc) {
+      const int chunk = chunk0 + cc;
+      if (chunk < nchunks) {
+        const float *st = (const float *)(stage + (chunk & 1) * SDW);
+        // 32-bit windows: bits p_base - 16c + 32*chunk + 4j, j = 0..7
+        uint32_t w[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          w[c] = window32(sbits, pos_mod(p_base - 16 * c + 32 * chunk, a.N));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          double av[2][2];
+#pragma unroll
+          for (int r2 = 0; r2 < 2; ++r2) {
+            av[r2][0] = (double)st[(16 * r2 + j16) * RS + 4 * j + g];
+            av[r2][1] = (double)st[PS + (16 * r2 + j16) * RS + 4 * j + g];
+          }
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            const uint64_t bb =
+                (uint64_t)(0x3FF00000u | (((w[c] >> (4 * j)) & 1u) << 31)) << 32;
+            const double bv = __builtin_bit_cast(double, bb);
+#pragma unroll
+            for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+              for (int ri = 0; ri < 2; ++ri)
+                acc[r2][ri][c] =
+                    __builtin_amdgcn_mfma_f64_16x16x4f64(av[r2][ri], bv, acc[r2][ri][c], 0, 0, 0);
+          }
+        }
+        if (chunk + 1 < nchunks) {
+          store_stage<MODE_F32>(stage + ((chunk + 1) & 1) * SDW, raw[(cc + 1) % PF], tid);
+          if (chunk + 1 + PF < nchunks)
+            load_stage(raw[(cc + 1) % PF], fin, a.R, a0, a.ld_in, a.t_len,
+                       (chunk + 1 + PF) * CH, tid);
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // Lane (j, g) holds, per block, column col0 + 16c + j and rows g + 4v (the
+  // FP64 16x16 result interleaves rows across the four lane groups).
+  const double alpha = (double)a.alpha * (a.scales ? (double)a.scales[b] : 1.0);
+  const double beta = (double)a.beta;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int col = col0 + 16 * c + j16;
+    if (col < a.c_len) {
+#pragma unroll
+      for (int r2 = 0; r2 < 2; ++r2) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ant = a0 + 16 * r2 + g + 4 * v;
+          if (ant < a.R) {
+            const size_t o = ((size_t)(b * a.R + ant) * a.ld_out + col) * 2;
+            double re = alpha * acc[r2][0][c][v];
+            double im = alpha * acc[r2][1][c][v];
+            if (beta != 0.0) {
+              const f2a8 old = *(const f2a8 *)(a.cin + o);
+              re += beta * (double)old.x;
+              im += beta * (double)old.y;
+            }
+            *(f2a8 *)(a.out + o) = f2a8{(float)re, (float)im};
+          }
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_f64mm(const TgArgs &a, hipStream_t s) {
+  constexpr int NB = 4;
+  const int tiles_r = (a.R + kRows - 1) / kRows;
+  const int cols_per_tile = kWaves * 16 * NB;
+  const int tiles_c = (a.c_len + cols_per_tile - 1) / cols_per_tile;
+  const long nt = (long)a.batch * tiles_r * tiles_c;
+  if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
+  const int nbw_pad = (a.nbw + 3) & ~3;
+  const size_t lds = (size_t)(nbw_pad + 2 * stage_dwords<MODE_F32>()) * 4;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)tg_f64mm_kernel<NB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((tg_f64mm_kernel<NB>), dim3((unsigned)nt), dim3(kThreads), lds, s, a,
+                     tiles_r, tiles_c, nbw_pad);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // FP8 (OCP e4m3fn) correlator on quantised planes, v_mfma_f32_32x32x64_f8f6f4.
 // Same tiling as tg_kernel; one 64-sample k-step per LDS chunk (32 rows x
 // 2 planes x 64 codes). Lane (m, h) supplies codes n0 + 32h .. +31 of row m
@@ -516,13 +904,6 @@ hipError_t launch_varlen(int in_fmt, const VArgs &a, int n_wg, hipStream_t s) {
 // p_base + 32(2i - c), so two new windows per k-step serve all blocks.
 // ---------------------------------------------------------------------------
 typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8;
-
-// 32 bits of the periodic stream starting at bit p.
-__device__ __forceinline__ uint32_t window32(const uint32_t *sbits, int p) {
-  const uint32_t w0 = sbits[p >> 5];
-  const uint32_t w1 = sbits[(p >> 5) + 1];
-  return __builtin_amdgcn_alignbit(w1, w0, (uint32_t)(p & 31));
-}
 
 // 32 bits -> 32 e4m3 codes of +-1 (bit i -> byte i; 1 -> sign set).
 __device__ __forceinline__ i32x8 expand_e4m3(uint32_t x) {
@@ -699,23 +1080,32 @@ static hipError_t launch_fp8_nc(const TgArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int MODE, int IN, int NC>
-static hipError_t launch_tg_nc(const TgArgs &a, hipStream_t s) {
+template <int MODE, int IN, int NC, bool AL>
+static hipError_t launch_tg_nc_al(const TgArgs &a, hipStream_t s) {
   const int tiles_r = (a.R + kRows - 1) / kRows;
   const int cols_per_tile = kWaves * 32 * NC;
   const int tiles_c = (a.c_len + cols_per_tile - 1) / cols_per_tile;
   const long nt = (long)a.batch * tiles_r * tiles_c;
   if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
   const int nbw_pad = (a.nbw + 3) & ~3;
-  const size_t lds = (size_t)(nbw_pad + 2 * stage_dwords<MODE>()) * 4;
+  const size_t lds = (size_t)tile_lds_dwords<MODE, IN>(nbw_pad) * 4;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)tg_kernel<MODE, IN, NC>,
+    hipError_t e = hipFuncSetAttribute((const void *)tg_kernel<MODE, IN, NC, AL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((tg_kernel<MODE, IN, NC>), dim3((unsigned)nt), dim3(kThreads), lds, s, a,
-                     tiles_r, tiles_c, nbw_pad);
+  hipLaunchKernelGGL((tg_kernel<MODE, IN, NC, AL>), dim3((unsigned)nt), dim3(kThreads), lds, s,
+                     a, tiles_r, tiles_c, nbw_pad);
   return hipGetLastError();
+}
+
+// Packed rows take the branch-free loader when rows are 8-code aligned and
+// the reduction length is a multiple of 8; complex64 rows always do.
+template <int MODE, int IN, int NC>
+static hipError_t launch_tg_nc(const TgArgs &a, hipStream_t s) {
+  if (IN == IN_C64 || ((a.ld_in & 7) == 0 && (a.t_len & 7) == 0))
+    return launch_tg_nc_al<MODE, IN, NC, true>(a, s);
+  return launch_tg_nc_al<MODE, IN, NC, false>(a, s);
 }
 
 template <int MODE, int IN>
