@@ -17,6 +17,7 @@
 //  - Toeplitz reuse: the B fragment of column block c at k-step i equals the
 //    fragment of block 0 at k-step i - 2c, so a wave expands ONE new fragment
 //    per k-step and rotates 2*NC of them through registers.
+#include <algorithm>
 #include <type_traits>
 
 #include "pnce_internal.h"
@@ -1212,35 +1213,58 @@ __device__ float pow2_scale(float m, float target) {
   return ldexpf(1.0f, e);
 }
 
-// One workgroup per frame: max |re|, |im| over R*N samples, then the scale.
-__global__ __launch_bounds__(256) void frame_scale_kernel(const float *y, float *scales,
-                                                          long n_floats, float target) {
-  __shared__ float smax[256];
-  __shared__ int snan[256];
-  const float *f = y + (size_t)blockIdx.x * n_floats;
-  float mx = 0.0f;
-  int nan = 0;
-  for (long i = threadIdx.x; i < n_floats; i += 256) {
-    const float v = fabsf(f[i]);
-    nan |= (v != v);
-    mx = fmaxf(mx, v);
-  }
-  smax[threadIdx.x] = mx;
-  snan[threadIdx.x] = nan;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + s]);
-      snan[threadIdx.x] |= snan[threadIdx.x + s];
+// The frame maximum travels as the bit pattern of |v|: for non-negative
+// floats the unsigned order is the numeric order, and every NaN pattern sits
+// above +inf, so one unsigned max also flags non-finite frames.
+__device__ __forceinline__ float scale_from_maxbits(uint32_t mb, float target) {
+  if (mb == 0u || mb >= 0x7F800000u) return 1.0f;  // zeros, inf or NaN
+  return pow2_scale(__builtin_bit_cast(float, mb), target);
+}
+
+__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Grid (slices, frames): each workgroup reduces one slice of a frame's R*N
+// complex samples and folds it into the frame's word with one atomic max.
+constexpr int kMaxUnroll = 8;
+__global__ __launch_bounds__(256) void frame_max_kernel(const f2a8 *y, uint32_t *maxbits,
+                                                        long per_frame) {
+  const f2a8 *f = y + (size_t)blockIdx.y * per_frame;
+  const long step = (long)gridDim.x * 256;
+  uint32_t m = 0u;
+  for (long i0 = (long)blockIdx.x * 256 + threadIdx.x; i0 < per_frame; i0 += step * kMaxUnroll) {
+    f2a8 v[kMaxUnroll];
+#pragma unroll
+    for (int u = 0; u < kMaxUnroll; ++u) {
+      const long i = i0 + u * step;
+      v[u] = i < per_frame ? f[i] : f2a8{0.0f, 0.0f};
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kMaxUnroll; ++u) {
+      // by-value floats: a bit cast of a vector element lvalue is not safe here
+      const float re = v[u].x, im = v[u].y;
+      m = max(m, __builtin_bit_cast(uint32_t, re) & 0x7FFFFFFFu);
+      m = max(m, __builtin_bit_cast(uint32_t, im) & 0x7FFFFFFFu);
+    }
   }
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
+  __shared__ uint32_t sm[4];
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const float m = smax[0];
-    float sc = 1.0f;
-    if (!snan[0] && m > 0.0f && __builtin_isfinite(m)) sc = pow2_scale(m, target);
-    scales[blockIdx.x] = sc;
+    m = max(max(sm[0], sm[1]), max(sm[2], sm[3]));
+    if (m) atomicMax(maxbits + blockIdx.y, m);
   }
+}
+
+// Max bits -> power-of-two scale, in place, once every pack block has read them.
+__global__ __launch_bounds__(256) void finalize_scale_kernel(float *scales, int batch,
+                                                             float target) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b < batch)
+    scales[b] = scale_from_maxbits(__builtin_bit_cast(uint32_t, scales[b]), target);
 }
 
 // float -> OCP e4m3fn code, round to nearest even, saturating at +-448;
@@ -1263,57 +1287,82 @@ __device__ __forceinline__ uint32_t e4m3_code(float x) {
   return sign | ((uint32_t)(E + 7) << 3) | (q - 8u);
 }
 
-// One thread per (row, sample) of the padded planar output.
+// Four consecutive samples of one padded output row per thread. The padded
+// row length N + 1 is a power of two, so each thread's codes form one aligned
+// 8-byte (16-bit codes) or 4-byte (e4m3) store per plane.
 template <int FMT>
-__global__ __launch_bounds__(256) void pack_kernel(const float *y, void *yq, const float *scales,
-                                                   int R, int N, long total) {
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void pack_kernel(const f2a8 *y, void *yq, const uint32_t *maxbits,
+                                                   int R, int N, float target, long total) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;  // (row, quad)
   if (i >= total) return;
-  const int Np = N + 1;
-  const long row = i / Np;  // frame * R + antenna
-  const int n = (int)(i - row * Np);
+  const int Np = N + 1, nq = Np >> 2;
+  const long row = i / nq;  // frame * R + antenna
+  const int n0 = (int)(i - row * nq) * 4;
   const int b = (int)(row / R);
-  float re = 0.0f, im = 0.0f;
-  if (n < N) {
-    const float inv = 1.0f / scales[b];
-    const f2a8 v = *(const f2a8 *)(y + (row * N + n) * 2);
-    re = v.x * inv;
-    im = v.y * inv;
-  }
-  const size_t o = (size_t)row * 2 * Np + n;
+  const float inv = 1.0f / scale_from_maxbits(maxbits[b], target);
+  f2a8 v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    v[u] = n0 + u < N ? y[row * N + n0 + u] : f2a8{0.0f, 0.0f};
+  const size_t o = (size_t)row * 2 * Np + n0;
   if constexpr (FMT == 3) {
-    uint8_t *q = (uint8_t *)yq;
-    q[o] = (uint8_t)(n < N ? e4m3_code(re) : 0u);
-    q[o + Np] = (uint8_t)(n < N ? e4m3_code(im) : 0u);
-  } else {
-    uint16_t *q = (uint16_t *)yq;
-    if constexpr (FMT == 1) {
-      q[o] = (uint16_t)bf16_bits(re);
-      q[o + Np] = (uint16_t)bf16_bits(im);
-    } else {
-      q[o] = __builtin_bit_cast(uint16_t, (_Float16)re);
-      q[o + Np] = __builtin_bit_cast(uint16_t, (_Float16)im);
+    uint32_t cr = 0u, ci = 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (n0 + u < N) {
+        cr |= e4m3_code(v[u].x * inv) << (8 * u);
+        ci |= e4m3_code(v[u].y * inv) << (8 * u);
+      }
     }
+    uint8_t *q = (uint8_t *)yq;
+    *(uint32_t *)(q + o) = cr;
+    *(uint32_t *)(q + o + Np) = ci;
+  } else {
+    uint64_t cr = 0u, ci = 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (n0 + u < N) {
+        uint32_t r, m;
+        if constexpr (FMT == 1) {
+          r = bf16_bits(v[u].x * inv);
+          m = bf16_bits(v[u].y * inv);
+        } else {
+          r = __builtin_bit_cast(uint16_t, (_Float16)(v[u].x * inv));
+          m = __builtin_bit_cast(uint16_t, (_Float16)(v[u].y * inv));
+        }
+        cr |= (uint64_t)r << (16 * u);
+        ci |= (uint64_t)m << (16 * u);
+      }
+    }
+    uint16_t *q = (uint16_t *)yq;
+    *(uint64_t *)(q + o) = cr;
+    *(uint64_t *)(q + o + Np) = ci;
   }
 }
 
+// scales doubles as the per-frame max word until the last launch turns it
+// into the scale, so the four launches must stay in this order on one stream.
 hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R, int N,
                        int fmt, hipStream_t s) {
+  if (fmt < 1 || fmt > 3) return hipErrorInvalidValue;
   const float target = (fmt == 3) ? 448.0f : 1.0f;
-  hipLaunchKernelGGL(frame_scale_kernel, dim3(batch), dim3(256), 0, s, y, scales,
-                     (long)R * N * 2, target);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const long total = (long)batch * R * (N + 1);
+  uint32_t *mb = (uint32_t *)scales;
+  const f2a8 *yc = (const f2a8 *)y;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, mb, batch);
+  const long per_frame = (long)R * N;
+  const long slices = std::max(1L, std::min(64L, per_frame / (256L * kMaxUnroll)));
+  hipLaunchKernelGGL(frame_max_kernel, dim3((unsigned)slices, (unsigned)batch), dim3(256), 0, s,
+                     yc, mb, per_frame);
+  const long total = (long)batch * R * ((N + 1) >> 2);
   const dim3 grid((unsigned)((total + 255) / 256));
   if (fmt == 1)
-    hipLaunchKernelGGL((pack_kernel<1>), grid, dim3(256), 0, s, y, yq, scales, R, N, total);
+    hipLaunchKernelGGL((pack_kernel<1>), grid, dim3(256), 0, s, yc, yq, mb, R, N, target, total);
   else if (fmt == 2)
-    hipLaunchKernelGGL((pack_kernel<2>), grid, dim3(256), 0, s, y, yq, scales, R, N, total);
-  else if (fmt == 3)
-    hipLaunchKernelGGL((pack_kernel<3>), grid, dim3(256), 0, s, y, yq, scales, R, N, total);
+    hipLaunchKernelGGL((pack_kernel<2>), grid, dim3(256), 0, s, yc, yq, mb, R, N, target, total);
   else
-    return hipErrorInvalidValue;
+    hipLaunchKernelGGL((pack_kernel<3>), grid, dim3(256), 0, s, yc, yq, mb, R, N, target, total);
+  hipLaunchKernelGGL(finalize_scale_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, scales,
+                     batch, target);
   return hipGetLastError();
 }
 

@@ -159,6 +159,29 @@ def test_pack_bit_exact(shape, fmt):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "f16", "e4m3"])
+def test_pack_degenerate_frames(fmt):
+    """An all-zero frame and a frame holding +-inf both get scale 1; the
+    infinity encodes as the format's inf (e4m3: saturates to +-448); a frame
+    whose maximum sits exactly on a power of two keeps that power."""
+    N, T, L, R = 63, 2, 8, 5
+    y = _rand_frames(N, R, 4, 21)
+    y[0] = 0.0
+    y[1, 2, 9] = np.inf
+    y[1, 4, 0] = -np.inf + 1j
+    y[2] *= np.float32(0.49) / max(np.abs(y[2].real).max(), np.abs(y[2].imag).max())
+    y[2, 1, 3] = 0.5
+    y[3, 0, 0] = 1e-30
+    with _plan(N, T, L, R) as p:
+        q, sc = p.pack(dev(y), fmt)
+        q, sc = host(q), host(sc)
+    ref_q, ref_sc = oracle.quantize(y, fmt)
+    assert sc[0] == 1.0 and sc[1] == 1.0
+    assert sc[2] == (0.5 if fmt != "e4m3" else 2.0 ** -9)
+    assert np.array_equal(sc, ref_sc)
+    assert np.array_equal(q.view(ref_q.dtype), ref_q)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "e4m3"])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
 def test_estimate_packed_parity(shape, fmt):
     N, T, L, R, B = shape
