@@ -76,8 +76,9 @@ typedef int pnce_status;
  * state 1,0,...,0; bit 0 sent as +1 and bit 1 as -1) and uploads its bits
  * (a few KiB) to the current device. Synchronous.
  * Errors: plan == NULL or T, L, R <= 0 -> PNCE_E_INVALID; N not 2^d - 1 with
- * 2 <= d <= 16 -> PNCE_E_UNSUPPORTED; T*L > 16*N or R > 65535 ->
- * PNCE_E_INVALID. Warning: T*L > N (Eq. 7's bound N_batch <= floor(N/L)
+ * 2 <= d <= 16, or one frame too large for 32-bit offsets
+ * ((R + 32) * (max(N, T*L) + 1) * 8 >= 2^31) -> PNCE_E_UNSUPPORTED;
+ * T*L > 16*N or R > 65535 -> PNCE_E_INVALID. Warning: T*L > N (Eq. 7's bound N_batch <= floor(N/L)
  * broken) -> PNCE_W_LAG_ALIAS, with a valid plan. On error *plan = NULL.
  */
 pnce_status pnce_create(pnce_plan **plan, int N, int T, int L, int R);
@@ -189,7 +190,8 @@ typedef struct pnce_varlen_plan pnce_varlen_plan;   /* opaque */
  * longest-first. Column width per (N, T*L) class defaults to 128, 64 or 32
  * lags per wave by T*L; pnce_varlen_tune replaces it with measured choices.
  * Synchronous (uploads the tables). Errors: PNCE_E_INVALID for a bad frame,
- * offset or format, PNCE_E_UNSUPPORTED for a bad N. Warning
+ * offset or format, PNCE_E_UNSUPPORTED for a bad N or a frame whose codes
+ * ((R + 32) * 2 * (N + 1) * 2 bytes) reach 2 GiB. Warning
  * PNCE_W_LAG_ALIAS if some frame has T*L > N.
  */
 pnce_status pnce_varlen_create(pnce_varlen_plan **vplan, const pnce_frame_desc *frames,

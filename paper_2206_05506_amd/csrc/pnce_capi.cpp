@@ -180,6 +180,10 @@ pnce_status pnce_create(pnce_plan **plan, int N, int T, int L, int R) {
     if ((long)T * L > 16L * N) return fail(PNCE_E_INVALID, "T*L exceeds 16*N");
     if (R > 65535) return fail(PNCE_E_INVALID, "R exceeds 65535");
     const int K = T * L;
+    // The kernels address one frame (rows of N or K complex64) with 32-bit
+    // byte offsets, including reads up to 32 rows past its end.
+    if (((long long)R + 32) * ((K > N ? K : N) + 1) * 8 >= (1LL << 31))
+      return fail(PNCE_E_UNSUPPORTED, "frame exceeds 2 GiB: (R + 32) * max(N, T*L) too large");
 
     pnce_plan *p = new (std::nothrow) pnce_plan();
     if (!p) return fail(PNCE_E_NOMEM, "host allocation failed");
@@ -190,8 +194,9 @@ pnce_status pnce_create(pnce_plan **plan, int N, int T, int L, int R) {
     p->K = K;
     p->d = d;
     p->seq = make_sequence(d);
-    // Positions read by the kernels stay below N + max(N, K) + 80 bits.
-    const long bits = (long)N + (K > N ? K : N) + 160;
+    // Positions read by the kernels stay below N + max(N, K) + 16 * 16 + 64
+    // bits (the direct kernel runs up to 16 k-steps past the last one).
+    const long bits = (long)N + (K > N ? K : N) + 352;
     p->nbw = (int)((bits + 31) / 32);
     const std::vector<uint32_t> fwd = bit_stream(p->seq, p->nbw, +1);
     const std::vector<uint32_t> rev = bit_stream(p->seq, p->nbw, -1);
@@ -496,6 +501,8 @@ pnce_status pnce_varlen_create(pnce_varlen_plan **vplan, const pnce_frame_desc *
         return fail(PNCE_E_UNSUPPORTED, "frame " + std::to_string(f) + ": N must be 2^d - 1");
       if (d.R <= 0 || d.T <= 0 || d.L <= 0 || d.R > 65535 || (long)d.T * d.L > 16L * d.N)
         return fail(PNCE_E_INVALID, "frame " + std::to_string(f) + ": bad R, T or L");
+      if (((long long)d.R + 32) * 2 * (d.N + 1) * 2 >= (1LL << 31))
+        return fail(PNCE_E_UNSUPPORTED, "frame " + std::to_string(f) + ": exceeds 2 GiB");
       if (d.y_off < 0 || d.h_off < 0 || (d.y_off & 7))
         return fail(PNCE_E_INVALID,
                     "frame " + std::to_string(f) + ": offsets must be >= 0, y_off a multiple of 8");
@@ -520,7 +527,7 @@ pnce_status pnce_varlen_create(pnce_varlen_plan **vplan, const pnce_frame_desc *
       int deg = 0;
       while ((1 << deg) - 1 < kv.first) ++deg;
       const std::vector<signed char> s = make_sequence(deg);
-      const int nbw = (int)(((long)kv.first + std::max(kv.first, kv.second) + 160 + 31) / 32);
+      const int nbw = (int)(((long)kv.first + std::max(kv.first, kv.second) + 352 + 31) / 32);
       const std::vector<uint32_t> w = bit_stream(s, nbw, +1);
       boff[kv.first] = {(int)bits.size(), nbw};
       bits.insert(bits.end(), w.begin(), w.end());

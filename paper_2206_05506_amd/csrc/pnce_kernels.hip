@@ -99,59 +99,64 @@ template <int CH> struct RawPacked {
   u32x4 v[CH / 32];
 };
 
-// Where the 16 bytes of sample pair (row a, samples n, n+1) are read from:
-// a whole pair is read in place; a pair cut by the end of its row (n + 1 ==
-// t_len) is read one sample early and shifted; anything outside the rows
-// reads row 0 and is zeroed. Returns the mode (1 whole, 2 cut, 0 outside)
-// and the in-bounds element offset. Needs t_len >= 2 (the host routes
-// one-term rows to the vector kernel).
-__device__ __forceinline__ uint32_t pair_source(int a, int n, int R, int ld_in, int t_len,
-                                                size_t &off) {
-  const bool row_ok = a < R;
-  const bool full = row_ok && (n + 1 < t_len);
-  const bool cut = row_ok && (n + 1 == t_len);
-  const int na = full ? n : (cut ? n - 1 : 0);
-  const int aa = row_ok ? a : 0;
-  off = ((size_t)aa * ld_in + na) * 2;
-  return full ? 1u : (cut ? 2u : 0u);
+// Complex64 rows come through a raw buffer resource bounded by the frame:
+// reads at or past its end (antennas at or beyond R) return zeros, so every
+// load is unconditional and the compiler can count them exactly (a load in a
+// divergent branch forces it to wait for all outstanding loads). Thread t
+// reads sample pairs q = t + 256 i of a stage (row q / (CH/2), samples
+// 2 (q % (CH/2)) and +1); a wave instruction reads 64 consecutive pairs.
+constexpr int kRsrcFlags = 0x00020000;  // raw buffer, 32-bit dwords
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frame_rsrc(const void *base, long long bytes) {
+  // The descriptor lives in scalar registers: make its parts provably uniform.
+  const uint64_t b = (uint64_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  const int n = __builtin_amdgcn_readfirstlane((int)bytes);
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0, n,
+                                           kRsrcFlags);
 }
 
-__device__ __forceinline__ f32x4 pair_apply(uint32_t md, f32x4 v) {
-  f32x4 x;
-  x.x = md == 1u ? v.x : (md == 2u ? v.z : 0.f);
-  x.y = md == 1u ? v.y : (md == 2u ? v.w : 0.f);
-  x.z = md == 1u ? v.z : 0.f;
-  x.w = md == 1u ? v.w : 0.f;
-  return x;
-}
-
-// c64 rows into registers: pair q = t + 256 i (row q / (CH/2), samples
-// 2 (q % (CH/2)) and +1); each wave instruction reads 64 consecutive pairs.
+// Byte offset of this thread's pair i of a stage at sample 0.
 template <int CH>
-__device__ __forceinline__ void load_stage(RawC64<CH> &raw, const float *in_frame,
-                                           int R, int a0, int ld_in, int t_len,
-                                           int n0, int tid) {
+__device__ __forceinline__ uint32_t pair_voff(int i, int a0, int ld_in, int tid) {
+  const int q = tid + kThreads * i;
+  return ((uint32_t)(a0 + q / (CH / 2)) * (uint32_t)ld_in + 2u * (q % (CH / 2))) * 8u;
+}
+
+template <int CH>
+__device__ __forceinline__ void load_stage(RawC64<CH> &raw, __amdgpu_buffer_rsrc_t rsrc,
+                                           const uint32_t (&voff)[CH / 16], int n0) {
+#pragma unroll
+  for (int i = 0; i < CH / 16; ++i)
+    raw.v[i] = __builtin_bit_cast(
+        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], 8 * n0, 0));
+}
+
+// Pairs cut by the end of the row keep only their valid sample; pairs past it
+// (which read the next row) become zero. Only the last stage needs this.
+template <int CH>
+__device__ __forceinline__ void mask_stage(RawC64<CH> &raw, int n0, int t_len, int tid) {
+  const int n = n0 + 2 * (tid % (CH / 2));
 #pragma unroll
   for (int i = 0; i < CH / 16; ++i) {
-    const int q = tid + kThreads * i;
-    size_t off;
-    const uint32_t md =
-        pair_source(a0 + q / (CH / 2), n0 + 2 * (q % (CH / 2)), R, ld_in, t_len, off);
-    const f4a8 v = *(const f4a8 *)(in_frame + off);
-    raw.v[i] = pair_apply(md, f32x4{v.x, v.y, v.z, v.w});
+    if (n >= t_len) {
+      raw.v[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    } else if (n + 1 >= t_len) {
+      raw.v[i].z = 0.f;
+      raw.v[i].w = 0.f;
+    }
   }
 }
 
 // Packed rows: 32 rows x 2 planes x CH codes in 16-byte pieces; piece
 // q = t + 256 i covers row q / (CH/4), plane (q / (CH/8)) & 1, codes
-// 8 (q % (CH/8)) .. +7.
-// AL: rows are 8-code aligned and t_len is a multiple of 8 (N + 1 = 2^d with
-// d >= 3), so one branch-free 16-byte load per piece is exact; otherwise
-// codes are read one by one.
-template <bool AL, int CH>
-__device__ __forceinline__ void load_stage(RawPacked<CH> &raw, const uint16_t *in_frame,
-                                           int R, int a0, int ld_in, int t_len,
-                                           int n0, int tid) {
+// 8 (q % (CH/8)) .. +7. Rows that are not 8-code aligned, or a t_len that is
+// not a multiple of 8 (N + 1 = 4, d = 2), take this code-by-code loader.
+template <int CH>
+__device__ __forceinline__ void load_stage_codes(RawPacked<CH> &raw, const uint16_t *in_frame,
+                                                 int R, int a0, int ld_in, int t_len, int n0,
+                                                 int tid) {
 #pragma unroll
   for (int i = 0; i < CH / 32; ++i) {
     const int q = tid + kThreads * i;
@@ -159,23 +164,45 @@ __device__ __forceinline__ void load_stage(RawPacked<CH> &raw, const uint16_t *i
     const int plane = (q / (CH / 8)) & 1;
     const int n = n0 + 8 * (q % (CH / 8));
     const int a = a0 + row;
-    if constexpr (AL) {
-      const bool ok = (a < R) && (n < t_len);
-      const int aa = ok ? a : 0;
-      const int nn = ok ? n : 0;
-      const u32x4 v = *(const u32x4 *)(in_frame + ((size_t)aa * 2 + plane) * ld_in + nn);
-      raw.v[i] = ok ? v : u32x4{0u, 0u, 0u, 0u};
-    } else {
-      u32x4 x = {0u, 0u, 0u, 0u};
-      if (a < R) {
-        const uint16_t *p = in_frame + ((size_t)a * 2 + plane) * ld_in + n;
-        uint32_t e[8];
+    u32x4 x = {0u, 0u, 0u, 0u};
+    if (a < R) {
+      const uint16_t *p = in_frame + ((size_t)a * 2 + plane) * ld_in + n;
+      uint32_t e[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) e[j] = (n + j < t_len) ? p[j] : 0u;
-        x = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
-      }
-      raw.v[i] = x;
+      for (int j = 0; j < 8; ++j) e[j] = (n + j < t_len) ? p[j] : 0u;
+      x = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
     }
+    raw.v[i] = x;
+  }
+}
+
+// Aligned packed rows (8-code aligned, t_len a multiple of 8) through the
+// frame-bounded buffer resource: piece q = t + 256 i at byte offset
+// ((a0 + row) * 2 + plane) * ld_in * 2 + 16 * (q % (CH/8)) + 2 * n0.
+template <int CH>
+__device__ __forceinline__ uint32_t piece_voff(int i, int a0, int ld_in, int tid) {
+  const int q = tid + kThreads * i;
+  const int row = q / (CH / 4);
+  const int plane = (q / (CH / 8)) & 1;
+  return ((uint32_t)((a0 + row) * 2 + plane) * (uint32_t)ld_in) * 2u + 16u * (q % (CH / 8));
+}
+
+template <int CH>
+__device__ __forceinline__ void load_stage(RawPacked<CH> &raw, __amdgpu_buffer_rsrc_t rsrc,
+                                           const uint32_t (&voff)[CH / 16], int n0) {
+#pragma unroll
+  for (int i = 0; i < CH / 32; ++i)
+    raw.v[i] = __builtin_bit_cast(
+        u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], 2 * n0, 0));
+}
+
+// Pieces at or past t_len (they read the next plane) become zero.
+template <int CH>
+__device__ __forceinline__ void mask_stage(RawPacked<CH> &raw, int n0, int t_len, int tid) {
+#pragma unroll
+  for (int i = 0; i < CH / 32; ++i) {
+    const int q = tid + kThreads * i;
+    if (n0 + 8 * (q % (CH / 8)) >= t_len) raw.v[i] = u32x4{0u, 0u, 0u, 0u};
   }
 }
 
@@ -213,94 +240,6 @@ __device__ __forceinline__ void store_stage(uint32_t *st, const RawC64<CH> &raw,
     const int q = tid + kThreads * i;
     store_pair<MODE>(st, q / (CH / 2), q % (CH / 2), raw.v[i]);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Complex64 input through LDS by direct global->LDS loads (the pipeline of
-// the tiled kernel). Each wave issues two global_load_lds_dwordx4 per chunk:
-// lane i of wave w, load j fetches sample pair Q = 128w + 64j + i (row Q >> 4,
-// pair Q & 15) into ring bytes 16Q. A wave later converts exactly the pairs
-// it fetched, so only its own outstanding-load count matters (vmcnt), and no
-// register holds in-flight data. The compiler does not track these loads,
-// so waits are explicit; barriers are bare s_barrier with LDS waits.
-// ---------------------------------------------------------------------------
-// Ring slot of one CH-sample chunk: 32 rows x CH samples x 8 bytes.
-template <int CH> constexpr int ring_dwords() { return kRows * CH * 2; }
-
-// DMA mapping: wave w, load j (j < CH/16), lane i fetches pair
-// q = 64 (CH/16) w + 64 j + i (row q / (CH/2), pair q % (CH/2)) to bytes 16q.
-template <int CH>
-__device__ __forceinline__ int dma_pair(int wave, int j, int lane) {
-  return 64 * (CH / 16) * wave + 64 * j + lane;
-}
-
-template <int CH>
-__device__ __forceinline__ void dma_chunk(uint32_t *slot, const float *in_frame, int R, int a0,
-                                          int ld_in, int t_len, int n0, int wave, int lane) {
-#pragma unroll
-  for (int j = 0; j < CH / 16; ++j) {
-    const int q = dma_pair<CH>(wave, j, lane);
-    size_t off;
-    (void)pair_source(a0 + q / (CH / 2), n0 + 2 * (q % (CH / 2)), R, ld_in, t_len, off);
-    __builtin_amdgcn_global_load_lds(
-        (const void *)(in_frame + off),
-        (__attribute__((address_space(3))) void *)(slot + 4 * dma_pair<CH>(wave, j, 0)), 16, 0,
-        0);
-  }
-}
-
-template <int MODE, int CH>
-__device__ __forceinline__ void convert_chunk(uint32_t *st, const uint32_t *slot, int R, int a0,
-                                              int ld_in, int t_len, int n0, int wave, int lane) {
-#pragma unroll
-  for (int j = 0; j < CH / 16; ++j) {
-    const int q = dma_pair<CH>(wave, j, lane);
-    size_t off;
-    const uint32_t md =
-        pair_source(a0 + q / (CH / 2), n0 + 2 * (q % (CH / 2)), R, ld_in, t_len, off);
-    const f32x4 v = *(const f32x4 *)(slot + 4 * q);
-    store_pair<MODE>(st, q / (CH / 2), q % (CH / 2), pair_apply(md, v));
-  }
-}
-
-// Steady-state chunks (every chunk but the last) need no masking: the pair
-// lies inside its row, and rows at or beyond R were clamped to row 0 once
-// per tile (their outputs are never stored).
-template <int CH>
-__device__ __forceinline__ void dma_chunk_fast(uint32_t *slot, const float *const *src, int n0,
-                                               int wave) {
-#pragma unroll
-  for (int j = 0; j < CH / 16; ++j)
-    __builtin_amdgcn_global_load_lds(
-        (const void *)(src[j] + 2 * n0),
-        (__attribute__((address_space(3))) void *)(slot + 4 * dma_pair<CH>(wave, j, 0)), 16, 0,
-        0);
-}
-
-template <int MODE, int CH>
-__device__ __forceinline__ void convert_chunk_fast(uint32_t *st, const uint32_t *slot, int wave,
-                                                   int lane) {
-#pragma unroll
-  for (int j = 0; j < CH / 16; ++j) {
-    const int q = dma_pair<CH>(wave, j, lane);
-    store_pair<MODE>(st, q / (CH / 2), q % (CH / 2), *(const f32x4 *)(slot + 4 * q));
-  }
-}
-
-// s_waitcnt with only one counter constrained (gfx9 encoding).
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
-}
-__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
-
-// Workgroup barrier that does not drain outstanding global->LDS loads.
-__device__ __forceinline__ void bar_lds() {
-  wait_lds();
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
 }
 
 template <int MODE, int CH>
@@ -377,15 +316,16 @@ __device__ __forceinline__ int pos_mod(int a, int n) {
 // ---------------------------------------------------------------------------
 // Global->LDS load depth (chunks in flight) per mode: deep for the
 // HBM-bound bf16 mode, shallower where the stage itself is large.
-template <int MODE> struct DmaDepth { static constexpr int value = 4; };
-template <> struct DmaDepth<MODE_BF16> { static constexpr int value = 2; };
-template <> struct DmaDepth<MODE_F32S> { static constexpr int value = 3; };
+// Stages in flight (register sets) per mode and input: 32 KiB of complex64
+// per workgroup for every mode; packed input stages are half as large.
+template <int MODE, int IN> struct RegDepth {
+  static constexpr int value = StageGeom<MODE>::ch == 64 ? 2 : 4;
+};
 
-// LDS dwords of one workgroup tile: bit stream + two stages (+ ring).
+// LDS dwords of one workgroup tile: bit stream + window table + two stages.
 template <int MODE, int IN>
 constexpr int tile_lds_dwords(int nbw_pad) {
-  return nbw_pad + kLutDw + 2 * stage_dwords<MODE>() +
-         (IN == IN_C64 ? (DmaDepth<MODE>::value + 1) * ring_dwords<StageGeom<MODE>::ch>() : 0);
+  return nbw_pad + kLutDw + 2 * stage_dwords<MODE>();
 }
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
@@ -419,17 +359,13 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   constexpr int SDW = stage_dwords<MODE>();
   constexpr int CH = StageGeom<MODE>::ch;    // samples per stage
   constexpr int KS = CH / 16;                // k-steps per stage
-  constexpr bool DMA = IN == IN_C64;
-  constexpr int LPC = CH / 16;               // DMA loads per wave and chunk
-  // Chunks in flight: DMA depth (complex64) or register sets (packed).
-  constexpr int PF = DMA ? DmaDepth<MODE>::value : (CH == 64 ? 2 : 4);
-  constexpr int RING = PF + 1;
-  constexpr int RDW = ring_dwords<CH>();
-  // Chunks per unrolled body: the window rotation (NWIN k-steps) and, for
-  // register sets, the set rotation (PF) both repeat after CPB chunks.
+  constexpr bool C64 = IN == IN_C64;
+  constexpr int PF = RegDepth<MODE, IN>::value;  // stages in flight
+  // Chunks per unrolled body: the window rotation (NWIN k-steps) and the
+  // register-set rotation (PF) both repeat after CPB chunks.
   constexpr int CPW = (NWIN > KS) ? NWIN / KS : 1;
-  constexpr int CPB = DMA ? CPW : ((CPW > PF) ? CPW : PF);
-  static_assert((CPB * KS) % NWIN == 0 && (DMA || CPB % PF == 0), "body must cover rotations");
+  constexpr int CPB = (CPW > PF) ? CPW : PF;
+  static_assert((CPB * KS) % NWIN == 0 && CPB % PF == 0, "body must cover rotations");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -441,56 +377,42 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
 
   const int nchunks = (tl.t_len + CH - 1) / CH;
   const int last = nchunks - 1;
-  // complex64: global -> LDS ring (PF chunks ahead) -> converted LDS stage;
-  // packed: global -> registers (PF chunks ahead) -> LDS stage.
-  uint32_t *ring = stage + 2 * SDW;
-  const float *fin = (const float *)tl.in;
-  RawPacked<CH> raw[DMA ? 1 : PF];
-  // This thread's c64 sample pairs of chunk 0 (rows past R clamped to 0).
-  const float *src[LPC];
+  // global -> registers (PF chunks ahead) -> LDS stage in operand format.
+  using Raw = std::conditional_t<C64, RawC64<CH>, RawPacked<CH>>;
+  Raw raw[PF];
+  // complex64 and aligned packed rows: unconditional loads through the
+  // frame-bounded buffer resource, masked once in the last chunk.
+  constexpr bool BUF = C64 || AL;
+  const __amdgpu_buffer_rsrc_t rsrc =
+      frame_rsrc(tl.in, C64 ? (long long)tl.R * tl.ld_in * 8 : (long long)tl.R * tl.ld_in * 4);
+  uint32_t voff[CH / 16] = {};
 #pragma unroll
-  for (int j = 0; j < LPC; ++j) {
-    const int q = dma_pair<CH>(wave, j, lane);
-    const int a = a0 + q / (CH / 2);
-    src[j] = fin + ((size_t)(a < tl.R ? a : 0) * tl.ld_in + 2 * (q % (CH / 2))) * 2;
-  }
-  // chunk -> ring slot `slot` (complex64) or register set ISET (packed)
-  auto fetch = [&](int chunk, int slot, auto iset) {
+  for (int i = 0; i < CH / 16; ++i)
+    voff[i] = C64 ? pair_voff<CH>(i, a0, tl.ld_in, tid) : piece_voff<CH>(i, a0, tl.ld_in, tid);
+  // chunk -> register set ISET; past the end: re-read the last chunk
+  auto fetch = [&](int chunk, auto iset) {
     constexpr int S = decltype(iset)::value;
-    const int c = chunk < last ? chunk : last;  // past the end: re-read the last chunk
-    if constexpr (DMA) {
-      if (c < last)
-        dma_chunk_fast<CH>(ring + slot * RDW, src, c * CH, wave);
-      else
-        dma_chunk<CH>(ring + slot * RDW, fin, tl.R, a0, tl.ld_in, tl.t_len, c * CH, wave, lane);
-    } else {
-      load_stage<AL>(raw[S], (const uint16_t *)tl.in, tl.R, a0, tl.ld_in, tl.t_len, c * CH,
-                     tid);
-    }
+    const int c = chunk < last ? chunk : last;
+    if constexpr (BUF)
+      load_stage<CH>(raw[S], rsrc, voff, c * CH);
+    else
+      load_stage_codes<CH>(raw[S], (const uint16_t *)tl.in, tl.R, a0, tl.ld_in, tl.t_len,
+                           c * CH, tid);
   };
-  // stage chunk `chunk` from ring slot `slot` / register set ISET into st
-  auto land = [&](int chunk, int slot, auto iset, uint32_t *st) {
+  // register set ISET (holding `chunk`) -> LDS stage st
+  auto land = [&](int chunk, auto iset, uint32_t *st) {
     constexpr int S = decltype(iset)::value;
-    if constexpr (DMA) {
-      if (chunk < last)
-        convert_chunk_fast<MODE, CH>(st, ring + slot * RDW, wave, lane);
-      else
-        convert_chunk<MODE, CH>(st, ring + slot * RDW, tl.R, a0, tl.ld_in, tl.t_len, chunk * CH,
-                                wave, lane);
-    } else {
-      store_stage<MODE>(st, raw[S], tid);
+    if constexpr (BUF) {
+      if (chunk == last) mask_stage<CH>(raw[S], chunk * CH, tl.t_len, tid);
     }
+    store_stage<MODE>(st, raw[S], tid);
   };
   using I0 = std::integral_constant<int, 0>;
 
-  static_for<0, PF>([&](auto ij) { fetch(decltype(ij)::value, decltype(ij)::value, ij); });
-  if constexpr (DMA) wait_vm<LPC * (PF - 1)>();
-  land(0, 0, I0{}, stage);
-  fetch(PF, PF % RING, I0{});
-  if constexpr (DMA)
-    bar_lds();
-  else
-    __syncthreads();
+  static_for<0, PF>([&](auto ij) { fetch(decltype(ij)::value, ij); });
+  land(0, I0{}, stage);
+  fetch(PF, I0{});
+  __syncthreads();
 
   // Bit position of this lane's B fragment for block 0 at k-step 0:
   // reduction index t0 = 8h (+ e), output column col0 + m.
@@ -581,28 +503,36 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
 
   // Chunk c: matrix-core work on stage (c & 1); then chunk c + 1, fetched PF
   // chunks ago into set (c + 1), is staged, set (c + 1) is refilled with
-  // chunk c + 1 + PF, and one barrier publishes the stage. DMA waits count
-  // this wave's loads: LPC per chunk, the PF - 1 younger chunks may remain.
-  const int nbodies = (nchunks + CPB - 1) / CPB;
-  for (int body = 0; body < nbodies; ++body) {
+  // chunk c + 1 + PF, and one barrier publishes the stage.
+  // Steady state: bodies whose chunks stage only chunks before the last run
+  // without a branch, so the compiler waits for exactly one register set per
+  // chunk; the remaining 2 .. CPB + 1 chunks run with their checks.
+  const int nmain = last >= 1 ? (last - 1) / CPB : 0;
+  for (int body = 0; body < nmain; ++body) {
     static_for<0, CPB>([&](auto icc) {
       constexpr int cc = decltype(icc)::value;
       const int chunk = body * CPB + cc;
-      if (chunk < nchunks) {
-        do_chunk(icc, chunk);
-        using IS = std::integral_constant<int, (cc + 1) % PF>;  // set of chunk + 1
-        if constexpr (DMA) wait_vm<LPC * (PF - 1)>();
-        if (chunk + 1 < nchunks)
-          land(chunk + 1, (chunk + 1) % RING, IS{}, stage + ((chunk + 1) & 1) * SDW);
-        fetch(chunk + 1 + PF, (chunk + 1 + PF) % RING, IS{});
-        if constexpr (DMA)
-          bar_lds();
-        else
-          __syncthreads();
-      }
+      do_chunk(icc, chunk);
+      using IS = std::integral_constant<int, (cc + 1) % PF>;  // set of chunk + 1
+      store_stage<MODE>(stage + ((chunk + 1) & 1) * SDW, raw[IS::value], tid);
+      fetch(chunk + 1 + PF, IS{});
+      __syncthreads();
+      // Do not let the next chunk's conversion move up: it would wait for
+      // every set in flight instead of one.
+      __builtin_amdgcn_sched_barrier(0);
     });
   }
-  if constexpr (DMA) wait_vm<0>();  // no global->LDS load outlives the tile
+  static_for<0, CPB + 1>([&](auto icc) {
+    constexpr int cc = decltype(icc)::value;
+    const int chunk = nmain * CPB + cc;
+    if (chunk < nchunks) {
+      do_chunk(std::integral_constant<int, cc % CPB>{}, chunk);
+      using IS = std::integral_constant<int, (cc + 1) % PF>;
+      if (chunk + 1 < nchunks) land(chunk + 1, IS{}, stage + ((chunk + 1) & 1) * SDW);
+      if (chunk + 1 + PF < nchunks) fetch(chunk + 1 + PF, IS{});
+      __syncthreads();
+    }
+  });
 
   // Epilogue: lane (m, h) holds, for block c, output column col0 + 32c + m
   // and rows 8*(v/4) + 4*h + (v%4) of the 32x32 accumulator.
@@ -786,13 +716,26 @@ __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int til
   const float *fin = (const float *)a.in + (size_t)b * a.R * a.ld_in * 2;
   constexpr int CH = 32;  // 8 k-steps of 4 terms per stage
   const int nchunks = (a.t_len + CH - 1) / CH;
+  const int last = nchunks - 1;
+  const __amdgpu_buffer_rsrc_t rsrc = frame_rsrc(fin, (long long)a.R * a.ld_in * 8);
+  uint32_t voff[CH / 16];
+#pragma unroll
+  for (int i = 0; i < CH / 16; ++i) voff[i] = pair_voff<CH>(i, a0, a.ld_in, tid);
+  // chunk -> set (past the end: the last chunk again); set -> stage, masked
+  // when it holds the last chunk
+  auto fetch = [&](RawC64<CH> &r, int chunk) {
+    load_stage<CH>(r, rsrc, voff, (chunk < last ? chunk : last) * CH);
+  };
+  auto land = [&](uint32_t *st, RawC64<CH> &r, int chunk) {
+    if (chunk == last) mask_stage<CH>(r, chunk * CH, a.t_len, tid);
+    store_stage<MODE_F32>(st, r, tid);
+  };
   RawC64<CH> raw[PF];
 #pragma unroll
-  for (int c = 0; c < PF; ++c)
-    if (c < nchunks) load_stage(raw[c], fin, a.R, a0, a.ld_in, a.t_len, c * CH, tid);
+  for (int c = 0; c < PF; ++c) fetch(raw[c], c);
   for (int i = tid; i < a.nbw; i += kThreads) sbits[i] = a.bits[i];
-  store_stage<MODE_F32>(stage, raw[0], tid);
-  if (PF < nchunks) load_stage(raw[0], fin, a.R, a0, a.ld_in, a.t_len, PF * CH, tid);
+  land(stage, raw[0], 0);
+  fetch(raw[0], PF);
   __syncthreads();
 
   const int p_base = pos_mod(g - j16 - col0, a.N);
@@ -836,12 +779,8 @@ __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int til
                     __builtin_amdgcn_mfma_f64_16x16x4f64(av[r2][ri], bv, acc[r2][ri][c], 0, 0, 0);
           }
         }
-        if (chunk + 1 < nchunks) {
-          store_stage<MODE_F32>(stage + ((chunk + 1) & 1) * SDW, raw[(cc + 1) % PF], tid);
-          if (chunk + 1 + PF < nchunks)
-            load_stage(raw[(cc + 1) % PF], fin, a.R, a0, a.ld_in, a.t_len,
-                       (chunk + 1 + PF) * CH, tid);
-        }
+        if (chunk + 1 < nchunks) land(stage + ((chunk + 1) & 1) * SDW, raw[(cc + 1) % PF], chunk + 1);
+        fetch(raw[(cc + 1) % PF], chunk + 1 + PF);
         __syncthreads();
       }
     }
