@@ -426,6 +426,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
     const int p = pos_mod(p_base - 16 * j, tl.N);
     make_window<MODE, IN>(win[NWIN - j], window8(sbits, p), lut);
   }
+  make_window<MODE, IN>(win[0], window8(sbits, p_base), lut);  // k-step 0
 
   f32x16 acc_re[NC], acc_im[NC];
 #pragma unroll
@@ -439,66 +440,80 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
 
   // One chunk of matrix-core work from LDS stage (chunk & 1); cc is the
   // chunk's position in the unrolled body, which fixes the window slots.
+  // Software pipelined: during k-step i the window of step i + 1 is built
+  // (its slot held step i + 1 - NWIN, an odd offset no block reads at step i)
+  // and, in the one-plane 16-bit mode, the A operands of step i + 1 are read,
+  // so no LDS round trip sits between two bursts of matrix-core ops.
+  constexpr int NP = (MODE == MODE_F32S) ? 3 : 1;
+  constexpr int AB = (MODE == MODE_BF16) ? 2 : 1;  // A operand buffers
+  auto read_a = [&](const uint32_t *st, int u, u32x4 (&are)[NP], u32x4 (&aim)[NP]) {
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      are[s] = *(const u32x4 *)(st + s * PS + m * RS + 8 * u + 4 * h);
+      aim[s] = *(const u32x4 *)(st + (NP + s) * PS + m * RS + 8 * u + 4 * h);
+    }
+  };
   auto do_chunk = [&](auto icc, int chunk) {
     constexpr int cc = decltype(icc)::value;
-      const uint32_t *st = stage + (chunk & 1) * SDW;
-  #pragma unroll
-      for (int u = 0; u < KS; ++u) {
-        const int q = (KS * cc + u) % NWIN;  // slot of k-step i = KS*chunk + u
-        const int i = KS * chunk + u;
-        make_window<MODE, IN>(win[q], window8(sbits, p_base + 16 * i), lut);
-        if constexpr (MODE == MODE_F32) {
-          const float *pre = (const float *)st + m * RS + 16 * u + 8 * h;
-          const float *pim = pre + PS;
-          f32x4 r0 = *(const f32x4 *)pre, r1 = *(const f32x4 *)(pre + 4);
-          f32x4 i0 = *(const f32x4 *)pim, i1 = *(const f32x4 *)(pim + 4);
-          float are[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-          float aim[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
-  #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-  #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              const uint32_t x = win[(q - 2 * c + NWIN) % NWIN].f;
-              const float bv =
-                  __builtin_bit_cast(float, 0x3F800000u | ((x << (31 - j)) & 0x80000000u));
-              acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[j], bv, acc_re[c], 0, 0, 0);
-              acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[j], bv, acc_im[c], 0, 0, 0);
-            }
+    const uint32_t *st = stage + (chunk & 1) * SDW;
+    [[maybe_unused]] u32x4 are[AB][NP], aim[AB][NP];
+    if constexpr (AB == 2) read_a(st, 0, are[0], aim[0]);
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int q = (KS * cc + u) % NWIN;  // slot of k-step i = KS*chunk + u
+      const int i = KS * chunk + u;
+      make_window<MODE, IN>(win[(q + 1) % NWIN], window8(sbits, p_base + 16 * (i + 1)), lut);
+      if constexpr (MODE == MODE_F32) {
+        const float *pre = (const float *)st + m * RS + 16 * u + 8 * h;
+        const float *pim = pre + PS;
+        f32x4 r0 = *(const f32x4 *)pre, r1 = *(const f32x4 *)(pre + 4);
+        f32x4 i0 = *(const f32x4 *)pim, i1 = *(const f32x4 *)(pim + 4);
+        float fre[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+        float fim[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const uint32_t x = win[(q - 2 * c + NWIN) % NWIN].f;
+            const float bv =
+                __builtin_bit_cast(float, 0x3F800000u | ((x << (31 - j)) & 0x80000000u));
+            acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(fre[j], bv, acc_re[c], 0, 0, 0);
+            acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(fim[j], bv, acc_im[c], 0, 0, 0);
           }
+        }
+      } else {
+        const int cur = (AB == 2) ? (u & 1) : 0;
+        if constexpr (AB == 2) {
+          if (u + 1 < KS) read_a(st, u + 1, are[(u + 1) & 1], aim[(u + 1) & 1]);
         } else {
-          constexpr int NP = (MODE == MODE_F32S) ? 3 : 1;
-          u32x4 are[NP], aim[NP];
-  #pragma unroll
-          for (int s = 0; s < NP; ++s) {
-            are[s] = *(const u32x4 *)(st + s * PS + m * RS + 8 * u + 4 * h);
-            aim[s] = *(const u32x4 *)(st + (NP + s) * PS + m * RS + 8 * u + 4 * h);
-          }
-          // split part outer, lag block inner: the dependent updates of one
-          // accumulator are 2*NC matrix-core ops apart
-  #pragma unroll
-          for (int s = 0; s < NP; ++s) {
-  #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              const u32x4 bw = win[(q - 2 * c + NWIN) % NWIN].f;
-              if constexpr (IN == IN_F16) {
-                acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                    __builtin_bit_cast(f16x8, are[s]), __builtin_bit_cast(f16x8, bw),
-                    acc_re[c], 0, 0, 0);
-                acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                    __builtin_bit_cast(f16x8, aim[s]), __builtin_bit_cast(f16x8, bw),
-                    acc_im[c], 0, 0, 0);
-              } else {
-                acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    __builtin_bit_cast(bf16x8, are[s]), __builtin_bit_cast(bf16x8, bw),
-                    acc_re[c], 0, 0, 0);
-                acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    __builtin_bit_cast(bf16x8, aim[s]), __builtin_bit_cast(bf16x8, bw),
-                    acc_im[c], 0, 0, 0);
-              }
+          read_a(st, u, are[0], aim[0]);
+        }
+        // split part outer, lag block inner: the dependent updates of one
+        // accumulator are 2*NC matrix-core ops apart
+#pragma unroll
+        for (int s = 0; s < NP; ++s) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const u32x4 bw = win[(q - 2 * c + NWIN) % NWIN].f;
+            if constexpr (IN == IN_F16) {
+              acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                  __builtin_bit_cast(f16x8, are[cur][s]), __builtin_bit_cast(f16x8, bw),
+                  acc_re[c], 0, 0, 0);
+              acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                  __builtin_bit_cast(f16x8, aim[cur][s]), __builtin_bit_cast(f16x8, bw),
+                  acc_im[c], 0, 0, 0);
+            } else {
+              acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  __builtin_bit_cast(bf16x8, are[cur][s]), __builtin_bit_cast(bf16x8, bw),
+                  acc_re[c], 0, 0, 0);
+              acc_im[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  __builtin_bit_cast(bf16x8, aim[cur][s]), __builtin_bit_cast(bf16x8, bw),
+                  acc_im[c], 0, 0, 0);
             }
           }
         }
       }
+    }
   };
 
   // Chunk c: matrix-core work on stage (c & 1); then chunk c + 1, fetched PF
@@ -857,7 +872,11 @@ __device__ __forceinline__ i32x8 expand_e4m3(uint32_t x) {
   return r;
 }
 
-template <int NC>
+// AL: rows are 16-code aligned and t_len is a multiple of 16, so every
+// 16-code piece is read by one unconditional buffer load (zeros past the
+// frame) and only the last chunk is masked; otherwise codes are read one by
+// one.
+template <int NC, bool AL>
 __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles_r, int tiles_c,
                                                              int nbw_pad) {
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
@@ -890,9 +909,12 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
   const int col0 = cg * (kWaves * 32 * NC) + wave * 32 * NC;
 
   const int nchunks = (a.t_len + CH - 1) / CH;
+  const int last = nchunks - 1;
   const uint8_t *fin = (const uint8_t *)a.in + (size_t)b * a.R * 2 * a.ld_in;
   // thread t loads 16 codes: row t >> 3, plane (t >> 2) & 1, codes 16*(t & 3)
   const int lrow = tid >> 3, lplane = (tid >> 2) & 1, lpart = tid & 3;
+  const __amdgpu_buffer_rsrc_t rsrc = frame_rsrc(fin, (long long)a.R * 2 * a.ld_in);
+  const uint32_t voff = (uint32_t)((a0 + lrow) * 2 + lplane) * (uint32_t)a.ld_in + 16u * lpart;
   auto load_chunk = [&](u32x4 &r, int chunk) {
     const int n = chunk * CH + 16 * lpart;
     const int arow = a0 + lrow;
@@ -915,14 +937,30 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
   auto store_chunk = [&](uint32_t *st, const u32x4 &r) {
     *(u32x4 *)(st + lplane * PS + lrow * RS + 4 * lpart) = r;
   };
+  // chunk -> registers (past the end: the last chunk again)
+  auto fetch = [&](u32x4 &r, int chunk) {
+    const int c = chunk < last ? chunk : last;
+    if constexpr (AL)
+      r = __builtin_bit_cast(u32x4,
+                             __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, c * CH, 0));
+    else
+      load_chunk(r, c);
+  };
+  // registers holding `chunk` -> stage; pieces past t_len (the next plane's
+  // codes) are zeroed in the last chunk
+  auto land = [&](uint32_t *st, u32x4 &r, int chunk) {
+    if constexpr (AL) {
+      if (chunk == last && chunk * CH + 16 * lpart >= a.t_len) r = u32x4{0u, 0u, 0u, 0u};
+    }
+    store_chunk(st, r);
+  };
 
   u32x4 raw[PF];
 #pragma unroll
-  for (int j = 0; j < PF; ++j)
-    if (j < nchunks) load_chunk(raw[j], j);
+  for (int j = 0; j < PF; ++j) fetch(raw[j], j);
   for (int i = tid; i < a.nbw; i += kThreads) sbits[i] = a.bits[i];
-  store_chunk(stage, raw[0]);
-  if (PF < nchunks) load_chunk(raw[0], PF);
+  land(stage, raw[0], 0);
+  fetch(raw[0], PF);
   __syncthreads();
 
   const int p_base = pos_mod(32 * h - m - col0, a.N);
@@ -942,40 +980,54 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
     }
   }
 
-  const int nbodies = (nchunks + CPB - 1) / CPB;
-  for (int body = 0; body < nbodies; ++body) {
+  // matrix-core work of chunk i (= k-step i) from stage (i & 1); cc = i mod CPB
+  auto compute = [&](auto icc, int i) {
+    constexpr int cc = decltype(icc)::value;
+    const uint32_t *st = stage + (i & 1) * SDW;
+    const int q = (2 * cc) % NW;  // slot of W(2i)
+    win[q] = expand_e4m3(window32(sbits, p_base + 64 * i));
+    win[(q + 1) % NW] = expand_e4m3(window32(sbits, p_base + 64 * i + 32));
+    const u32x4 r0 = *(const u32x4 *)(st + m * RS + 8 * h);
+    const u32x4 r1 = *(const u32x4 *)(st + m * RS + 8 * h + 4);
+    const u32x4 i0 = *(const u32x4 *)(st + PS + m * RS + 8 * h);
+    const u32x4 i1 = *(const u32x4 *)(st + PS + m * RS + 8 * h + 4);
+    const i32x8 are = {(int)r0.x, (int)r0.y, (int)r0.z, (int)r0.w,
+                       (int)r1.x, (int)r1.y, (int)r1.z, (int)r1.w};
+    const i32x8 aim = {(int)i0.x, (int)i0.y, (int)i0.z, (int)i0.w,
+                       (int)i1.x, (int)i1.y, (int)i1.z, (int)i1.w};
 #pragma unroll
-    for (int cc = 0; cc < CPB; ++cc) {
-      const int i = body * CPB + cc;  // chunk = k-step
-      if (i < nchunks) {
-        const uint32_t *st = stage + (i & 1) * SDW;
-        const int q = (2 * cc) % NW;  // slot of W(2i)
-        win[q] = expand_e4m3(window32(sbits, p_base + 64 * i));
-        win[(q + 1) % NW] = expand_e4m3(window32(sbits, p_base + 64 * i + 32));
-        const u32x4 r0 = *(const u32x4 *)(st + m * RS + 8 * h);
-        const u32x4 r1 = *(const u32x4 *)(st + m * RS + 8 * h + 4);
-        const u32x4 i0 = *(const u32x4 *)(st + PS + m * RS + 8 * h);
-        const u32x4 i1 = *(const u32x4 *)(st + PS + m * RS + 8 * h + 4);
-        const i32x8 are = {(int)r0.x, (int)r0.y, (int)r0.z, (int)r0.w,
-                           (int)r1.x, (int)r1.y, (int)r1.z, (int)r1.w};
-        const i32x8 aim = {(int)i0.x, (int)i0.y, (int)i0.z, (int)i0.w,
-                           (int)i1.x, (int)i1.y, (int)i1.z, (int)i1.w};
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const i32x8 bw = win[(q - c + NW) % NW];
-          acc_re[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(are, bw, acc_re[c], 0, 0,
-                                                                      0, 0, 0, 0);
-          acc_im[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(aim, bw, acc_im[c], 0, 0,
-                                                                      0, 0, 0, 0);
-        }
-        if (i + 1 < nchunks) {
-          store_chunk(stage + ((i + 1) & 1) * SDW, raw[(cc + 1) % PF]);
-          if (i + 1 + PF < nchunks) load_chunk(raw[(cc + 1) % PF], i + 1 + PF);
-        }
-        __syncthreads();
-      }
+    for (int c = 0; c < NC; ++c) {
+      const i32x8 bw = win[(q - c + NW) % NW];
+      acc_re[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(are, bw, acc_re[c], 0, 0, 0,
+                                                                  0, 0, 0);
+      acc_im[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(aim, bw, acc_im[c], 0, 0, 0,
+                                                                  0, 0, 0);
     }
+  };
+  // Steady state without branches (exact waits), then 2 .. CPB + 1 chunks
+  // with their checks; same scheme as the 16-bit kernel.
+  const int nmain = last >= 1 ? (last - 1) / CPB : 0;
+  for (int body = 0; body < nmain; ++body) {
+    static_for<0, CPB>([&](auto icc) {
+      constexpr int cc = decltype(icc)::value;
+      const int i = body * CPB + cc;
+      compute(icc, i);
+      store_chunk(stage + ((i + 1) & 1) * SDW, raw[(cc + 1) % PF]);
+      fetch(raw[(cc + 1) % PF], i + 1 + PF);
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+    });
   }
+  static_for<0, CPB + 1>([&](auto icc) {
+    constexpr int cc = decltype(icc)::value;
+    const int i = nmain * CPB + cc;
+    if (i < nchunks) {
+      compute(std::integral_constant<int, cc % CPB>{}, i);
+      if (i + 1 < nchunks) land(stage + ((i + 1) & 1) * SDW, raw[(cc + 1) % PF], i + 1);
+      if (i + 1 + PF < nchunks) fetch(raw[(cc + 1) % PF], i + 1 + PF);
+      __syncthreads();
+    }
+  });
 
   const float alpha = a.alpha * (a.scales ? a.scales[b] : 1.0f);
 #pragma unroll
@@ -1001,8 +1053,8 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
   }
 }
 
-template <int NC>
-static hipError_t launch_fp8_nc(const TgArgs &a, hipStream_t s) {
+template <int NC, bool AL>
+static hipError_t launch_fp8_nc_al(const TgArgs &a, hipStream_t s) {
   const int tiles_r = (a.R + kRows - 1) / kRows;
   const int cols_per_tile = kWaves * 32 * NC;
   const int tiles_c = (a.c_len + cols_per_tile - 1) / cols_per_tile;
@@ -1011,13 +1063,19 @@ static hipError_t launch_fp8_nc(const TgArgs &a, hipStream_t s) {
   const int nbw_pad = (a.nbw + 3) & ~3;
   const size_t lds = (size_t)(nbw_pad + 2 * 2 * kRows * 20) * 4;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)tg_fp8_kernel<NC>,
+    hipError_t e = hipFuncSetAttribute((const void *)tg_fp8_kernel<NC, AL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((tg_fp8_kernel<NC>), dim3((unsigned)nt), dim3(kThreads), lds, s, a,
+  hipLaunchKernelGGL((tg_fp8_kernel<NC, AL>), dim3((unsigned)nt), dim3(kThreads), lds, s, a,
                      tiles_r, tiles_c, nbw_pad);
   return hipGetLastError();
+}
+
+template <int NC>
+static hipError_t launch_fp8_nc(const TgArgs &a, hipStream_t s) {
+  if ((a.ld_in & 15) == 0 && (a.t_len & 15) == 0) return launch_fp8_nc_al<NC, true>(a, s);
+  return launch_fp8_nc_al<NC, false>(a, s);
 }
 
 template <int MODE, int IN, int NC, bool AL>
@@ -1048,10 +1106,21 @@ static hipError_t launch_tg_nc(const TgArgs &a, hipStream_t s) {
   return launch_tg_nc_al<MODE, IN, NC, false>(a, s);
 }
 
+// Column width per wave: the widest that the output needs (fewest re-reads
+// of the input), narrowed while the launch has fewer tiles than the chip has
+// compute units, so small batches (one frame) spread over more of them.
+static int pick_nc(const TgArgs &a) {
+  int nc = a.c_len > 256 ? 4 : (a.c_len > 128 ? 2 : 1);
+  const long rows = (long)a.batch * ((a.R + kRows - 1) / kRows);
+  while (nc > 1 && rows * ((a.c_len + kWaves * 32 * nc - 1) / (kWaves * 32 * nc)) < 256) nc /= 2;
+  return nc;
+}
+
 template <int MODE, int IN>
 static hipError_t launch_tg_mode(const TgArgs &a, hipStream_t s) {
-  if (a.c_len > 256) return launch_tg_nc<MODE, IN, 4>(a, s);
-  if (a.c_len > 128) return launch_tg_nc<MODE, IN, 2>(a, s);
+  const int nc = pick_nc(a);
+  if (nc == 4) return launch_tg_nc<MODE, IN, 4>(a, s);
+  if (nc == 2) return launch_tg_nc<MODE, IN, 2>(a, s);
   return launch_tg_nc<MODE, IN, 1>(a, s);
 }
 
@@ -1081,8 +1150,9 @@ hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s) {
   if (in_fmt == IN_BF16) return launch_tg_mode<MODE_BF16, IN_BF16>(a, s);
   if (in_fmt == IN_F16) return launch_tg_mode<MODE_BF16, IN_F16>(a, s);
   if (in_fmt == IN_E4M3) {
-    if (a.c_len > 256) return launch_fp8_nc<4>(a, s);
-    if (a.c_len > 128) return launch_fp8_nc<2>(a, s);
+    const int nc = pick_nc(a);
+    if (nc == 4) return launch_fp8_nc<4>(a, s);
+    if (nc == 2) return launch_fp8_nc<2>(a, s);
     return launch_fp8_nc<1>(a, s);
   }
   return hipErrorInvalidValue;
