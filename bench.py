@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # HBM bytes per launch of the bf16 estimate measured with rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
 # for the kernel source with this sha256; any other source reports null.
-TRAFFIC = {"source_sha256": "21ae562ad810b171b76cc77e251cb2039825bc63b2c92f9362757732c671e8ea",
-           "bytes_per_launch": 203393399}
+TRAFFIC = {"source_sha256": "bd35629c5334d4384022359929c292204947a33f68a1df27d9f1b76f0d5ab936",
+           "bytes_per_launch": 203502053}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix
 
