@@ -14,8 +14,17 @@ A timed step is one estimation pass over the batch resident in HBM:
                matrix cores, FP32 accumulation, c64 CIRs written;
   fp32 path  : pnce_estimate(precision=F32S), FP32-accurate (timed too).
 
+Besides the headline, the line carries timings of every other form of the
+path: the quantiser, the packed estimate, the adjoint, refinement and the
+4096-frame uneven batch (rows), the precision-study workload (N = 4095,
+T*L = 2048, R = 256, 512 frames: bf16 / f16 / e4m3 packed estimates and
+refinement) and the differentiation workload (N = 1023, T*L = 1024, R = 128,
+1024 frames: forward + backward through autograd), and a second one-frame
+latency that includes the copy of the frame from pinned host memory.
+
 Prints one JSON line (rank 0). Usage:
-  python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu]
+  python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-rows]
+                  [--no-workloads]
 """
 from __future__ import annotations
 
@@ -38,8 +47,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # for the kernel source with this sha256; any other source reports null.
 TRAFFIC = {"source_sha256": "bd35629c5334d4384022359929c292204947a33f68a1df27d9f1b76f0d5ab936",
            "bytes_per_launch": 203502053}
-BF16_PEAK_TFLOPS = 2516.6      # dense bf16 matrix
+BF16_PEAK_TFLOPS = 2516.6      # dense bf16 / f16 matrix
+FP8_PEAK_TFLOPS = 5033.2       # dense fp8 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix
+FP64_PEAK_TFLOPS = 78.6        # dense fp64 matrix
 
 
 def parse():
@@ -55,6 +66,8 @@ def parse():
                          "rocprofv3 --pmc byte counters and their copy-kernel calibration)")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the quantiser/adjoint/refinement/uneven-batch timings")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the precision-study and differentiation workloads")
     return ap.parse_args()
 
 
@@ -86,6 +99,18 @@ def nmse_db(H, h):
     e = ((H - h).abs() ** 2).reshape(B, -1).sum(1).double()
     p = (h.abs() ** 2).reshape(B, -1).sum(1).double()
     return float(10.0 * np.log10((e / p).mean().item()))
+
+
+def spin_up(fn, seconds, torch):
+    """Untimed: keep the GPU busy with the step itself for `seconds` so that
+    its clocks have left the idle state before warm-up and timing (a few
+    dozen microsecond launches alone do not get them there)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -198,6 +223,83 @@ def uneven_batch(torch, args):
             "workgroups": st["workgroups"], "tiles": st["tiles"]}
 
 
+def _randn_c64(shape, seed, torch):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    re = torch.randn(shape, generator=g, device="cuda")
+    im = torch.randn(shape, generator=g, device="cuda")
+    return torch.complex(re, im).contiguous()
+
+
+def precision_workload(torch, args):
+    """Precision-study shape (N=4095, T=32, L=64, R=256, 512 frames): quantiser,
+    packed estimates in bf16 / f16 / e4m3, and least-squares refinement from
+    the original complex64 frames (parity is in the GPU tests; here, time)."""
+    import synth
+    from paper_2206_05506_amd import Plan
+    cfg = synth.PRECISION
+    B, R, N, K = cfg.B, cfg.R, cfg.N, cfg.K
+    plan = Plan(N, cfg.T, cfg.L, R)
+    y = _randn_c64((B, R, N), 21, torch)
+    H = torch.empty((B, R, K), dtype=torch.complex64, device="cuda")
+    flops = 4.0 * B * R * N * K
+    res = {"workload": cfg.name, "frames": B, "R": R, "N": N, "T*L": K}
+    steps = max(2, args.steps // 4)
+    for fmt, peak in (("bf16", BF16_PEAK_TFLOPS), ("f16", BF16_PEAK_TFLOPS),
+                      ("e4m3", FP8_PEAK_TFLOPS)):
+        q, sc = plan.pack(y, fmt)
+        ms_p, _ = time_steps(lambda: plan.pack(y, fmt, out=q, scales=sc), steps, 1, torch)
+        ms_e, _ = time_steps(lambda: plan.estimate_packed(q, sc, fmt, out=H), steps, 1, torch)
+        code_b = q.numel() * q.element_size()
+        res[fmt] = {"pack_ms": ms_p, "pack_GB/s": (B * R * N * 8 * 2 + code_b) / ms_p / 1e6,
+                    "estimate_ms": ms_e, "TFLOP/s": flops / ms_e / 1e9,
+                    "mfma_frac": flops / ms_e / 1e9 / peak,
+                    "GB/s": (code_b + B * R * K * 8) / ms_e / 1e6,
+                    "CIR/s": B * R * cfg.T / (ms_e * 1e-3)}
+        del q, sc
+    ms_s, _ = time_steps(lambda: plan.estimate(y, "f32s", out=H), steps, 1, torch)
+    res["f32s_estimate_ms"] = ms_s
+    work = torch.empty_like(y)
+    X = H.clone()
+    ms_1, _ = time_steps(lambda: plan.refine(y, X, 1, work=work), 2, 1, torch)
+    ms_5, _ = time_steps(lambda: plan.refine(y, X, 5, work=work), 2, 1, torch)
+    res["refine"] = {"steps_1_ms": ms_1, "steps_5_ms": ms_5,
+                     "note": "every step: residual y - P x then x += P^T r / N (f32s); the "
+                             "last step's residual accumulates in FP64 on FP64 matrix cores"}
+    plan.close()
+    del y, H, work, X
+    torch.cuda.empty_cache()
+    return res
+
+
+def differentiation_workload(torch, args):
+    """Differentiation shape (N=1023, T=16, L=64, R=128, 1024 frames): one
+    forward correlation and its backward (adjoint) through autograd."""
+    import synth
+    from paper_2206_05506_amd import Plan
+    from paper_2206_05506_amd.autograd import correlate
+    cfg = synth.DIFF
+    B, R, N, K = cfg.B, cfg.R, cfg.N, cfg.K
+    plan = Plan(N, cfg.T, cfg.L, R)
+    y = _randn_c64((B, R, N), 22, torch).requires_grad_(True)
+    G = _randn_c64((B, R, K), 23, torch)
+
+    def fwd_bwd():
+        H = correlate(y, plan, "f32s")
+        (g,) = torch.autograd.grad(H, y, grad_outputs=G)
+        return g
+
+    ms, _ = time_steps(fwd_bwd, max(2, args.steps // 4), 1, torch)
+    flops = 2 * 4.0 * B * R * N * K
+    plan.close()
+    del y, G
+    torch.cuda.empty_cache()
+    return {"workload": cfg.name, "frames": B, "forward_backward_ms": ms,
+            "TFLOP/s": flops / ms / 1e9,
+            "note": "FP32-accurate forward and adjoint kernels; 3 bf16 matrix-core products "
+                    "per term, so matrix-core rate = 3x the TFLOP/s shown"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -238,18 +340,29 @@ def main():
     def step_f32():
         plan.estimate(y, "f32", out=H_mf)
 
+    spin_up(step_bf16, 0.3, torch)
     ms_bf, wall_bf = time_steps(step_bf16, args.steps, args.warmup, torch)
     ms_32, _ = time_steps(step_f32s, args.steps, args.warmup, torch)
     ms_mf, _ = time_steps(step_f32, max(2, args.steps // 4), 2, torch)
 
     y1 = y[:1].contiguous()
     H1 = torch.empty((1, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
-    lat_bf = lat_32 = None
+    lat_bf = lat_32 = lat_h2d = None
     if args.latency_iters > 0:
         lat_bf = p50_latency_us(lambda: plan.estimate(y1, "bf16", out=H1), args.latency_iters,
                                 torch)
         lat_32 = p50_latency_us(lambda: plan.estimate(y1, "f32s", out=H1), args.latency_iters,
                                 torch)
+        # the same frame handed over in pinned host memory: copy in, then estimate
+        y1_host = torch.empty(y1.shape, dtype=y1.dtype, pin_memory=True)
+        y1_host.copy_(y1.cpu())
+        y1_dev = torch.empty_like(y1)
+
+        def h2d_then_estimate():
+            y1_dev.copy_(y1_host, non_blocking=True)
+            plan.estimate(y1_dev, "bf16", out=H1)
+
+        lat_h2d = p50_latency_us(h2d_then_estimate, args.latency_iters, torch)
 
     nmse_bf = nmse_db(H_bf, h)
     nmse_32 = nmse_db(H_32, h)
@@ -275,7 +388,8 @@ def main():
         "data": "synthetic (seeded draws, y = P h + noise composed on the GPU)",
         "config": {"workload": cfg.name, "N": cfg.N, "T": cfg.T, "L": cfg.L, "R": cfg.R,
                    "frames": cfg.B, "input": "complex64", "snr_db": [cfg.snr_lo, cfg.snr_hi]},
-        "p50_frame_latency_us": {"bf16": lat_bf, "fp32": lat_32},
+        "p50_frame_latency_us": {"bf16": lat_bf, "fp32": lat_32,
+                                 "bf16_with_h2d_copy": lat_h2d},
         "fp32_path": {"value": cirs / (ms_32 * 1e-3), "ms_per_step": ms_32,
                       "precision": "f32s (3-way bf16 split, exact)"},
         "fp32_mfma_path": {"value": cirs / (ms_mf * 1e-3), "ms_per_step": ms_mf,
@@ -291,6 +405,9 @@ def main():
     }
     if not args.no_rows:
         out["rows"] = other_rows(plan, cfg, y, H_32, torch, args)
+    if not args.no_workloads:
+        out["precision_workload"] = precision_workload(torch, args)
+        out["differentiation_workload"] = differentiation_workload(torch, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(y, cfg, args.cpu_seconds)
     plan.close()
