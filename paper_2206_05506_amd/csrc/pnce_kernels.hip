@@ -38,23 +38,25 @@ constexpr int kThreads = 64 * kWaves;
 
 // ---------------------------------------------------------------------------
 // Samples per LDS stage (one barrier each) and operand formats of a stage.
-// The bf16 mode runs 4 k-steps (64 samples) per stage so that its short
-// matrix-core work per k-step amortises the stage's barrier and LDS round
-// trips; the FP32-accurate and FP32 modes already do 3x / 4x more matrix
-// work per k-step and use 32-sample stages.
+// Between barriers a wave runs KS = ch/16 k-steps of matrix-core work, so a
+// stage is as long as the register sets that feed it allow: complex64 input
+// needs twice the registers of packed codes per sample, and the FP32-accurate
+// and FP32 modes do 3x / 4x more matrix work per k-step already.
 // Rows are padded by 4 dwords so that the 16-byte fragment reads of 8
 // consecutive rows fall in distinct LDS banks.
-//   MODE_F32  : 2 fp32 planes (re, im), 32 samples + pad  -> 36 dwords
-//   MODE_F32S : 6 bf16 planes (re hi/mid/lo, im hi/mid/lo) -> 20 dwords
-//   MODE_BF16 : 2 bf16 (or f16) planes, 64 samples + pad   -> 36 dwords
+//   MODE_F32            : 2 fp32 planes (re, im), 32 samples + pad   -> 36 dwords
+//   MODE_F32S           : 6 bf16 planes (re hi/mid/lo, im hi/mid/lo) -> 20 dwords
+//   MODE_BF16, complex64: 2 bf16 planes, 64 samples + pad            -> 36 dwords
+//   MODE_BF16, codes    : 2 bf16/f16 planes, 128 samples + pad       -> 68 dwords
 // ---------------------------------------------------------------------------
-template <int MODE> struct StageGeom;
-template <> struct StageGeom<MODE_F32> { static constexpr int ch = 32, planes = 2, rs = 36; };
-template <> struct StageGeom<MODE_F32S> { static constexpr int ch = 32, planes = 6, rs = 20; };
-template <> struct StageGeom<MODE_BF16> { static constexpr int ch = 64, planes = 2, rs = 36; };
+template <int MODE, int IN = IN_C64> struct StageGeom;
+template <int IN> struct StageGeom<MODE_F32, IN> { static constexpr int ch = 32, planes = 2, rs = 36; };
+template <int IN> struct StageGeom<MODE_F32S, IN> { static constexpr int ch = 32, planes = 6, rs = 20; };
+template <int IN> struct StageGeom<MODE_BF16, IN> { static constexpr int ch = 128, planes = 2, rs = 68; };
+template <> struct StageGeom<MODE_BF16, IN_C64> { static constexpr int ch = 64, planes = 2, rs = 36; };
 
-template <int MODE> constexpr int stage_dwords() {
-  return StageGeom<MODE>::planes * kRows * StageGeom<MODE>::rs;
+template <int MODE, int IN = IN_C64> constexpr int stage_dwords() {
+  return StageGeom<MODE, IN>::planes * kRows * StageGeom<MODE, IN>::rs;
 }
 
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
@@ -244,7 +246,7 @@ __device__ __forceinline__ void store_stage(uint32_t *st, const RawC64<CH> &raw,
 
 template <int MODE, int CH>
 __device__ __forceinline__ void store_stage(uint32_t *st, const RawPacked<CH> &raw, int tid) {
-  constexpr int RS = StageGeom<MODE>::rs;
+  constexpr int RS = StageGeom<MODE, IN_BF16>::rs;
   constexpr int PS = kRows * RS;
 #pragma unroll
   for (int i = 0; i < CH / 32; ++i) {
@@ -314,18 +316,16 @@ __device__ __forceinline__ int pos_mod(int a, int n) {
 // ---------------------------------------------------------------------------
 // The tiled kernel.
 // ---------------------------------------------------------------------------
-// Global->LDS load depth (chunks in flight) per mode: deep for the
-// HBM-bound bf16 mode, shallower where the stage itself is large.
-// Stages in flight (register sets) per mode and input: 32 KiB of complex64
-// per workgroup for every mode; packed input stages are half as large.
+// Stages in flight (register sets): 32 KiB of complex64, or 32 KiB of
+// codes, per workgroup.
 template <int MODE, int IN> struct RegDepth {
-  static constexpr int value = StageGeom<MODE>::ch == 64 ? 2 : 4;
+  static constexpr int value = StageGeom<MODE, IN>::ch >= 64 ? 2 : 4;
 };
 
 // LDS dwords of one workgroup tile: bit stream + window table + two stages.
 template <int MODE, int IN>
 constexpr int tile_lds_dwords(int nbw_pad) {
-  return nbw_pad + kLutDw + 2 * stage_dwords<MODE>();
+  return nbw_pad + kLutDw + 2 * stage_dwords<MODE, IN>();
 }
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
@@ -354,10 +354,10 @@ template <int MODE, int IN, int NC, bool AL>
 __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
                                          const uint32_t *lut, uint32_t *stage) {
   constexpr int NWIN = 2 * NC;
-  constexpr int RS = StageGeom<MODE>::rs;
+  constexpr int RS = StageGeom<MODE, IN>::rs;
   constexpr int PS = kRows * RS;
-  constexpr int SDW = stage_dwords<MODE>();
-  constexpr int CH = StageGeom<MODE>::ch;    // samples per stage
+  constexpr int SDW = stage_dwords<MODE, IN>();
+  constexpr int CH = StageGeom<MODE, IN>::ch;  // samples per stage
   constexpr int KS = CH / 16;                // k-steps per stage
   constexpr bool C64 = IN == IN_C64;
   constexpr int PF = RegDepth<MODE, IN>::value;  // stages in flight
@@ -876,18 +876,25 @@ __device__ __forceinline__ i32x8 expand_e4m3(uint32_t x) {
 // 16-code piece is read by one unconditional buffer load (zeros past the
 // frame) and only the last chunk is masked; otherwise codes are read one by
 // one.
+constexpr int kFp8Chunk = 128;               // codes per stage (two k-steps)
+constexpr int kFp8RowDw = kFp8Chunk / 4 + 4;  // padded plane row in dwords
+
 template <int NC, bool AL>
 __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles_r, int tiles_c,
                                                              int nbw_pad) {
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
   constexpr int NW = 2 * NC;       // window slots (32-sample granularity)
-  constexpr int RS = 20;           // dwords per plane row: 64 codes + pad
+  constexpr int CH = kFp8Chunk;    // codes per stage
+  constexpr int KS = CH / 64;      // k-steps of 64 codes per stage
+  constexpr int RS = kFp8RowDw;    // dwords per plane row: CH codes + pad
   constexpr int PS = kRows * RS;
   constexpr int SDW = 2 * PS;
-  constexpr int CH = 64;           // samples per chunk = one k-step
-  constexpr int PF = 4;
-  constexpr int CPB = (NC > PF) ? NC : PF;  // chunks per unrolled body
-  static_assert(CPB % PF == 0 && CPB % NC == 0, "body must cover both rotations");
+  constexpr int NPC = CH / 64;     // 16-code pieces per thread and stage
+  constexpr int PF = 4;            // stages in flight (register sets)
+  // chunks per unrolled body: covers the register-set rotation (PF) and the
+  // window rotation (NW slots, 2 per k-step)
+  constexpr int CPB = (NW > 2 * KS * PF) ? NW / (2 * KS) : PF;
+  static_assert(CPB % PF == 0 && (2 * KS * CPB) % NW == 0, "body must cover both rotations");
 
   uint32_t *sbits = smem;
   uint32_t *stage = smem + nbw_pad;
@@ -911,19 +918,29 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
   const int nchunks = (a.t_len + CH - 1) / CH;
   const int last = nchunks - 1;
   const uint8_t *fin = (const uint8_t *)a.in + (size_t)b * a.R * 2 * a.ld_in;
-  // thread t loads 16 codes: row t >> 3, plane (t >> 2) & 1, codes 16*(t & 3)
-  const int lrow = tid >> 3, lplane = (tid >> 2) & 1, lpart = tid & 3;
+  // piece q = t + 256 i of a stage: 16 codes of row q / (CH/8), plane
+  // (q / (CH/16)) & 1, codes 16 (q % (CH/16)) .. +15
+  int prow[NPC], pplane[NPC], ppart[NPC];
+  uint32_t voff[NPC];
+#pragma unroll
+  for (int i = 0; i < NPC; ++i) {
+    const int q = tid + kThreads * i;
+    prow[i] = q / (CH / 8);
+    pplane[i] = (q / (CH / 16)) & 1;
+    ppart[i] = q % (CH / 16);
+    voff[i] = (uint32_t)((a0 + prow[i]) * 2 + pplane[i]) * (uint32_t)a.ld_in + 16u * ppart[i];
+  }
   const __amdgpu_buffer_rsrc_t rsrc = frame_rsrc(fin, (long long)a.R * 2 * a.ld_in);
-  const uint32_t voff = (uint32_t)((a0 + lrow) * 2 + lplane) * (uint32_t)a.ld_in + 16u * lpart;
-  auto load_chunk = [&](u32x4 &r, int chunk) {
-    const int n = chunk * CH + 16 * lpart;
-    const int arow = a0 + lrow;
-    u32x4 x = {0u, 0u, 0u, 0u};
-    if (arow < a.R) {
-      const uint8_t *p = fin + ((size_t)arow * 2 + lplane) * a.ld_in + n;
-      if (n + 16 <= a.t_len && (a.ld_in & 15) == 0) {
-        x = *(const u32x4 *)p;
-      } else {
+  using Raw = u32x4[NPC];
+  // codes one by one (rows not 16-code aligned or t_len not a multiple of 16)
+  auto load_codes = [&](Raw &r, int chunk) {
+#pragma unroll
+    for (int i = 0; i < NPC; ++i) {
+      const int n = chunk * CH + 16 * ppart[i];
+      const int arow = a0 + prow[i];
+      u32x4 x = {0u, 0u, 0u, 0u};
+      if (arow < a.R) {
+        const uint8_t *p = fin + ((size_t)arow * 2 + pplane[i]) * a.ld_in + n;
         uint32_t e[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) e[j] = (n + j < a.t_len) ? p[j] : 0u;
@@ -931,31 +948,40 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
         for (int w = 0; w < 4; ++w)
           x[w] = e[4 * w] | (e[4 * w + 1] << 8) | (e[4 * w + 2] << 16) | (e[4 * w + 3] << 24);
       }
+      r[i] = x;
     }
-    r = x;
   };
-  auto store_chunk = [&](uint32_t *st, const u32x4 &r) {
-    *(u32x4 *)(st + lplane * PS + lrow * RS + 4 * lpart) = r;
+  auto store_chunk = [&](uint32_t *st, const Raw &r) {
+#pragma unroll
+    for (int i = 0; i < NPC; ++i)
+      *(u32x4 *)(st + pplane[i] * PS + prow[i] * RS + 4 * ppart[i]) = r[i];
   };
   // chunk -> registers (past the end: the last chunk again)
-  auto fetch = [&](u32x4 &r, int chunk) {
+  auto fetch = [&](Raw &r, int chunk) {
     const int c = chunk < last ? chunk : last;
-    if constexpr (AL)
-      r = __builtin_bit_cast(u32x4,
-                             __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, c * CH, 0));
-    else
-      load_chunk(r, c);
+    if constexpr (AL) {
+#pragma unroll
+      for (int i = 0; i < NPC; ++i)
+        r[i] = __builtin_bit_cast(
+            u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], c * CH, 0));
+    } else {
+      load_codes(r, c);
+    }
   };
   // registers holding `chunk` -> stage; pieces past t_len (the next plane's
   // codes) are zeroed in the last chunk
-  auto land = [&](uint32_t *st, u32x4 &r, int chunk) {
+  auto land = [&](uint32_t *st, Raw &r, int chunk) {
     if constexpr (AL) {
-      if (chunk == last && chunk * CH + 16 * lpart >= a.t_len) r = u32x4{0u, 0u, 0u, 0u};
+      if (chunk == last) {
+#pragma unroll
+        for (int i = 0; i < NPC; ++i)
+          if (chunk * CH + 16 * ppart[i] >= a.t_len) r[i] = u32x4{0u, 0u, 0u, 0u};
+      }
     }
     store_chunk(st, r);
   };
 
-  u32x4 raw[PF];
+  Raw raw[PF];
 #pragma unroll
   for (int j = 0; j < PF; ++j) fetch(raw[j], j);
   for (int i = tid; i < a.nbw; i += kThreads) sbits[i] = a.bits[i];
@@ -980,28 +1006,33 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
     }
   }
 
-  // matrix-core work of chunk i (= k-step i) from stage (i & 1); cc = i mod CPB
-  auto compute = [&](auto icc, int i) {
+  // matrix-core work of chunk `chunk` (k-steps KS*chunk .. +KS-1) from stage
+  // (chunk & 1); cc = chunk mod CPB fixes the window slots
+  auto compute = [&](auto icc, int chunk) {
     constexpr int cc = decltype(icc)::value;
-    const uint32_t *st = stage + (i & 1) * SDW;
-    const int q = (2 * cc) % NW;  // slot of W(2i)
-    win[q] = expand_e4m3(window32(sbits, p_base + 64 * i));
-    win[(q + 1) % NW] = expand_e4m3(window32(sbits, p_base + 64 * i + 32));
-    const u32x4 r0 = *(const u32x4 *)(st + m * RS + 8 * h);
-    const u32x4 r1 = *(const u32x4 *)(st + m * RS + 8 * h + 4);
-    const u32x4 i0 = *(const u32x4 *)(st + PS + m * RS + 8 * h);
-    const u32x4 i1 = *(const u32x4 *)(st + PS + m * RS + 8 * h + 4);
-    const i32x8 are = {(int)r0.x, (int)r0.y, (int)r0.z, (int)r0.w,
-                       (int)r1.x, (int)r1.y, (int)r1.z, (int)r1.w};
-    const i32x8 aim = {(int)i0.x, (int)i0.y, (int)i0.z, (int)i0.w,
-                       (int)i1.x, (int)i1.y, (int)i1.z, (int)i1.w};
+    const uint32_t *st = stage + (chunk & 1) * SDW;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const i32x8 bw = win[(q - c + NW) % NW];
-      acc_re[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(are, bw, acc_re[c], 0, 0, 0,
-                                                                  0, 0, 0);
-      acc_im[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(aim, bw, acc_im[c], 0, 0, 0,
-                                                                  0, 0, 0);
+    for (int u = 0; u < KS; ++u) {
+      const int i = KS * chunk + u;         // k-step
+      const int q = (2 * (KS * cc + u)) % NW;  // slot of W(2i)
+      win[q] = expand_e4m3(window32(sbits, p_base + 64 * i));
+      win[(q + 1) % NW] = expand_e4m3(window32(sbits, p_base + 64 * i + 32));
+      const u32x4 r0 = *(const u32x4 *)(st + m * RS + 16 * u + 8 * h);
+      const u32x4 r1 = *(const u32x4 *)(st + m * RS + 16 * u + 8 * h + 4);
+      const u32x4 i0 = *(const u32x4 *)(st + PS + m * RS + 16 * u + 8 * h);
+      const u32x4 i1 = *(const u32x4 *)(st + PS + m * RS + 16 * u + 8 * h + 4);
+      const i32x8 are = {(int)r0.x, (int)r0.y, (int)r0.z, (int)r0.w,
+                         (int)r1.x, (int)r1.y, (int)r1.z, (int)r1.w};
+      const i32x8 aim = {(int)i0.x, (int)i0.y, (int)i0.z, (int)i0.w,
+                         (int)i1.x, (int)i1.y, (int)i1.z, (int)i1.w};
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const i32x8 bw = win[(q - c + NW) % NW];
+        acc_re[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(are, bw, acc_re[c], 0, 0,
+                                                                    0, 0, 0, 0);
+        acc_im[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(aim, bw, acc_im[c], 0, 0,
+                                                                    0, 0, 0, 0);
+      }
     }
   };
   // Steady state without branches (exact waits), then 2 .. CPB + 1 chunks
@@ -1061,7 +1092,7 @@ static hipError_t launch_fp8_nc_al(const TgArgs &a, hipStream_t s) {
   const long nt = (long)a.batch * tiles_r * tiles_c;
   if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
   const int nbw_pad = (a.nbw + 3) & ~3;
-  const size_t lds = (size_t)(nbw_pad + 2 * 2 * kRows * 20) * 4;
+  const size_t lds = (size_t)(nbw_pad + 2 * 2 * kRows * kFp8RowDw) * 4;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)tg_fp8_kernel<NC, AL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
