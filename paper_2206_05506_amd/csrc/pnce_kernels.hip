@@ -102,10 +102,13 @@ template <int CH> struct RawPacked {
 };
 
 // Complex64 rows come through a raw buffer resource bounded by the frame:
-// reads at or past its end (antennas at or beyond R) return zeros, so every
-// load is unconditional and the compiler can count them exactly (a load in a
-// divergent branch forces it to wait for all outstanding loads). Thread t
-// reads sample pairs q = t + 256 i of a stage (row q / (CH/2), samples
+// reads at or past its end (antennas at or beyond R, the tail of the last
+// row) return zeros, so every load is unconditional and the compiler can
+// count them exactly (a load in a divergent branch forces it to wait for all
+// outstanding loads). The whole byte offset goes in the per-lane offset,
+// which the hardware checks against the frame size (the scalar offset is not
+// checked), so no load ever touches memory past the frame. Thread t reads
+// sample pairs q = t + 256 i of a stage (row q / (CH/2), samples
 // 2 (q % (CH/2)) and +1); a wave instruction reads 64 consecutive pairs.
 constexpr int kRsrcFlags = 0x00020000;  // raw buffer, 32-bit dwords
 
@@ -126,17 +129,23 @@ __device__ __forceinline__ uint32_t pair_voff(int i, int a0, int ld_in, int tid)
   return ((uint32_t)(a0 + q / (CH / 2)) * (uint32_t)ld_in + 2u * (q % (CH / 2))) * 8u;
 }
 
+// A pair cut by the end of its row (n + 1 == t_len, t_len >= 2) is read one
+// sample early, so the 16 bytes end at the row's end; mask_stage shifts it.
 template <int CH>
 __device__ __forceinline__ void load_stage(RawC64<CH> &raw, __amdgpu_buffer_rsrc_t rsrc,
-                                           const uint32_t (&voff)[CH / 16], int n0) {
+                                           const uint32_t (&voff)[CH / 16], int n0, int t_len,
+                                           int tid) {
+  const int n = n0 + 2 * (tid % (CH / 2));
+  const uint32_t off = 8u * n0 - (n + 1 == t_len ? 8u : 0u);
 #pragma unroll
   for (int i = 0; i < CH / 16; ++i)
     raw.v[i] = __builtin_bit_cast(
-        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], 8 * n0, 0));
+        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i] + off, 0, 0));
 }
 
-// Pairs cut by the end of the row keep only their valid sample; pairs past it
-// (which read the next row) become zero. Only the last stage needs this.
+// Pairs cut by the end of the row keep only their valid sample (read one
+// sample early: it arrives in the upper half); pairs past it (the next row's
+// samples, or zeros past the frame) become zero. Only the last stage needs it.
 template <int CH>
 __device__ __forceinline__ void mask_stage(RawC64<CH> &raw, int n0, int t_len, int tid) {
   const int n = n0 + 2 * (tid % (CH / 2));
@@ -144,9 +153,8 @@ __device__ __forceinline__ void mask_stage(RawC64<CH> &raw, int n0, int t_len, i
   for (int i = 0; i < CH / 16; ++i) {
     if (n >= t_len) {
       raw.v[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    } else if (n + 1 >= t_len) {
-      raw.v[i].z = 0.f;
-      raw.v[i].w = 0.f;
+    } else if (n + 1 == t_len) {
+      raw.v[i] = f32x4{raw.v[i].z, raw.v[i].w, 0.f, 0.f};
     }
   }
 }
@@ -195,7 +203,7 @@ __device__ __forceinline__ void load_stage(RawPacked<CH> &raw, __amdgpu_buffer_r
 #pragma unroll
   for (int i = 0; i < CH / 32; ++i)
     raw.v[i] = __builtin_bit_cast(
-        u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], 2 * n0, 0));
+        u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i] + 2u * n0, 0, 0));
 }
 
 // Pieces at or past t_len (they read the next plane) become zero.
@@ -393,7 +401,9 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   auto fetch = [&](int chunk, auto iset) {
     constexpr int S = decltype(iset)::value;
     const int c = chunk < last ? chunk : last;
-    if constexpr (BUF)
+    if constexpr (C64)
+      load_stage<CH>(raw[S], rsrc, voff, c * CH, tl.t_len, tid);
+    else if constexpr (BUF)
       load_stage<CH>(raw[S], rsrc, voff, c * CH);
     else
       load_stage_codes<CH>(raw[S], (const uint16_t *)tl.in, tl.R, a0, tl.ld_in, tl.t_len,
@@ -739,7 +749,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int til
   // chunk -> set (past the end: the last chunk again); set -> stage, masked
   // when it holds the last chunk
   auto fetch = [&](RawC64<CH> &r, int chunk) {
-    load_stage<CH>(r, rsrc, voff, (chunk < last ? chunk : last) * CH);
+    load_stage<CH>(r, rsrc, voff, (chunk < last ? chunk : last) * CH, a.t_len, tid);
   };
   auto land = [&](uint32_t *st, RawC64<CH> &r, int chunk) {
     if (chunk == last) mask_stage<CH>(r, chunk * CH, a.t_len, tid);
@@ -963,7 +973,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
 #pragma unroll
       for (int i = 0; i < NPC; ++i)
         r[i] = __builtin_bit_cast(
-            u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], c * CH, 0));
+            u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i] + (uint32_t)(c * CH), 0, 0));
     } else {
       load_codes(r, c);
     }
