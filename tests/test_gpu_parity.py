@@ -233,6 +233,21 @@ def test_fp32_baseline_full_batch_sampled():
     assert oracle.relerr(Hb[pick], refb) <= TOL32
 
 
+def test_tile_width_does_not_change_results():
+    """One frame alone launches narrow column tiles (spread over more compute
+    units); the same frame inside a 256-frame batch uses full-width tiles.
+    The k-step order per output is the same, so the CIRs agree bit for bit."""
+    cfg = synth.FP32
+    y, _, s = frames(cfg)
+    with _plan(cfg.N, cfg.T, cfg.L, cfg.R) as p:
+        yd = dev(y)
+        for prec in ("bf16", "f32s", "f32"):
+            Hb = p.estimate(yd, prec)
+            for f in (0, 131, 255):
+                H1 = p.estimate(yd[f:f + 1].contiguous(), prec)
+                assert torch.equal(H1[0], Hb[f]), (prec, f)
+
+
 def test_nonfinite_inputs_propagate():
     N, T, L, R = 63, 2, 8, 2
     y = _rand_frames(N, R, 1, 4)
