@@ -578,7 +578,8 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
             re += tl.beta * old.x;
             im += tl.beta * old.y;
           }
-          *(f2a8 *)(tl.out + o) = f2a8{re, im};
+          // streaming store: the CIRs are not read again by this launch
+          __builtin_nontemporal_store(f2a8{re, im}, (f2a8 *)(tl.out + o));
         }
       }
     }
@@ -833,7 +834,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int til
               re += beta * (double)old.x;
               im += beta * (double)old.y;
             }
-            *(f2a8 *)(a.out + o) = f2a8{(float)re, (float)im};
+            __builtin_nontemporal_store(f2a8{(float)re, (float)im}, (f2a8 *)(a.out + o));
           }
         }
       }
@@ -1087,7 +1088,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
             re += a.beta * old.x;
             im += a.beta * old.y;
           }
-          *(f2a8 *)(a.out + o) = f2a8{re, im};
+          __builtin_nontemporal_store(f2a8{re, im}, (f2a8 *)(a.out + o));
         }
       }
     }
