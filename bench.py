@@ -211,12 +211,24 @@ def uneven_batch(torch, args):
     vp.tune(Yq, None, out=H, reps=3)
     ms_p, _ = time_steps(lambda: vp.estimate(Yq, None, out=H), args.steps, 2, torch)
     ms_e, _ = time_steps(lambda: vp.estimate_each(Yq, None, out=H), 3, 1, torch)
+    # the persistent launch captured once in a HIP graph and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        vp.estimate(Yq, None, out=H)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        vp.estimate(Yq, None, out=H)
+    ms_g, _ = time_steps(graph.replay, args.steps, 2, torch)
+    del graph
     cirs = sum(R * T for R, N, T, L in shapes)
     byt = vp.n_codes * 2 + vp.n_out * 8
     flops = sum(4.0 * R * N * T * L for R, N, T, L in shapes)
     st = vp.stats()
     vp.close()
-    return {"frames": len(shapes), "persistent_ms": ms_p, "per_frame_launches_ms": ms_e,
+    return {"frames": len(shapes), "persistent_ms": ms_p, "graph_replay_ms": ms_g,
+            "per_frame_launches_ms": ms_e,
             "speedup": ms_e / ms_p, "CIR/s": cirs / (ms_p * 1e-3),
             "GB/s": byt / ms_p / 1e6, "hbm_frac": byt / ms_p / 1e6 / HBM_PEAK_GBS,
             "mfma_frac": flops / ms_p / 1e9 / BF16_PEAK_TFLOPS,

@@ -9,9 +9,11 @@
 //
 // Tiling (one workgroup = 4 wave64s):
 //  - tile = 32 antennas x (4 waves * 32*NC output columns);
-//  - the 32x(32-sample) input chunk of the tile is staged through LDS, already
-//    converted to the operand format of the matrix core, double-buffered with
-//    one barrier per chunk; all 4 waves read it (each owns 32*NC columns);
+//  - input chunks of the tile (32 rows x 32..128 samples) arrive in register
+//    sets by unconditional buffer loads bounded by the frame, are converted
+//    to the operand format of the matrix core while stored into LDS, and are
+//    double-buffered with one barrier per chunk; all 4 waves read a chunk
+//    (each owns 32*NC columns);
 //  - matrix-core A operand = input rows (real and imaginary planes), B operand
 //    = the +-1 Toeplitz tile, C = FP32 accumulators (2*NC 32x32 blocks);
 //  - Toeplitz reuse: the B fragment of column block c at k-step i equals the
