@@ -45,8 +45,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # HBM bytes per launch of the bf16 estimate measured with rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
 # for the kernel source with this sha256; any other source reports null.
-TRAFFIC = {"source_sha256": "bd35629c5334d4384022359929c292204947a33f68a1df27d9f1b76f0d5ab936",
-           "bytes_per_launch": 203502053}
+TRAFFIC = {"source_sha256": "5d8bb275bde82804e369669e76f81afa956b2325286f733647636cca0696cd53",
+           "bytes_per_launch": 203428849}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 / f16 matrix
 FP8_PEAK_TFLOPS = 5033.2       # dense fp8 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix
