@@ -187,6 +187,15 @@ def other_rows(plan, cfg, y, H, torch, args):
     A = torch.empty_like(y)
     ms, _ = time_steps(lambda: plan.adjoint(H, "f32s", out=A), args.steps, 2, torch)
     res["adjoint_f32s"] = {"ms": ms, "TFLOP/s": 4.0 * B * R * N * K / ms / 1e9}
+    Hls = torch.empty_like(H)
+    ms_f, _ = time_steps(lambda: plan.estimate_ls(y, "bf16", out=Hls), args.steps, 2, torch)
+    ms_d, _ = time_steps(lambda: plan.debias(Hls), args.steps, 2, torch)
+    res["least_squares"] = {"estimate_ls_bf16_ms": ms_f, "debias_ms": ms_d,
+                            "debias_GB/s": 2 * B * R * K * 8 / ms_d / 1e6,
+                            "note": "closed-form LS rows: fused into the correlator epilogue "
+                                    "(one column group per row here); debias alone reads and "
+                                    "writes the CIRs"}
+    del Hls
     X = H.clone()
     work = torch.empty_like(y)
     ms, _ = time_steps(lambda: plan.refine(y, X, 1, work=work), max(2, args.steps // 4), 1, torch)

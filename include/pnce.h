@@ -166,6 +166,31 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
 pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y,
                         void *X, void *work, int batch, int steps);
 
+/*
+ * Least-squares CIRs in closed form. The two-level autocorrelation of the
+ * sequence (Eq. 1) gives P^T P = (N+1) I - J (J all-ones, K = T*L <= N), so
+ * (P^T P)^-1 = (I + J / (N+1-K)) / (N+1), and from correlator outputs
+ * H = P^T y / N (Eq. 3, Eq. 10) every row (frame, antenna) becomes
+ *   H <- N/(N+1) * (H + (sum_k H[k]) / (N+1-K)),
+ * the exact least-squares solution: it removes the -sum(h)/N bias that the
+ * -1 off-peak autocorrelation leaves in Eq. 3 (noiseless frames are
+ * recovered to rounding). In place on H: [batch][R][T*L] complex64 device;
+ * the row sums are accumulated in FP64. Errors: PNCE_E_UNSUPPORTED when
+ * T*L > N (least squares is not unique); the usual plan/batch/pointer checks.
+ */
+pnce_status pnce_debias(const pnce_plan *plan, void *stream, void *H, int batch);
+
+/*
+ * pnce_estimate (alpha = 1/N, beta = 0) followed by pnce_debias: the
+ * correction is applied in the correlator's epilogue when one workgroup
+ * holds every lag of a row (T*L <= 512 and enough frames to fill the chip),
+ * otherwise by a second launch. precision: PNCE_PREC_F32, _F32S or _BF16.
+ * scales: optional per-frame factors as for pnce_estimate. Same errors as
+ * pnce_debias and pnce_estimate.
+ */
+pnce_status pnce_estimate_ls(const pnce_plan *plan, void *stream, const void *Y, void *H,
+                             int batch, int precision, const float *scales);
+
 /* ---------------------------------------------------------------------------
  * Uneven batches (the batching form): frames of different (R, N, T, L) drawn
  * from the ranges of Table I, estimated in ONE persistent launch whose work

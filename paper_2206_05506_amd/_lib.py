@@ -32,7 +32,7 @@ PNCE_FMT_E4M3 = 3
 
 SYMBOLS = ("pnce_create", "pnce_destroy", "pnce_get_sequence", "pnce_get_shape",
            "pnce_estimate", "pnce_pack", "pnce_estimate_packed", "pnce_adjoint",
-           "pnce_refine", "pnce_varlen_create", "pnce_varlen_destroy", "pnce_varlen_estimate",
+           "pnce_refine", "pnce_debias", "pnce_estimate_ls", "pnce_varlen_create", "pnce_varlen_destroy", "pnce_varlen_estimate",
            "pnce_varlen_estimate_each", "pnce_varlen_tune", "pnce_varlen_get_tuning",
            "pnce_varlen_set_tuning", "pnce_varlen_stats", "pnce_status_string",
            "pnce_last_error")
@@ -69,6 +69,8 @@ def _load() -> ctypes.CDLL:
         "pnce_estimate_packed": ([_P, _P, _P, _P, _P, _I, _I, _D], _I),
         "pnce_adjoint": ([_P, _P, _P, _P, _P, _I, _I, _D, _D], _I),
         "pnce_refine": ([_P, _P, _P, _P, _P, _I, _I], _I),
+        "pnce_debias": ([_P, _P, _P, _I], _I),
+        "pnce_estimate_ls": ([_P, _P, _P, _P, _I, _I, _P], _I),
         "pnce_varlen_create": ([ctypes.POINTER(_P), ctypes.POINTER(pnce_frame_desc), _I, _I],
                                _I),
         "pnce_varlen_destroy": ([_P], _I),
@@ -141,6 +143,15 @@ def pnce_adjoint(plan, stream, G, A, C, batch, precision, alpha, beta) -> int:
 
 def pnce_refine(plan, stream, y, X, work, batch, steps) -> int:
     return check(lib.pnce_refine(plan, stream, y, X, work, batch, steps), "pnce_refine")
+
+
+def pnce_debias(plan, stream, H, batch) -> int:
+    return check(lib.pnce_debias(plan, stream, H, batch), "pnce_debias")
+
+
+def pnce_estimate_ls(plan, stream, Y, H, batch, precision, scales) -> int:
+    return check(lib.pnce_estimate_ls(plan, stream, Y, H, batch, precision, scales),
+                 "pnce_estimate_ls")
 
 
 def pnce_varlen_create(frames, fmt: int):

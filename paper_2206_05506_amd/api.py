@@ -93,6 +93,30 @@ class Plan:
                            _ptr(scales), float(beta))
         return out
 
+    def debias(self, H: torch.Tensor) -> torch.Tensor:
+        """Least-squares CIRs from correlator outputs, in place:
+        H <- N/(N+1) (H + sum_k H[k] / (N+1-T*L)) per row (needs T*L <= N)."""
+        B = H.shape[0]
+        _need(H, (B, self.R, self.K), torch.complex64, "H")
+        _lib.pnce_debias(self.handle, _stream(), _ptr(H), B)
+        return H
+
+    def estimate_ls(self, Y: torch.Tensor, precision: str = "f32s", out=None,
+                    scales=None) -> torch.Tensor:
+        """Correlation followed by the least-squares correction (fused into the
+        correlator's epilogue when one workgroup holds a row's lags)."""
+        prec = PRECISIONS[precision]
+        B = Y.shape[0]
+        _need(Y, (B, self.R, self.N), torch.complex64, "Y")
+        if out is None:
+            out = torch.empty((B, self.R, self.K), dtype=torch.complex64, device=Y.device)
+        _need(out, (B, self.R, self.K), torch.complex64, "H")
+        if scales is not None:
+            _need(scales, (B,), torch.float32, "scales")
+        _lib.pnce_estimate_ls(self.handle, _stream(), _ptr(Y), _ptr(out), B, prec,
+                              _ptr(scales))
+        return out
+
     # ---------------------------------------------------------------- a3
     def pack(self, Y: torch.Tensor, fmt: str = "bf16", out=None, scales=None):
         """Quantise Y [B, R, N] complex64 -> (codes [B, R, 2, N+1], scales [B])."""

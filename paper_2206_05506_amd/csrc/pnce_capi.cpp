@@ -117,7 +117,7 @@ pnce_status check_batch(const pnce_plan *p, int batch) {
 pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
                    const void *in, int t_len, int ld_in, void *out, int c_len,
                    const void *cin, const uint32_t *bits, const float *scales,
-                   int batch, double alpha, double beta) {
+                   int batch, double alpha, double beta, bool ls = false) {
   hipError_t e;
   if (precision == PNCE_PREC_F64 || (in_fmt == pnce::IN_C64 && t_len < 2)) {
     // FP64 vector kernel: the FP64 path, and complex64 rows of one term
@@ -157,6 +157,7 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.nbw = p->nbw;
     a.alpha = (float)alpha;
     a.beta = (float)beta;
+    a.ls = ls ? 1 : 0;
     e = precision == PNCE_PREC_F64ACC ? pnce::launch_f64mm(a, s)
                                       : pnce::launch_tg(precision, in_fmt, a, s);
   }
@@ -272,6 +273,31 @@ pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y, vo
   if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
   return run_tg(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
                 plan->K, beta != 0.0 ? H : nullptr, plan->d_fwd, scales, batch, alpha, beta);
+}
+
+pnce_status pnce_debias(const pnce_plan *plan, void *stream, void *H, int batch) {
+  if (pnce_status st = check_plan(plan)) return st;
+  if (!H) return fail(PNCE_E_INVALID, "H must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
+  if (plan->K > plan->N)
+    return fail(PNCE_E_UNSUPPORTED, "T*L > N: least squares is not unique");
+  hipError_t e = pnce::launch_debias((float *)H, (long)batch * plan->R, plan->K, plan->N,
+                                     (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "debias launch");
+  return PNCE_OK;
+}
+
+pnce_status pnce_estimate_ls(const pnce_plan *plan, void *stream, const void *Y, void *H,
+                             int batch, int precision, const float *scales) {
+  if (pnce_status st = check_plan(plan)) return st;
+  if (!Y || !H) return fail(PNCE_E_INVALID, "Y and H must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
+  if (precision != PNCE_PREC_F32 && precision != PNCE_PREC_F32S && precision != PNCE_PREC_BF16)
+    return fail(PNCE_E_INVALID, "estimate_ls precision must be F32, F32S or BF16");
+  if (plan->K > plan->N)
+    return fail(PNCE_E_UNSUPPORTED, "T*L > N: least squares is not unique");
+  return run_tg(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
+                plan->K, nullptr, plan->d_fwd, scales, batch, 1.0 / plan->N, 0.0, true);
 }
 
 pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y, void *Yq,

@@ -29,9 +29,15 @@ struct TgArgs {
   int c_len, ld_out;
   int N, nbw;
   float alpha, beta;
+  // Nonzero: least-squares rows, out <- N/(N+1) (out + sum(out)/(N+1-c_len))
+  // (complex64 input, beta = 0, c_len <= N).
+  int ls;
 };
 
 hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s);
+
+// In-place least-squares correction of `rows` rows of K complex64 values.
+hipError_t launch_debias(float *H, long rows, int K, int N, hipStream_t s);
 
 // Same contraction on complex64 rows with FP64 sums on FP64 matrix cores;
 // alpha and beta are applied in FP64 before the single rounding to FP32.

@@ -358,6 +358,7 @@ struct Tile {
   int R, t_len, ld_in, c_len, ld_out, N;
   int a0, colg;
   float alpha, beta;
+  bool ls;  // least-squares rows (the tile holds every lag of its rows)
 };
 
 template <int MODE, int IN, int NC, bool AL>
@@ -563,7 +564,56 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
 
   // Epilogue: lane (m, h) holds, for block c, output column col0 + 32c + m
   // and rows 8*(v/4) + 4*h + (v%4) of the 32x32 accumulator.
-  const float alpha = tl.alpha;
+  float alpha = tl.alpha;
+  f32x16 tot_re = {}, tot_im = {};  // least squares: alpha * row sums
+  if (tl.ls) {
+    // Row sums over this wave's columns (those < c_len), then over the 32
+    // lanes of each half-wave, then over the 4 waves through LDS (the stage
+    // is no longer read); every lane then holds the sums of its 16 rows.
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const bool in = col0 + 32 * c + m < tl.c_len;
+        sr += in ? acc_re[c][v] : 0.f;
+        si += in ? acc_im[c][v] : 0.f;
+      }
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) {
+        sr += __shfl_xor(sr, o);
+        si += __shfl_xor(si, o);
+      }
+      tot_re[v] = sr;
+      tot_im[v] = si;
+    }
+    float *red = (float *)stage;  // [wave][row][re, im]
+    __syncthreads();
+    if (m == 0) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = 8 * (v >> 2) + 4 * h + (v & 3);
+        red[(wave * kRows + r) * 2] = tot_re[v];
+        red[(wave * kRows + r) * 2 + 1] = tot_im[v];
+      }
+    }
+    __syncthreads();
+    const float c1 = (float)tl.N / (float)(tl.N + 1);
+    const float c2 = 1.0f / (float)(tl.N + 1 - tl.c_len);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int r = 8 * (v >> 2) + 4 * h + (v & 3);
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        sr += red[(w * kRows + r) * 2];
+        si += red[(w * kRows + r) * 2 + 1];
+      }
+      tot_re[v] = c1 * alpha * c2 * sr;
+      tot_im[v] = c1 * alpha * c2 * si;
+    }
+    alpha *= c1;
+  }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int col = col0 + 32 * c + m;
@@ -573,8 +623,8 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
         const int ant = a0 + 8 * (v >> 2) + 4 * h + (v & 3);
         if (ant < tl.R) {
           const size_t o = ((size_t)ant * tl.ld_out + col) * 2;
-          float re = alpha * acc_re[c][v];
-          float im = alpha * acc_im[c][v];
+          float re = alpha * acc_re[c][v] + tot_re[v];
+          float im = alpha * acc_im[c][v] + tot_im[v];
           if (tl.beta != 0.0f) {
             const f2a8 old = *(const f2a8 *)(tl.cin + o);
             re += tl.beta * old.x;
@@ -624,6 +674,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
   tl.colg = cg * (kWaves * 32 * NC);
   tl.alpha = a.alpha * (a.scales ? a.scales[b] : 1.0f);
   tl.beta = a.beta;
+  tl.ls = a.ls != 0;
   run_tile<MODE, IN, NC, AL>(tl, smem, smem + nbw_pad, smem + nbw_pad + kLutDw);
 }
 
@@ -662,6 +713,7 @@ __global__ __launch_bounds__(kThreads, 2) void varlen_kernel(VArgs a) {
     tl.colg = vt.colg;
     tl.alpha = (a.scales ? a.scales[vt.frame] : 1.0f) / (float)f.N;
     tl.beta = 0.0f;
+    tl.ls = false;
     if (f.N >= 7) {  // N + 1 = 2^d, d >= 3: rows 8-code aligned
       if (vt.nc == 4)
         run_tile<MODE, IN, 4, true>(tl, smem, lut, stage);
@@ -1136,6 +1188,17 @@ static hipError_t launch_tg_nc_al(const TgArgs &a, hipStream_t s) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  if (a.ls && tiles_c > 1) {
+    // the rows' lags span several workgroups: plain correlation, then the
+    // least-squares correction as a second launch
+    TgArgs b = a;
+    b.ls = 0;
+    hipLaunchKernelGGL((tg_kernel<MODE, IN, NC, AL>), dim3((unsigned)nt), dim3(kThreads), lds, s,
+                       b, tiles_r, tiles_c, nbw_pad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_debias(a.out, (long)a.batch * a.R, a.c_len, a.N, s);
+  }
   hipLaunchKernelGGL((tg_kernel<MODE, IN, NC, AL>), dim3((unsigned)nt), dim3(kThreads), lds, s,
                      a, tiles_r, tiles_c, nbw_pad);
   return hipGetLastError();
@@ -1251,6 +1314,43 @@ hipError_t launch_tg64(const Tg64Args &a, hipStream_t s) {
                        cblocks);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Least-squares correction of correlator rows: one wave per row, FP64 row sum,
+// then every element out = c1 * (H + c2 * sum) with c1 = N/(N+1),
+// c2 = 1/(N+1-K). The row is read twice (the second time from cache).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void debias_kernel(float *H, long rows, int K, float c1,
+                                                     float c2) {
+  const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const int lane = threadIdx.x & 63;
+  f2a8 *h = (f2a8 *)H + (size_t)row * K;
+  double sr = 0.0, si = 0.0;
+  for (int k = lane; k < K; k += 64) {
+    const f2a8 v = h[k];
+    sr += (double)v.x;
+    si += (double)v.y;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sr += __shfl_xor(sr, o);
+    si += __shfl_xor(si, o);
+  }
+  const float ar = (float)(c2 * sr), ai = (float)(c2 * si);
+  for (int k = lane; k < K; k += 64) {
+    const f2a8 v = h[k];
+    h[k] = f2a8{c1 * (v.x + ar), c1 * (v.y + ai)};
+  }
+}
+
+hipError_t launch_debias(float *H, long rows, int K, int N, hipStream_t s) {
+  if (rows <= 0 || K <= 0 || K > N) return hipErrorInvalidValue;
+  const long blocks = (rows + 3) / 4;
+  if (blocks > 0x7FFFFFFFL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(debias_kernel, dim3((unsigned)blocks), dim3(256), 0, s, H, rows, K,
+                     (float)N / (float)(N + 1), 1.0f / (float)(N + 1 - K));
   return hipGetLastError();
 }
 

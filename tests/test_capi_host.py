@@ -30,7 +30,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("pnce_create", "pnce_destroy", "pnce_estimate", "pnce_adjoint", "pnce_pack",
-              "pnce_estimate_packed", "pnce_refine", "pnce_get_sequence"):
+              "pnce_estimate_packed", "pnce_refine", "pnce_debias", "pnce_estimate_ls",
+              "pnce_get_sequence"):
         assert n in names
 
 
@@ -94,6 +95,10 @@ def test_null_plan_is_rejected_everywhere(lib):
     assert lib.pnce_refine(None, None, None, None, None, 1, 1) == -1
     lib.pnce_pack.argtypes = [P, P, P, P, P, ctypes.c_int, ctypes.c_int]
     assert lib.pnce_pack(None, None, None, None, None, 1, 1) == -1
+    lib.pnce_debias.argtypes = [P, P, P, ctypes.c_int]
+    assert lib.pnce_debias(None, None, None, 1) == -1
+    lib.pnce_estimate_ls.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, P]
+    assert lib.pnce_estimate_ls(None, None, None, None, 1, 1, None) == -1
     lib.pnce_destroy.argtypes = [P]
     assert lib.pnce_destroy(None) == 0
     lib.pnce_get_sequence.argtypes = [P, P]
