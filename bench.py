@@ -322,6 +322,38 @@ def differentiation_workload(torch, args):
                     "per term, so matrix-core rate = 3x the TFLOP/s shown"}
 
 
+def front_end(plan, cfg, y, torch, lat_h2d_us, args):
+    """Raw blocks with a cyclic prefix of L samples in pinned host memory,
+    streamed to the device in chunks (copies overlapped with estimation),
+    against the pilot airtime of Eq. 11: T = (C + N) / Fs * N_t / N_batch,
+    here one multiplexed block of the T transmitters (N_t = N_batch = T)."""
+    cp = cfg.L
+    B, R, N = cfg.B, cfg.R, cfg.N
+    raw = torch.empty((B, R, cp + N), dtype=torch.complex64, device="cuda")
+    raw[:, :, cp:] = y
+    raw[:, :, :cp] = y[:, :, N - cp:]           # the prefix repeats the period's tail
+    host = torch.empty(raw.shape, dtype=raw.dtype, pin_memory=True)
+    host.copy_(raw.cpu())
+    H = torch.empty((B, R, cfg.K), dtype=torch.complex64, device="cuda")
+    chunk = 32
+    ms, _ = time_steps(lambda: plan.stream_from_host(host, cp, chunk, "bf16", out=H),
+                       max(2, args.steps // 4), 1, torch)
+    ms_dev, _ = time_steps(lambda: plan.estimate_cp(raw, cp, "bf16", out=H), args.steps, 2,
+                           torch)
+    byt = raw.numel() * 8
+    airtime = {f"{fs:g} MHz": (cp + N) / fs for fs in (10.0, 30.72, 61.44, 122.88)}
+    del raw, host, H
+    return {"cp": cp, "frames": B, "chunk_frames": chunk,
+            "host_stream_ms": ms, "host_stream_GB/s": byt / ms / 1e6,
+            "host_stream_CIR/s": B * R * cfg.T / (ms * 1e-3),
+            "device_resident_cp_ms": ms_dev,
+            "frame_latency_with_h2d_us": lat_h2d_us,
+            "frame_airtime_us": airtime,
+            "note": "PCIe-inclusive: raw c64 blocks from pinned host memory, copies on a second "
+                    "stream overlapped with the bf16 estimate (prefix skipped by addressing); "
+                    "airtime per multiplexed block of Eq. 11 at each sample rate"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -462,6 +494,7 @@ def main():
     }
     if not args.no_rows:
         out["rows"] = other_rows(plan, cfg, y, H_32, torch, args)
+        out["rows"]["front_end"] = front_end(plan, cfg, y, torch, lat_h2d, args)
     if not args.no_workloads:
         out["precision_workload"] = precision_workload(torch, args)
         out["differentiation_workload"] = differentiation_workload(torch, args)

@@ -167,6 +167,22 @@ pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y,
                         void *X, void *work, int batch, int steps);
 
 /*
+ * Raw received blocks (Section II-A, Section III-B): each antenna row holds
+ * the cyclic prefix of cp samples followed by the N samples of the sequence
+ * period; the prefix is removed by addressing alone (rows are cp + N
+ * samples apart), in the same launch as the correlation or the conversion.
+ * Y_raw: [batch][R][cp + N] complex64 (complex128 for PNCE_PREC_F64);
+ * pnce_estimate_cp computes H = scales_b * (Y P) / N as pnce_estimate with
+ * alpha = 1/N, beta = 0; pnce_pack_cp writes the codes and scales of
+ * pnce_pack. cp >= 0; raw frames must stay below 2 GiB
+ * (PNCE_E_UNSUPPORTED), other errors as for pnce_estimate / pnce_pack.
+ */
+pnce_status pnce_estimate_cp(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
+                             void *H, int batch, int precision, const float *scales);
+pnce_status pnce_pack_cp(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
+                         void *Yq, float *scales, int batch, int format);
+
+/*
  * Least-squares CIRs in closed form. The two-level autocorrelation of the
  * sequence (Eq. 1) gives P^T P = (N+1) I - J (J all-ones, K = T*L <= N), so
  * (P^T P)^-1 = (I + J / (N+1-K)) / (N+1), and from correlator outputs

@@ -1,7 +1,7 @@
 """ctypes binding of libpnce.so: the C entry points of include/pnce.h under
 the same names, with argument marshalling only (no computation here).
 
-The library must be built in-tree (``python -m paper_2206_05506_amd.build``);
+The library must be built in-tree (``python paper_2206_05506_amd/build.py``);
 importing this module without it raises, there is no fallback path.
 """
 from __future__ import annotations
@@ -32,7 +32,8 @@ PNCE_FMT_E4M3 = 3
 
 SYMBOLS = ("pnce_create", "pnce_destroy", "pnce_get_sequence", "pnce_get_shape",
            "pnce_estimate", "pnce_pack", "pnce_estimate_packed", "pnce_adjoint",
-           "pnce_refine", "pnce_debias", "pnce_estimate_ls", "pnce_varlen_create", "pnce_varlen_destroy", "pnce_varlen_estimate",
+           "pnce_refine", "pnce_debias", "pnce_estimate_ls", "pnce_estimate_cp", "pnce_pack_cp",
+           "pnce_varlen_create", "pnce_varlen_destroy", "pnce_varlen_estimate",
            "pnce_varlen_estimate_each", "pnce_varlen_tune", "pnce_varlen_get_tuning",
            "pnce_varlen_set_tuning", "pnce_varlen_stats", "pnce_status_string",
            "pnce_last_error")
@@ -57,7 +58,7 @@ _D = ctypes.c_double
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libpnce.so not built at {LIB_PATH}; run "
-                          "`python -m paper_2206_05506_amd.build`")
+                          "`python paper_2206_05506_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "pnce_create": ([ctypes.POINTER(_P), _I, _I, _I, _I], _I),
@@ -71,6 +72,8 @@ def _load() -> ctypes.CDLL:
         "pnce_refine": ([_P, _P, _P, _P, _P, _I, _I], _I),
         "pnce_debias": ([_P, _P, _P, _I], _I),
         "pnce_estimate_ls": ([_P, _P, _P, _P, _I, _I, _P], _I),
+        "pnce_estimate_cp": ([_P, _P, _P, _I, _P, _I, _I, _P], _I),
+        "pnce_pack_cp": ([_P, _P, _P, _I, _P, _P, _I, _I], _I),
         "pnce_varlen_create": ([ctypes.POINTER(_P), ctypes.POINTER(pnce_frame_desc), _I, _I],
                                _I),
         "pnce_varlen_destroy": ([_P], _I),
@@ -84,7 +87,11 @@ def _load() -> ctypes.CDLL:
         "pnce_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
-        fn = getattr(lib, name)
+        try:
+            fn = getattr(lib, name)
+        except AttributeError as e:
+            raise ImportError(f"{LIB_PATH} lacks {name}: it is older than its sources; run "
+                              "`python paper_2206_05506_amd/build.py`") from e
         fn.argtypes = args
         fn.restype = res
     return lib
@@ -147,6 +154,16 @@ def pnce_refine(plan, stream, y, X, work, batch, steps) -> int:
 
 def pnce_debias(plan, stream, H, batch) -> int:
     return check(lib.pnce_debias(plan, stream, H, batch), "pnce_debias")
+
+
+def pnce_estimate_cp(plan, stream, Y_raw, cp, H, batch, precision, scales) -> int:
+    return check(lib.pnce_estimate_cp(plan, stream, Y_raw, cp, H, batch, precision, scales),
+                 "pnce_estimate_cp")
+
+
+def pnce_pack_cp(plan, stream, Y_raw, cp, Yq, scales, batch, fmt) -> int:
+    return check(lib.pnce_pack_cp(plan, stream, Y_raw, cp, Yq, scales, batch, fmt),
+                 "pnce_pack_cp")
 
 
 def pnce_estimate_ls(plan, stream, Y, H, batch, precision, scales) -> int:

@@ -28,6 +28,17 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
+def _need_host(t: torch.Tensor, shape, dtype, name):
+    if not isinstance(t, torch.Tensor) or t.is_cuda:
+        raise ValueError(f"{name} must be a host tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
 def _need(t: torch.Tensor, shape, dtype, name):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
@@ -132,6 +143,78 @@ class Plan:
         _lib.pnce_pack(self.handle, _stream(), _ptr(Y), _ptr(out), _ptr(scales), B,
                        FORMATS[fmt])
         return out, scales
+
+    # ------------------------------------------------------ front end
+    def estimate_cp(self, Y_raw: torch.Tensor, cp: int, precision: str = "f32s", out=None,
+                    scales=None) -> torch.Tensor:
+        """Correlation of raw blocks Y_raw [B, R, cp + N] whose first cp
+        samples per row are the cyclic prefix (removed by addressing)."""
+        prec = PRECISIONS[precision]
+        cdt = torch.complex128 if prec == PNCE_PREC_F64 else torch.complex64
+        B = Y_raw.shape[0]
+        _need(Y_raw, (B, self.R, self.N + cp), cdt, "Y_raw")
+        if out is None:
+            out = torch.empty((B, self.R, self.K), dtype=cdt, device=Y_raw.device)
+        _need(out, (B, self.R, self.K), cdt, "H")
+        if scales is not None:
+            _need(scales, (B,), torch.float32, "scales")
+        _lib.pnce_estimate_cp(self.handle, _stream(), _ptr(Y_raw), int(cp), _ptr(out), B, prec,
+                              _ptr(scales))
+        return out
+
+    def pack_cp(self, Y_raw: torch.Tensor, cp: int, fmt: str = "bf16", out=None, scales=None):
+        """Quantise raw blocks Y_raw [B, R, cp + N], dropping the cyclic prefix
+        in the same launch: (codes [B, R, 2, N+1], scales [B])."""
+        B = Y_raw.shape[0]
+        _need(Y_raw, (B, self.R, self.N + cp), torch.complex64, "Y_raw")
+        if out is None:
+            out = torch.empty((B, self.R, 2, self.N + 1), dtype=_CODE_DTYPE[fmt],
+                              device=Y_raw.device)
+        if scales is None:
+            scales = torch.empty((B,), dtype=torch.float32, device=Y_raw.device)
+        _need(out, (B, self.R, 2, self.N + 1), _CODE_DTYPE[fmt], "Yq")
+        _need(scales, (B,), torch.float32, "scales")
+        _lib.pnce_pack_cp(self.handle, _stream(), _ptr(Y_raw), int(cp), _ptr(out),
+                          _ptr(scales), B, FORMATS[fmt])
+        return out, scales
+
+    def stream_from_host(self, Y_host: torch.Tensor, cp: int, chunk: int,
+                         precision: str = "bf16", out=None) -> torch.Tensor:
+        """Estimate raw blocks that sit in pinned host memory
+        (Y_host [F, R, cp + N] complex64): chunks of `chunk` frames are copied
+        to the device on a copy stream while the previous chunk is estimated
+        on the current stream (two device buffers, events between them).
+        Returns H [F, R, T*L] on the device; the current stream carries the
+        last estimate."""
+        if not Y_host.is_pinned():
+            raise ValueError("Y_host must be in pinned host memory")
+        F = Y_host.shape[0]
+        _need_host(Y_host, (F, self.R, self.N + cp), torch.complex64, "Y_host")
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if out is None:
+            out = torch.empty((F, self.R, self.K), dtype=torch.complex64, device=dev)
+        _need(out, (F, self.R, self.K), torch.complex64, "H")
+        compute = torch.cuda.current_stream()
+        copy = torch.cuda.Stream()
+        bufs = [torch.empty((chunk, self.R, self.N + cp), dtype=torch.complex64, device=dev)
+                for _ in range(2)]
+        copied = [torch.cuda.Event() for _ in range(2)]
+        used = [torch.cuda.Event() for _ in range(2)]
+        starts = list(range(0, F, chunk))
+        for i, f0 in enumerate(starts):
+            n = min(chunk, F - f0)
+            k = i & 1
+            with torch.cuda.stream(copy):
+                if i >= 2:
+                    copy.wait_event(used[k])  # the estimate that read buffer k is done
+                bufs[k][:n].copy_(Y_host[f0:f0 + n], non_blocking=True)
+                copied[k].record(copy)
+            compute.wait_event(copied[k])
+            self.estimate_cp(bufs[k][:n], cp, precision, out=out[f0:f0 + n])
+            used[k].record(compute)
+        for b in bufs:
+            b.record_stream(copy)  # written there; keep them until its work is done
+        return out
 
     def estimate_packed(self, Yq: torch.Tensor, scales, fmt: str = "bf16", out=None,
                         beta: float = 0.0) -> torch.Tensor:

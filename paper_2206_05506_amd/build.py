@@ -1,6 +1,6 @@
 """Build libpnce.so (HIP kernels for gfx950 + C-ABI host code) in-tree.
 
-    python -m paper_2206_05506_amd.build
+    python paper_2206_05506_amd/build.py
 """
 import os
 import subprocess

@@ -307,7 +307,43 @@ pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y, void *
   if (pnce_status st = check_batch(plan, batch)) return st;
   if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
   hipError_t e = pnce::launch_pack((const float *)Y, Yq, scales, batch, plan->R, plan->N,
-                                   format, (hipStream_t)stream);
+                                   plan->N, format, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pack launch");
+  return PNCE_OK;
+}
+
+// Raw received blocks: every row holds a cyclic prefix of cp samples, then
+// the N sequence samples; the prefix is skipped by addressing.
+static pnce_status check_cp(const pnce_plan *plan, int cp) {
+  if (cp < 0) return fail(PNCE_E_INVALID, "cp must be >= 0");
+  if (((long long)plan->R + 32) * ((long long)plan->N + cp + 1) * 8 >= (1LL << 31))
+    return fail(PNCE_E_UNSUPPORTED, "raw frame exceeds 2 GiB");
+  return PNCE_OK;
+}
+
+pnce_status pnce_estimate_cp(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
+                             void *H, int batch, int precision, const float *scales) {
+  if (pnce_status st = check_plan(plan)) return st;
+  if (!Y_raw || !H) return fail(PNCE_E_INVALID, "Y_raw and H must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
+  if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
+  if (pnce_status st = check_cp(plan, cp)) return st;
+  const size_t esz = precision == PNCE_PREC_F64 ? 16 : 8;
+  const void *Y = (const char *)Y_raw + (size_t)cp * esz;
+  return run_tg(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N + cp, H,
+                plan->K, nullptr, plan->d_fwd, scales, batch, 1.0 / plan->N, 0.0);
+}
+
+pnce_status pnce_pack_cp(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
+                         void *Yq, float *scales, int batch, int format) {
+  if (pnce_status st = check_plan(plan)) return st;
+  if (!Y_raw || !Yq || !scales) return fail(PNCE_E_INVALID, "Y_raw, Yq and scales must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
+  if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
+  if (pnce_status st = check_cp(plan, cp)) return st;
+  const float *Y = (const float *)Y_raw + (size_t)cp * 2;
+  hipError_t e = pnce::launch_pack(Y, Yq, scales, batch, plan->R, plan->N, plan->N + cp, format,
+                                   (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pack launch");
   return PNCE_OK;
 }

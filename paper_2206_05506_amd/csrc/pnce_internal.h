@@ -84,7 +84,8 @@ hipError_t launch_varlen(int in_fmt, const VArgs &a, int n_wg, hipStream_t s);
 hipError_t launch_tg_frame(int in_fmt, int nc, const TgArgs &a, hipStream_t s);
 
 // Quantiser: per-frame scale, then conversion into planar codes.
+// Rows of N samples ld complex apart (ld = N: contiguous frames).
 hipError_t launch_pack(const float *y, void *yq, float *scales, int batch,
-                       int R, int N, int fmt, hipStream_t s);
+                       int R, int N, int ld, int fmt, hipStream_t s);
 
 }  // namespace pnce

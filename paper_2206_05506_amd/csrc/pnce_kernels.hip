@@ -347,6 +347,23 @@ __device__ __forceinline__ void static_for(F &&f) {
   }
 }
 
+// Sum over the 32 lanes of each half-wave, result in every lane: lane moves
+// within 16-lane rows (quad permutes for xor 1 and xor 2, then the half-row
+// and row mirrors, which pair each 4- and 8-lane group with the other one),
+// then one shuffle across the two rows.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float half_wave_sum(float x) {
+  x += dpp_move<0xB1>(x);   // quad_perm [1,0,3,2]: lane ^ 1
+  x += dpp_move<0x4E>(x);   // quad_perm [2,3,0,1]: lane ^ 2
+  x += dpp_move<0x141>(x);  // row_half_mirror: the other quad of each 8 lanes
+  x += dpp_move<0x140>(x);  // row_mirror: the other 8 lanes of each row
+  return x + __shfl_xor(x, 16);
+}
+
 // One workgroup tile of the contraction: 32 antennas from a0, 4 waves x
 // 32*NC output columns from colg, of one frame whose rows start at `in`
 // (input) and `out` / `cin` (output). The sequence bits must already be in
@@ -394,8 +411,10 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   // complex64 and aligned packed rows: unconditional loads through the
   // frame-bounded buffer resource, masked once in the last chunk.
   constexpr bool BUF = C64 || AL;
-  const __amdgpu_buffer_rsrc_t rsrc =
-      frame_rsrc(tl.in, C64 ? (long long)tl.R * tl.ld_in * 8 : (long long)tl.R * tl.ld_in * 4);
+  // the frame ends with its last row's last term (rows may be strided past it)
+  const __amdgpu_buffer_rsrc_t rsrc = frame_rsrc(
+      tl.in, C64 ? ((long long)(tl.R - 1) * tl.ld_in + tl.t_len) * 8
+                 : ((long long)(2 * tl.R - 1) * tl.ld_in + tl.t_len) * 2);
   uint32_t voff[CH / 16] = {};
 #pragma unroll
   for (int i = 0; i < CH / 16; ++i)
@@ -579,13 +598,8 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
         sr += in ? acc_re[c][v] : 0.f;
         si += in ? acc_im[c][v] : 0.f;
       }
-#pragma unroll
-      for (int o = 16; o > 0; o >>= 1) {
-        sr += __shfl_xor(sr, o);
-        si += __shfl_xor(si, o);
-      }
-      tot_re[v] = sr;
-      tot_im[v] = si;
+      tot_re[v] = half_wave_sum(sr);
+      tot_im[v] = half_wave_sum(si);
     }
     float *red = (float *)stage;  // [wave][row][re, im]
     __syncthreads();
@@ -797,7 +811,8 @@ __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int til
   constexpr int CH = 32;  // 8 k-steps of 4 terms per stage
   const int nchunks = (a.t_len + CH - 1) / CH;
   const int last = nchunks - 1;
-  const __amdgpu_buffer_rsrc_t rsrc = frame_rsrc(fin, (long long)a.R * a.ld_in * 8);
+  const __amdgpu_buffer_rsrc_t rsrc =
+      frame_rsrc(fin, ((long long)(a.R - 1) * a.ld_in + a.t_len) * 8);
   uint32_t voff[CH / 16];
 #pragma unroll
   for (int i = 0; i < CH / 16; ++i) voff[i] = pair_voff<CH>(i, a0, a.ld_in, tid);
@@ -995,7 +1010,8 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
     ppart[i] = q % (CH / 16);
     voff[i] = (uint32_t)((a0 + prow[i]) * 2 + pplane[i]) * (uint32_t)a.ld_in + 16u * ppart[i];
   }
-  const __amdgpu_buffer_rsrc_t rsrc = frame_rsrc(fin, (long long)a.R * 2 * a.ld_in);
+  const __amdgpu_buffer_rsrc_t rsrc =
+      frame_rsrc(fin, (long long)(2 * a.R - 1) * a.ld_in + a.t_len);
   using Raw = u32x4[NPC];
   // codes one by one (rows not 16-code aligned or t_len not a multiple of 16)
   auto load_codes = [&](Raw &r, int chunk) {
@@ -1412,6 +1428,30 @@ __global__ __launch_bounds__(256) void frame_max_kernel(const f2a8 *y, uint32_t 
   }
 }
 
+// Rows with a stride (raw blocks whose cyclic prefix is skipped): grid
+// (row slices, frames); a workgroup reduces whole rows r = x, x + slices, ...
+__global__ __launch_bounds__(256) void frame_max_rows_kernel(const f2a8 *y, uint32_t *maxbits,
+                                                             int R, int N, int ld) {
+  uint32_t m = 0u;
+  for (int r = blockIdx.x; r < R; r += gridDim.x) {
+    const f2a8 *row = y + ((size_t)blockIdx.y * R + r) * ld;
+    for (int n = threadIdx.x; n < N; n += 256) {
+      const f2a8 v = row[n];
+      const float re = v.x, im = v.y;
+      m = max(m, __builtin_bit_cast(uint32_t, re) & 0x7FFFFFFFu);
+      m = max(m, __builtin_bit_cast(uint32_t, im) & 0x7FFFFFFFu);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
+  __shared__ uint32_t sm[4];
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = max(max(sm[0], sm[1]), max(sm[2], sm[3]));
+    if (m) atomicMax(maxbits + blockIdx.y, m);
+  }
+}
+
 // Max bits -> power-of-two scale, in place, once every pack block has read them.
 __global__ __launch_bounds__(256) void finalize_scale_kernel(float *scales, int batch,
                                                              float target) {
@@ -1445,7 +1485,8 @@ __device__ __forceinline__ uint32_t e4m3_code(float x) {
 // 8-byte (16-bit codes) or 4-byte (e4m3) store per plane.
 template <int FMT>
 __global__ __launch_bounds__(256) void pack_kernel(const f2a8 *y, void *yq, const uint32_t *maxbits,
-                                                   int R, int N, float target, long total) {
+                                                   int R, int N, int ld, float target,
+                                                   long total) {
   const long i = (long)blockIdx.x * 256 + threadIdx.x;  // (row, quad)
   if (i >= total) return;
   const int Np = N + 1, nq = Np >> 2;
@@ -1456,7 +1497,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const f2a8 *y, void *yq, cons
   f2a8 v[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
-    v[u] = n0 + u < N ? y[row * N + n0 + u] : f2a8{0.0f, 0.0f};
+    v[u] = n0 + u < N ? y[row * ld + n0 + u] : f2a8{0.0f, 0.0f};
   const size_t o = (size_t)row * 2 * Np + n0;
   if constexpr (FMT == 3) {
     uint32_t cr = 0u, ci = 0u;
@@ -1496,24 +1537,32 @@ __global__ __launch_bounds__(256) void pack_kernel(const f2a8 *y, void *yq, cons
 // scales doubles as the per-frame max word until the last launch turns it
 // into the scale, so the four launches must stay in this order on one stream.
 hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R, int N,
-                       int fmt, hipStream_t s) {
+                       int ld, int fmt, hipStream_t s) {
   if (fmt < 1 || fmt > 3) return hipErrorInvalidValue;
   const float target = (fmt == 3) ? 448.0f : 1.0f;
   uint32_t *mb = (uint32_t *)scales;
   const f2a8 *yc = (const f2a8 *)y;
   hipLaunchKernelGGL(zero_u32_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, mb, batch);
-  const long per_frame = (long)R * N;
-  const long slices = std::max(1L, std::min(64L, per_frame / (256L * kMaxUnroll)));
-  hipLaunchKernelGGL(frame_max_kernel, dim3((unsigned)slices, (unsigned)batch), dim3(256), 0, s,
-                     yc, mb, per_frame);
+  if (ld == N) {
+    const long per_frame = (long)R * N;
+    const long slices = std::max(1L, std::min(64L, per_frame / (256L * kMaxUnroll)));
+    hipLaunchKernelGGL(frame_max_kernel, dim3((unsigned)slices, (unsigned)batch), dim3(256), 0,
+                       s, yc, mb, per_frame);
+  } else {
+    hipLaunchKernelGGL(frame_max_rows_kernel, dim3((unsigned)std::min(R, 64), (unsigned)batch),
+                       dim3(256), 0, s, yc, mb, R, N, ld);
+  }
   const long total = (long)batch * R * ((N + 1) >> 2);
   const dim3 grid((unsigned)((total + 255) / 256));
   if (fmt == 1)
-    hipLaunchKernelGGL((pack_kernel<1>), grid, dim3(256), 0, s, yc, yq, mb, R, N, target, total);
+    hipLaunchKernelGGL((pack_kernel<1>), grid, dim3(256), 0, s, yc, yq, mb, R, N, ld, target,
+                       total);
   else if (fmt == 2)
-    hipLaunchKernelGGL((pack_kernel<2>), grid, dim3(256), 0, s, yc, yq, mb, R, N, target, total);
+    hipLaunchKernelGGL((pack_kernel<2>), grid, dim3(256), 0, s, yc, yq, mb, R, N, ld, target,
+                       total);
   else
-    hipLaunchKernelGGL((pack_kernel<3>), grid, dim3(256), 0, s, yc, yq, mb, R, N, target, total);
+    hipLaunchKernelGGL((pack_kernel<3>), grid, dim3(256), 0, s, yc, yq, mb, R, N, ld, target,
+                       total);
   hipLaunchKernelGGL(finalize_scale_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, scales,
                      batch, target);
   return hipGetLastError();

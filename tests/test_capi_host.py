@@ -23,7 +23,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("libpnce.so is not built (run python -m paper_2206_05506_amd.build)")
+        pytest.fail("libpnce.so is not built (run python paper_2206_05506_amd/build.py)")
     return ctypes.CDLL(LIB)
 
 
