@@ -1,0 +1,107 @@
+"""Accuracy sweeps of Section IV on synthetic channels, run on the GPU.
+
+MAE of Eq. 12 (mean |h_hat - h| over every tap of every (r, t) pair) against
+SNR for the estimator's precisions, with and without the closed-form
+least-squares rows:
+
+  fig4: PN length M in {511, 2047}, multiplexed transmitters per pilot
+        block N_batch in {1, 2, 4}, L = L_nz = 64, N_t = N_r = 16;
+  fig5: M = 2047, N_batch = 4, L = 128, L_nz in {1, 4, 16, 64, 128}.
+
+Each point averages `iters` realisations (Table I: 50). One realisation of an
+N_t x N_r system sends N_t / N_batch multiplexed pilot blocks; each block is
+one frame of the estimator with T = N_batch. Channels follow the sparse-tap
+model of Section II (synth.sparse_taps); frames are y = P h + sigma w with
+the library's own adjoint kernel, sigma per frame from the receive SNR.
+Every estimate and the receive model run in libpnce's kernels; torch only
+draws the noise and averages the errors.
+
+Usage: python -m paper_2206_05506_amd.sweeps [--iters 50] [--out FILE.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+import torch
+
+from .api import Plan
+
+SNRS = (-10, -5, 0, 5, 10, 15, 20, 25, 30)
+N_T = N_R = 16
+METHODS = ("fp32", "bf16", "f16", "e4m3", "fp32_ls", "bf16_ls")
+
+
+def _point(plan: Plan, h: torch.Tensor, snr_db: float, gen: torch.Generator) -> dict:
+    """MAE of every method for one SNR on channels h [F, R, T*L]."""
+    y0 = plan.adjoint(h, "f32s", alpha=1.0)                  # P h
+    p = (y0.abs() ** 2).mean(dim=(1, 2))
+    sigma = torch.sqrt(p / 10.0 ** (snr_db / 10.0))
+    w = torch.complex(torch.randn(y0.shape, generator=gen, device=y0.device),
+                      torch.randn(y0.shape, generator=gen, device=y0.device)) / np.sqrt(2.0)
+    y = (y0 + sigma[:, None, None] * w).contiguous()
+    est = {
+        "fp32": plan.estimate(y, "f32s"),
+        "bf16": plan.estimate(y, "bf16"),
+        "fp32_ls": plan.estimate_ls(y, "f32s"),
+        "bf16_ls": plan.estimate_ls(y, "bf16"),
+    }
+    for fmt in ("f16", "e4m3"):
+        q, sc = plan.pack(y, fmt)
+        est[fmt] = plan.estimate_packed(q, sc, fmt)
+    return {m: float((est[m] - h).abs().mean()) for m in METHODS}
+
+
+def _curve(M: int, nb: int, L: int, lnz: int, iters: int, seed: int) -> dict:
+    import synth
+    F = iters * (N_T // nb)
+    h_np = synth.sparse_taps((F, N_R, nb), L, lnz, N_T, seed)
+    h = torch.from_numpy(h_np.reshape(F, N_R, nb * L)).to(torch.complex64).cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    with Plan(M, nb, L, N_R) as plan:
+        pts = {str(s): _point(plan, h, float(s), gen) for s in SNRS}
+    return {"M": M, "N_batch": nb, "L": L, "L_nz": lnz, "frames": F, "mae": pts}
+
+
+def fig4(iters: int) -> list:
+    return [_curve(M, nb, 64, 64, iters, 100 + 10 * nb + M % 7)
+            for M in (511, 2047) for nb in (1, 2, 4)]
+
+
+def fig5(iters: int) -> list:
+    return [_curve(2047, 4, 128, lnz, iters, 200 + lnz) for lnz in (1, 4, 16, 64, 128)]
+
+
+def table(curves: list, label) -> str:
+    """Markdown: one row per (curve, method), one column per SNR."""
+    head = "| " + " | ".join(["curve", "method"] + [f"{s} dB" for s in SNRS]) + " |"
+    sep = "|" + "---|" * (len(SNRS) + 2)
+    rows = [head, sep]
+    for c in curves:
+        for m in METHODS:
+            vals = [f"{c['mae'][str(s)][m]:.2e}" for s in SNRS]
+            rows.append("| " + " | ".join([label(c), m] + vals) + " |")
+    return "\n".join(rows)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    res = {"fig4": fig4(args.iters), "fig5": fig5(args.iters), "iters": args.iters,
+           "snr_db": list(SNRS), "methods": list(METHODS)}
+    text = json.dumps(res)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text, flush=True)
+    print(table(res["fig4"], lambda c: f"M={c['M']} Nb={c['N_batch']}"), file=sys.stderr)
+    print(table(res["fig5"], lambda c: f"Lnz={c['L_nz']}"), file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()

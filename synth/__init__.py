@@ -141,3 +141,20 @@ def device_draws(cfg: Config, torch, device="cuda", frames=None, seed_offset=100
                       torch.randn((F, cfg.R, cfg.N), generator=g, device=device))
     w = w / (2.0 ** 0.5)
     return {"snr_db": snr, "h": h, "w": w}
+
+
+def sparse_taps(shape, L: int, lnz: int, n_tx: int, seed: int) -> np.ndarray:
+    """The sparse-tap channel of Section II: within an L-tap CIR, lnz taps at
+    positions drawn uniformly without replacement, each CN(0, p) with
+    p = 1 / (n_tx * sqrt(lnz)), the others zero. shape = leading dims
+    (e.g. [frames, R, T]); returns complex128 [*shape, L]. Draw order: the
+    positions of every CIR, then real parts, then imaginary parts."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    keys = rng.random((n, L))
+    pos = np.argsort(keys, axis=1)[:, :lnz]          # lnz distinct positions per CIR
+    p = 1.0 / (n_tx * np.sqrt(lnz))
+    vals = (rng.standard_normal((n, lnz)) + 1j * rng.standard_normal((n, lnz))) * np.sqrt(p / 2)
+    h = np.zeros((n, L), dtype=np.complex128)
+    np.put_along_axis(h, pos, vals, axis=1)
+    return h.reshape(*shape, L)
