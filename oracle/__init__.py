@@ -7,10 +7,16 @@ never imports it; the GPU library never imports this package.
 What it computes, each function citing the passage it follows:
 
 * ``mseq``        m-sequence (Section II-A, Eq. 1) -- C, own LFSR.
+* ``mseq_mask`` / ``primitive_masks``  the m-sequence of any feedback
+                  polynomial, and every primitive one of a degree (the
+                  per-cell sequences of Section II-B) -- C, own LFSR.
+* ``lags``        the lag each estimated tap sits at: adjacent blocks of L, or
+                  Eq. 8's shifts floor(N/T)*t.
 * ``correlate``   correlator at the T*L multiplexed lags (Eq. 3, Eq. 10) -- C.
 * ``adjoint``     its transpose, circular convolution with the sequence -- C.
-* ``received``    multiplexed receive model y = sum_t s shifted by t*L, convolved
-                  with h_t, plus noise (Eq. 6 / Eq. 9) -- numpy FFT.
+* ``received``    multiplexed receive model y = sum_t s shifted by the
+                  transmitter's lag, convolved with h_t, plus noise
+                  (Eq. 6 / Eq. 9) -- numpy FFT.
 * ``refine``      least-squares refinement iterates built from the two above.
 * ``loss_grad``   ||y - P h||^2 and its gradient.
 * ``quantize`` / ``dequantize``  the reduced-precision storage of Y with a
@@ -45,10 +51,13 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     c_dp = ctypes.POINTER(ctypes.c_double)
     c_sp = ctypes.POINTER(ctypes.c_byte)
+    c_ip = ctypes.POINTER(ctypes.c_int)
     lib.oracle_mseq.argtypes = [ctypes.c_int, c_sp]
     lib.oracle_mseq.restype = ctypes.c_int
+    lib.oracle_mseq_mask.argtypes = [ctypes.c_int, ctypes.c_uint, c_sp]
+    lib.oracle_mseq_mask.restype = ctypes.c_int
     for fn in (lib.oracle_correlate, lib.oracle_adjoint):
-        fn.argtypes = [c_dp, c_sp, ctypes.c_int, ctypes.c_int, ctypes.c_long,
+        fn.argtypes = [c_dp, c_sp, ctypes.c_int, c_ip, ctypes.c_int, ctypes.c_long,
                        ctypes.c_int, c_dp]
         fn.restype = None
     lib.oracle_threads.argtypes = []
@@ -63,6 +72,10 @@ def _dp(a):
 
 def _sp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_byte))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
 
 
 def threads() -> int:
@@ -83,6 +96,48 @@ def mseq(d: int) -> np.ndarray:
     return s
 
 
+def mseq_mask(d: int, mask: int):
+    """m-sequence of the feedback polynomial x^d + sum_{bit i of mask} x^i.
+
+    Same recurrence, start state and +-1 mapping as ``mseq``. Returns the
+    int8 +-1 sequence of length 2^d - 1, or None when the polynomial is not
+    primitive (the bits do not repeat with period exactly 2^d - 1).
+    """
+    N = (1 << d) - 1
+    s = np.zeros(N, dtype=np.int8)
+    got = _load().oracle_mseq_mask(int(d), int(mask), _sp(s))
+    if got < 0:
+        raise ValueError(f"degree {d} outside [2, 16] or mask {mask:#x} has bits >= d")
+    return s if got == N else None
+
+
+def primitive_masks(d: int) -> list:
+    """Every feedback mask of degree d whose sequence is maximal length, by
+    trying all 2^d masks (the candidate sequences of the cells of Section
+    II-B)."""
+    return [m for m in range(1 << d) if mseq_mask(d, m) is not None]
+
+
+def lags(N: int, T: int, L: int, spacing: str = "contiguous") -> np.ndarray:
+    """Lag of estimated tap k = t*L + l (transmitter t, tap l), int32 [T*L].
+
+    "contiguous": t*L + l, the transmitters' blocks adjacent.
+    "eq8":        floor(N/T)*t + l, the circular shift of Eq. 8 with the
+                  non-integer N/T taken down to an integer, which leaves
+                  floor(N/T) - L guard lags after every block. Needs
+                  T*L <= N (Eq. 7) so that blocks do not overlap.
+    """
+    t = np.repeat(np.arange(T, dtype=np.int64), L)
+    l = np.tile(np.arange(L, dtype=np.int64), T)
+    if spacing == "contiguous":
+        return (t * L + l).astype(np.int32)
+    if spacing == "eq8":
+        if T * L > N:
+            raise ValueError("Eq. 8 spacing needs T*L <= N")
+        return ((N // T) * t + l).astype(np.int32)
+    raise ValueError(spacing)
+
+
 def degree_of(N: int) -> int:
     d = int(N + 1).bit_length() - 1
     if (1 << d) - 1 != N:
@@ -100,35 +155,46 @@ def _as_c128(x, ndim):
     return x
 
 
-def correlate(Y, s, K: int) -> np.ndarray:
-    """H[b,r,k] = (1/N) sum_n Y[b,r,n] s[(n-k) mod N], k < K (Eq. 3, Eq. 10).
+def _lag_array(K: int, lag) -> np.ndarray:
+    lag = np.arange(K, dtype=np.int32) if lag is None else np.ascontiguousarray(lag, np.int32)
+    if lag.shape != (K,):
+        raise ValueError("one lag per estimated tap expected")
+    return lag
 
-    Y: [B, R, N] complex. Returns [B, R, K] complex128. The CIR of
-    transmitter t sits at H[..., t*L:(t+1)*L] (the de-multiplexing of Eq. 10).
+
+def correlate(Y, s, K: int, lag=None) -> np.ndarray:
+    """H[b,r,k] = (1/N) sum_n Y[b,r,n] s[(n-lag[k]) mod N], k < K (Eq. 3, Eq. 10).
+
+    Y: [B, R, N] complex; lag: [K] ints (default k, the adjacent blocks).
+    Returns [B, R, K] complex128. The CIR of transmitter t sits at
+    H[..., t*L:(t+1)*L] (the de-multiplexing of Eq. 10).
     """
     Y = _as_c128(Y, 3)
     s = np.ascontiguousarray(s, dtype=np.int8)
     B, R, N = Y.shape
     if s.shape != (N,):
         raise ValueError("sequence length does not match Y")
+    lag = _lag_array(int(K), lag)
     H = np.empty((B, R, K), dtype=np.complex128)
-    _load().oracle_correlate(_dp(Y.view(np.float64)), _sp(s), N, int(K), B, R,
+    _load().oracle_correlate(_dp(Y.view(np.float64)), _sp(s), N, _ip(lag), int(K), B, R,
                              _dp(H.view(np.float64)))
     return H
 
 
-def adjoint(G, s) -> np.ndarray:
-    """A[b,r,n] = (1/N) sum_k G[b,r,k] s[(n-k) mod N]: transpose of correlate.
+def adjoint(G, s, lag=None) -> np.ndarray:
+    """A[b,r,n] = (1/N) sum_k G[b,r,k] s[(n-lag[k]) mod N]: transpose of correlate.
 
-    G: [B, R, K] complex. Returns [B, R, N] complex128. N * adjoint(h) is the
-    noiseless multiplexed received frame of Eq. 9 for stacked CIRs h.
+    G: [B, R, K] complex; lag as in ``correlate``. Returns [B, R, N]
+    complex128. N * adjoint(h) is the noiseless multiplexed received frame of
+    Eq. 9 for stacked CIRs h.
     """
     G = _as_c128(G, 3)
     s = np.ascontiguousarray(s, dtype=np.int8)
     B, R, K = G.shape
     N = s.shape[0]
+    lag = _lag_array(K, lag)
     A = np.empty((B, R, N), dtype=np.complex128)
-    _load().oracle_adjoint(_dp(G.view(np.float64)), _sp(s), N, K, B, R,
+    _load().oracle_adjoint(_dp(G.view(np.float64)), _sp(s), N, _ip(lag), K, B, R,
                            _dp(A.view(np.float64)))
     return A
 
@@ -136,26 +202,30 @@ def adjoint(G, s) -> np.ndarray:
 # --------------------------------------------------------------------------
 # Receive model (Eq. 6 / Eq. 9), used to build test inputs
 # --------------------------------------------------------------------------
-def received(s, h, w, snr_db):
+def received(s, h, w, snr_db, shifts=None):
     """Noisy multiplexed frame y = P h_stack + sigma * w  (Eq. 9).
 
-    s: [N] +-1; h: [B, R, T, L] complex CIRs; w: [B, R, N] unit-variance
-    complex noise; snr_db: [B] receive SNR per frame. Transmitter t sends the
-    sequence delayed by t*L (shift rule of Eq. 8 with spacing L), so its
-    taps occupy lags t*L ... t*L+L-1 and the stacked CIR is h_stack[k] with
-    k = t*L + l. The clean frame is the circular convolution of the sequence
-    with h_stack, computed with numpy's FFT. sigma^2 is the mean clean power
-    of the frame divided by 10^(SNR/10). Returns (y, y_clean), complex128.
+    s: [N] +-1; h: [B, R, T, Lh] complex CIRs; w: [B, R, N] unit-variance
+    complex noise; snr_db: [B] receive SNR per frame; shifts: [T] circular
+    shift of each transmitter's copy of the sequence (default t*Lh, adjacent
+    blocks; Eq. 8's floor(N/T)*t otherwise). Transmitter t sends the sequence
+    delayed by shifts[t], so its taps occupy lags shifts[t] ... shifts[t]+Lh-1.
+    The clean frame is the sum over transmitters of the circular convolution
+    of the delayed sequence with h_t, computed with numpy's FFT. sigma^2 is
+    the mean clean power of the frame divided by 10^(SNR/10). Returns
+    (y, y_clean), complex128.
     """
     s = np.asarray(s, dtype=np.float64)
     N = s.shape[0]
     h = np.asarray(h, dtype=np.complex128)
     B, R, T, L = h.shape
-    K = T * L
+    if shifts is None:
+        shifts = [t * L for t in range(T)]
     hs = np.zeros((B, R, N), dtype=np.complex128)
     # lags beyond N wrap around (they alias when T*L > N)
-    for k in range(K):
-        hs[:, :, k % N] += h.reshape(B, R, K)[:, :, k]
+    for t in range(T):
+        for l in range(L):
+            hs[:, :, (shifts[t] + l) % N] += h[:, :, t, l]
     y_clean = np.fft.ifft(np.fft.fft(hs, axis=-1) * np.fft.fft(s), axis=-1)
     p = np.mean(np.abs(y_clean) ** 2, axis=(1, 2))
     sigma = np.sqrt(p / 10.0 ** (np.asarray(snr_db, dtype=np.float64) / 10.0))
@@ -166,7 +236,7 @@ def received(s, h, w, snr_db):
 # --------------------------------------------------------------------------
 # a6: least-squares refinement, and the loss it descends
 # --------------------------------------------------------------------------
-def refine(y, s, K: int, steps: int):
+def refine(y, s, K: int, steps: int, lag=None):
     """Iterates x_0 = H(y), x_{j+1} = x_j + H(y - N A(x_j)), j < steps.
 
     H is ``correlate`` and N A(x) = P x is ``adjoint`` times N, so each step
@@ -176,32 +246,33 @@ def refine(y, s, K: int, steps: int):
     """
     y = _as_c128(y, 3)
     N = y.shape[2]
-    x = correlate(y, s, K)
+    x = correlate(y, s, K, lag)
     out = [x]
     for _ in range(steps):
-        r = y - N * adjoint(x, s)
-        x = x + correlate(r, s, K)
+        r = y - N * adjoint(x, s, lag)
+        x = x + correlate(r, s, K, lag)
         out.append(x)
     return out
 
 
-def loss_grad(y, s, x):
+def loss_grad(y, s, x, lag=None):
     """Loss ||y - P x||^2 summed over all frames and antennas, and its
     gradient in PyTorch's convention for a real loss of complex x
     (dL/d(re) + i dL/d(im)), which is -2 P^T (y - P x) = -2N H(y - P x)."""
     y = _as_c128(y, 3)
     x = _as_c128(x, 3)
     N = y.shape[2]
-    r = y - N * adjoint(x, s)
+    r = y - N * adjoint(x, s, lag)
     loss = float(np.sum(np.abs(r) ** 2))
-    grad = -2.0 * N * correlate(r, s, x.shape[2])
+    grad = -2.0 * N * correlate(r, s, x.shape[2], lag)
     return loss, grad
 
 
 def ls_closed_form(H, N: int):
     """Least-squares CIR from a correlator output when T*L <= N.
 
-    The sequence's two-level autocorrelation (Eq. 1) gives
+    The sequence's two-level autocorrelation (Eq. 1) gives, for any K
+    distinct lags (adjacent or Eq. 8's),
     P^T P = (N+1) I - J (J all-ones), whose inverse is
     (I + J/(N+1-K)) / (N+1). With H = P^T y / N this yields
     x_LS = N/(N+1) * (H + sum(H)/(N+1-K)), the sum over the K lags of a row.

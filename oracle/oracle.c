@@ -69,6 +69,46 @@ int oracle_mseq(int d, signed char *s)
     return N;
 }
 
+/*
+ * m-sequence of Section II-A from any feedback polynomial: the same
+ * recurrence and start as oracle_mseq, with the taps given as a mask (bit i
+ * set for each exponent i < d of x^d + sum x^i). Different primitive
+ * polynomials of one degree give the distinct sequences that neighbouring
+ * cells may use (Section II-B). Returns N when the bits repeat with period
+ * exactly N = 2^d - 1 (the polynomial is primitive: maximal length), 0 when
+ * they do not (s is then unspecified), -1 for d outside [2, 16] or a mask
+ * with a bit at or above d. s must hold N entries.
+ */
+int oracle_mseq_mask(int d, unsigned mask, signed char *s)
+{
+    if (d < 2 || d > 16 || (mask >> d) != 0)
+        return -1;
+    int N = (1 << d) - 1;
+    unsigned char b[(1 << 16) + 16];
+    memset(b, 0, sizeof(b));
+    b[0] = 1;
+    for (int n = 0; n < N; ++n) {
+        unsigned char x = 0;
+        for (int i = 0; i < d; ++i)
+            if ((mask >> i) & 1u)
+                x ^= b[n + i];
+        b[n + d] = x;
+    }
+    /* the d-bit window at n equals the start window 1,0,...,0 first at n = N */
+    for (int n = 1; n <= N; ++n) {
+        int same = 1;
+        for (int i = 0; i < d && same; ++i)
+            same = b[n + i] == b[i];
+        if (same && n < N)
+            return 0;
+        if (!same && n == N)
+            return 0;
+    }
+    for (int n = 0; n < N; ++n)
+        s[n] = b[n] ? -1 : 1;
+    return N;
+}
+
 /* (a mod N) in [0, N) for any integer a. */
 static int oracle_mod(long a, int N)
 {
@@ -78,15 +118,16 @@ static int oracle_mod(long a, int N)
 
 /*
  * Correlator of Eq. 3 / Eq. 10, restricted to the K = T*L lags that the
- * multiplexed transmitters occupy (Section II-B):
+ * multiplexed transmitters occupy (Section II-B); output column k holds lag
+ * lag[k] (k itself for adjacent blocks of L lags, Eq. 8's shifts otherwise):
  *
- *   H[b][r][k] = (1/N) * sum_{n=0}^{N-1} Y[b][r][n] * s[(n - k) mod N]
+ *   H[b][r][k] = (1/N) * sum_{n=0}^{N-1} Y[b][r][n] * s[(n - lag[k]) mod N]
  *
  * Y: [B][R][N] complex, H: [B][R][K] complex. The sum runs in natural n order
  * and the 1/N is applied once at the end.
  */
-void oracle_correlate(const double *Y, const signed char *s, int N, int K,
-                      long B, int R, double *H)
+void oracle_correlate(const double *Y, const signed char *s, int N,
+                      const int *lag, int K, long B, int R, double *H)
 {
     long rows = B * (long)R;
 #pragma omp parallel for schedule(static)
@@ -96,7 +137,7 @@ void oracle_correlate(const double *Y, const signed char *s, int N, int K,
         for (int k = 0; k < K; ++k) {
             double re = 0.0, im = 0.0;
             for (int n = 0; n < N; ++n) {
-                double p = (double)s[oracle_mod((long)n - k, N)];
+                double p = (double)s[oracle_mod((long)n - lag[k], N)];
                 re += y[2 * n] * p;
                 im += y[2 * n + 1] * p;
             }
@@ -110,13 +151,13 @@ void oracle_correlate(const double *Y, const signed char *s, int N, int K,
  * Adjoint (transpose) of the correlator: a circular convolution of the
  * lag-domain input with the sequence,
  *
- *   A[b][r][n] = (1/N) * sum_{k=0}^{K-1} G[b][r][k] * s[(n - k) mod N]
+ *   A[b][r][n] = (1/N) * sum_{k=0}^{K-1} G[b][r][k] * s[(n - lag[k]) mod N]
  *
  * G: [B][R][K] complex, A: [B][R][N] complex. With G the stacked CIRs and the
  * 1/N removed this is the noiseless multiplexed receive model of Eq. 9.
  */
-void oracle_adjoint(const double *G, const signed char *s, int N, int K,
-                    long B, int R, double *A)
+void oracle_adjoint(const double *G, const signed char *s, int N,
+                    const int *lag, int K, long B, int R, double *A)
 {
     long rows = B * (long)R;
 #pragma omp parallel for schedule(static)
@@ -126,7 +167,7 @@ void oracle_adjoint(const double *G, const signed char *s, int N, int K,
         for (int n = 0; n < N; ++n) {
             double re = 0.0, im = 0.0;
             for (int k = 0; k < K; ++k) {
-                double p = (double)s[oracle_mod((long)n - k, N)];
+                double p = (double)s[oracle_mod((long)n - lag[k], N)];
                 re += g[2 * k] * p;
                 im += g[2 * k + 1] * p;
             }

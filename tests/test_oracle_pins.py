@@ -318,3 +318,167 @@ def test_synth_is_deterministic_and_normalised():
     assert np.array_equal(f3["h"][0], synth.frame_draws(synth.FP32, 3)[1])
     shp = synth.varlen_shapes(64)
     assert np.all(shp[:, 2] * shp[:, 3] <= (1 << shp[:, 1]) - 1)
+
+
+# ------------------------------- per-cell sequences and Eq. 8 lag spacing
+def _totient(n):
+    r, m, p = n, n, 2
+    while p * p <= m:
+        if m % p == 0:
+            while m % p == 0:
+                m //= p
+            r -= r // p
+        p += 1
+    if m > 1:
+        r -= r // m
+    return r
+
+
+def _is_shift(u, v):
+    """True when v is a circular shift of u."""
+    return any(np.array_equal(np.roll(u, k), v) for k in range(u.size))
+
+
+@pytest.mark.parametrize("d", list(range(2, 11)))
+def test_primitive_polynomial_count(d):
+    """There are phi(2^d - 1)/d primitive binary polynomials of degree d, so
+    as many feedback masks give maximal-length sequences."""
+    assert len(oracle.primitive_masks(d)) == _totient((1 << d) - 1) // d
+
+
+@pytest.mark.parametrize("d", [5, 7, 8])
+def test_every_primitive_mask_has_two_level_autocorrelation(d):
+    """Eq. 1 holds for every cell's sequence, not only the default one."""
+    N = (1 << d) - 1
+    for m in oracle.primitive_masks(d):
+        s = oracle.mseq_mask(d, m).astype(np.float64)
+        assert np.sum(s == -1) == (N + 1) // 2
+        ac = np.real(np.fft.ifft(np.abs(np.fft.fft(s)) ** 2))
+        assert abs(ac[0] - N) < 1e-6 and np.max(np.abs(ac[1:] + 1.0)) < 1e-6
+
+
+@pytest.mark.parametrize("d", list(range(2, 11)))
+def test_default_sequence_is_a_primitive_mask_sequence(d):
+    seqs = [oracle.mseq_mask(d, m) for m in oracle.primitive_masks(d)]
+    assert any(np.array_equal(oracle.mseq(d), s) for s in seqs)
+
+
+@pytest.mark.parametrize("d", [5, 7, 10])
+def test_reciprocal_polynomial_reverses_the_sequence(d):
+    """x^d f(1/x) generates the time-reversed m-sequence (up to a shift)."""
+    for m in oracle.primitive_masks(d)[:6]:
+        rec = 1 | sum(1 << (d - i) for i in range(1, d) if (m >> i) & 1)
+        s, r = oracle.mseq_mask(d, m), oracle.mseq_mask(d, rec)
+        assert r is not None and _is_shift(s[::-1].copy(), r)
+
+
+@pytest.mark.parametrize("d", [5, 7, 9])
+def test_decimation_by_three_gives_a_preferred_pair(d):
+    """Gold: for odd d the sequence decimated by 3 is another cell's
+    m-sequence and the pair's cross-correlation takes only the three values
+    -1, -t, t - 2 with t = 2^((d+1)/2) + 1."""
+    N = (1 << d) - 1
+    s = oracle.mseq(d).astype(np.int64)
+    u = s[(3 * np.arange(N)) % N]
+    owners = [m for m in oracle.primitive_masks(d)
+              if _is_shift(oracle.mseq_mask(d, m).astype(np.int64), u)]
+    assert len(owners) == 1 and oracle.mseq_mask(d, owners[0]) is not None
+    cc = np.rint(np.real(np.fft.ifft(np.conj(np.fft.fft(s)) * np.fft.fft(u)))).astype(int)
+    t = (1 << ((d + 1) // 2)) + 1
+    assert set(cc.tolist()) == {-1, -t, t - 2}
+
+
+def test_mseq_mask_rejects_non_primitive_and_bad_masks():
+    assert oracle.mseq_mask(4, 0xF) is None        # x^4+x^3+x^2+x+1: period 5
+    assert oracle.mseq_mask(5, 0x0) is None        # x^5: not invertible
+    assert oracle.mseq_mask(6, 0x9) is None        # x^6+x^3+1: irreducible, order 9
+    with pytest.raises(ValueError):
+        oracle.mseq_mask(5, 1 << 5)
+    with pytest.raises(ValueError):
+        oracle.mseq_mask(1, 1)
+
+
+@pytest.mark.parametrize("N,T,L", [(31, 3, 7), (127, 4, 16), (1023, 16, 32), (255, 7, 36)])
+def test_eq8_lags_are_distinct_blocks_with_guards(N, T, L):
+    lag = oracle.lags(N, T, L, "eq8").reshape(T, L)
+    D = N // T
+    assert np.array_equal(lag[:, 0], D * np.arange(T))
+    assert np.array_equal(np.diff(lag, axis=1), np.ones((T, L - 1)))
+    assert len(np.unique(lag % N)) == T * L                     # no overlap
+    assert np.all(lag[1:, 0] - lag[:-1, -1] - 1 == D - L)        # guard lags
+    assert np.array_equal(oracle.lags(N, 1, L, "eq8"), oracle.lags(N, 1, L))
+    with pytest.raises(ValueError):
+        oracle.lags(N, T, N // T + 1, "eq8")
+
+
+@pytest.mark.parametrize("d,T,L", [(5, 3, 7), (7, 4, 16), (8, 5, 40)])
+def test_correlate_and_adjoint_at_eq8_lags_equal_dense_products(d, T, L):
+    """Column k of P is the sequence delayed by lag k (np.roll)."""
+    s = oracle.mseq(d)
+    N = s.size
+    lag = oracle.lags(N, T, L, "eq8")
+    P = np.stack([np.roll(s.astype(np.float64), int(k)) for k in lag], axis=1)
+    Y = rand_c((2, 3, N), 41)
+    G = rand_c((2, 3, T * L), 42)
+    assert np.max(np.abs(oracle.correlate(Y, s, T * L, lag) - Y @ P / N)) < 1e-13
+    assert np.max(np.abs(oracle.adjoint(G, s, lag) - G @ P.T / N)) < 1e-13
+
+
+@pytest.mark.parametrize("spacing", ["contiguous", "eq8"])
+def test_noiseless_least_squares_recovers_channel_at_any_spacing(spacing):
+    """Eq. 9 with each transmitter's shift, then the correlator at the same
+    lags and the closed-form inverse of P^T P: the CIRs come back exactly,
+    for any set of distinct lags."""
+    s = oracle.mseq(7)
+    N = s.size
+    T, L = 5, 12
+    lag = oracle.lags(N, T, L, spacing)
+    h = rand_c((1, 3, T, L), 43)
+    y, _ = oracle.received(s, h, np.zeros((1, 3, N)), np.array([400.0]),
+                           shifts=lag.reshape(T, L)[:, 0])
+    x = oracle.ls_closed_form(oracle.correlate(y, s, T * L, lag), N)
+    assert np.max(np.abs(x - h.reshape(1, 3, T * L))) < 1e-12
+
+
+def test_eq8_guard_lags_absorb_channel_tails():
+    """A channel longer than L: with adjacent blocks the tail of transmitter
+    0 lands on transmitter 1's first taps; with Eq. 8's shifts it falls in
+    the guard lags, and transmitter 1 only sees the -1/N floor of Eq. 1."""
+    s = oracle.mseq(8)
+    N = s.size
+    T, L, tail = 4, 16, 8
+    h = np.zeros((1, 1, T, L + tail), dtype=np.complex128)
+    h[0, 0, 0, L:] = 1.0                                         # taps past L
+    for spacing in ("contiguous", "eq8"):
+        lag = oracle.lags(N, T, L, spacing)
+        y, _ = oracle.received(s, h, np.zeros((1, 1, N)), np.array([400.0]),
+                               shifts=lag.reshape(T, L)[:, 0])
+        H = oracle.correlate(y, s, T * L, lag).reshape(T, L)
+        leak = np.max(np.abs(H[1, :tail]))
+        if spacing == "contiguous":                              # the tap, less
+            assert abs(leak - (1.0 - (tail - 1) / N)) < 1e-12    # the others' floor
+        else:
+            assert abs(leak - tail / N) < 1e-12
+
+
+def test_other_cell_interference_is_bounded_by_cross_correlation():
+    """A receiver of cell A hears cell B (a preferred pair): the correlator
+    sees B's CIR through the cross-correlation, so each estimated tap is at
+    most max|C_AB| / N times the sum of B's tap magnitudes, and equals the
+    circular cross-correlation of the two sequences weighted by B's taps."""
+    d = 7
+    N = (1 << d) - 1
+    sa = oracle.mseq(d)
+    sb = sa[(3 * np.arange(N)) % N].copy()                       # other cell
+    T, L = 4, 8
+    hb = rand_c((1, 2, T, L), 44)
+    y, _ = oracle.received(sb, hb, np.zeros((1, 2, N)), np.array([400.0]))
+    H = oracle.correlate(y, sa, T * L)
+    cab = np.real(np.fft.ifft(np.conj(np.fft.fft(sa.astype(float))) * np.fft.fft(sb.astype(float))))
+    bound = np.max(np.abs(cab)) / N * np.sum(np.abs(hb), axis=(2, 3))
+    assert np.all(np.max(np.abs(H), axis=-1) <= bound + 1e-12)
+    # H_A[k] = (1/N) sum_j hb[j] C_AB(k - j)  (j over B's stacked lags)
+    hbs = hb.reshape(1, 2, T * L)
+    k = np.arange(T * L)
+    C = cab[(k[:, None] - k[None, :]) % N]                       # [k, j]
+    assert np.max(np.abs(H - hbs @ C.T / N)) < 1e-12
