@@ -46,8 +46,8 @@ ROTATE_COPIES = 5              # frame / CIR buffer copies the timed steps rotat
 # HBM bytes per launch of the bf16 estimate measured with rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
 # for the kernel source with this sha256; any other source reports null.
-TRAFFIC = {"source_sha256": "5d8bb275bde82804e369669e76f81afa956b2325286f733647636cca0696cd53",
-           "bytes_per_launch": 203428849}
+TRAFFIC = {"source_sha256": "73630f8e32e7f679a7c0e8960daa3564fa2064ee16385555b621ecdb70b6a0a6",
+           "bytes_per_launch": 203654303}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 / f16 matrix
 FP8_PEAK_TFLOPS = 5033.2       # dense fp8 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix
@@ -201,8 +201,46 @@ def other_rows(plan, cfg, y, H, torch, args):
     ms, _ = time_steps(lambda: plan.refine(y, X, 1, work=work), max(2, args.steps // 4), 1, torch)
     res["refine_1_step"] = {"ms": ms, "note": "FP64-accumulated residual + f32s correlation"}
     del q, Hq, A, X, work
+    res["eq8_lags"] = eq8_lags(cfg, y, H, res, torch, args)
     res["uneven_batch"] = uneven_batch(torch, args)
     return res
+
+
+def eq8_lags(cfg, y, H, res, torch, args):
+    """The same frames on a plan with Eq. 8's lags (transmitter t at
+    floor(N/T)*t) and another cell's m-sequence: correlator, LS rows and
+    adjoint, against the adjacent-lag plan's rows above."""
+    from paper_2206_05506_amd import Plan
+    d = cfg.d
+    fb = next(m for m in range((1 << d) - 1, 0, -1)
+              if m & 1 and _is_primitive(d, m))
+    p8 = Plan(cfg.N, cfg.T, cfg.L, cfg.R, feedback=fb, spacing="eq8")
+    Hb = torch.empty_like(H)
+    ms_b, _ = time_steps(lambda: p8.estimate(y, "bf16", out=Hb), args.steps, 2, torch)
+    ms_l, _ = time_steps(lambda: p8.estimate_ls(y, "bf16", out=Hb), args.steps, 2, torch)
+    A = torch.empty_like(y)
+    ms_a, _ = time_steps(lambda: p8.adjoint(H, "f32s", out=A), args.steps, 2, torch)
+    lag = p8.lags()
+    p8.close()
+    del Hb, A
+    return {"feedback": fb, "lag_step": int(lag[cfg.L]) if cfg.T > 1 else 0,
+            "estimate_bf16_ms": ms_b, "estimate_ls_bf16_ms": ms_l, "adjoint_f32s_ms": ms_a,
+            "adjoint_vs_adjacent": ms_a / res["adjoint_f32s"]["ms"],
+            "note": "adjoint reduces over the lag span (T-1)*floor(N/T)+L with zeros in the "
+                    "guard lags: same HBM bytes, more matrix work"}
+
+
+def _is_primitive(d, mask):
+    """Maximal-length test of a feedback mask (the LFSR state returns to its
+    start after exactly 2^d - 1 steps), for choosing a cell's polynomial."""
+    N = (1 << d) - 1
+    w = 1
+    for n in range(1, N + 1):
+        fb = bin(w & mask).count("1") & 1
+        w = (w >> 1) | (fb << (d - 1))
+        if w == 1:
+            return n == N
+    return False
 
 
 def uneven_batch(torch, args):

@@ -16,6 +16,13 @@
  * view H[b][r][t*L : (t+1)*L] (Eq. 10). The library never stores P: the
  * kernels expand it from the sequence bits on chip.
  *
+ * Plans made by pnce_create_ex may instead delay transmitter t by
+ * floor(N/T)*t samples (Eq. 8's circular shift, PNCE_LAGS_EQ8): column
+ * k = t*L + l of H then holds lag lag(k) = floor(N/T)*t + l, P[n][k] =
+ * s[(n - lag(k)) mod N], and every "k" in the formulas below reads lag(k).
+ * They may also use another primitive polynomial, i.e. another m-sequence of
+ * the same length, as a neighbouring cell would (Section II-B).
+ *
  * Conventions for every entry point
  *  - Tensor pointers are DEVICE memory owned by the caller, dense row-major,
  *    with the shapes stated per call. Complex numbers are interleaved
@@ -69,6 +76,11 @@ typedef int pnce_status;
 #define PNCE_FMT_F16 2
 #define PNCE_FMT_E4M3 3   /* OCP e4m3fn, saturating at +-448 */
 
+/* Where transmitter t's L lags sit (the circular shift of its sequence). */
+#define PNCE_LAGS_ADJACENT 0 /* t*L + l: blocks side by side, K = T*L lags    */
+#define PNCE_LAGS_EQ8 1      /* floor(N/T)*t + l: Eq. 8, with floor(N/T) - L  */
+                             /* guard lags after each block                   */
+
 /*
  * Create a plan for sequence length N, T multiplexed transmitters, L taps
  * and R receive antennas (Sections II-A, II-B). Builds the m-sequence on the
@@ -82,6 +94,31 @@ typedef int pnce_status;
  * broken) -> PNCE_W_LAG_ALIAS, with a valid plan. On error *plan = NULL.
  */
 pnce_status pnce_create(pnce_plan **plan, int N, int T, int L, int R);
+
+/*
+ * pnce_create with a choice of sequence and lag layout (Section II-B, Eq. 8).
+ * feedback: 0 for the built-in polynomial, else the taps of the feedback
+ *   polynomial x^d + sum_{bit i set} x^i (bits below d; the LFSR computes
+ *   b[n+d] = XOR over set bits i of b[n+i] from the start 1,0,...,0). It must
+ *   be primitive, so that the sequence has length N and the two-level
+ *   autocorrelation of Eq. 1; neighbouring cells take different ones.
+ * spacing: PNCE_LAGS_ADJACENT (as pnce_create) or PNCE_LAGS_EQ8.
+ * Every entry point taking the plan follows its lags (estimate, packed and
+ * cyclic-prefix estimates, least squares, adjoint, refinement).
+ * Errors: as pnce_create, plus -> PNCE_E_INVALID for an unknown spacing,
+ * PNCE_LAGS_EQ8 with T*L > N (Eq. 7: the blocks would overlap), feedback
+ * bits at or above d, or a feedback polynomial that is not primitive.
+ */
+pnce_status pnce_create_ex(pnce_plan **plan, int N, int T, int L, int R, unsigned feedback,
+                           int spacing);
+
+/* The plan's lags as T*L host ints: lags_host[t*L + l] = t*D + l with D = L
+ * (PNCE_LAGS_ADJACENT) or floor(N/T) (PNCE_LAGS_EQ8). */
+pnce_status pnce_get_lags(const pnce_plan *plan, int *lags_host);
+
+/* The feedback taps of the plan's sequence (the built-in ones when the plan
+ * was made with feedback 0). */
+pnce_status pnce_get_feedback(const pnce_plan *plan, unsigned *feedback);
 
 /* Free a plan and its device tables. NULL is a no-op. Synchronous: the
  * caller must not destroy a plan that enqueued work still uses. */

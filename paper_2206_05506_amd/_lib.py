@@ -26,11 +26,15 @@ PNCE_PREC_BF16 = 2
 PNCE_PREC_F64 = 3
 PNCE_PREC_F64ACC = 4
 
+PNCE_LAGS_ADJACENT = 0
+PNCE_LAGS_EQ8 = 1
+
 PNCE_FMT_BF16 = 1
 PNCE_FMT_F16 = 2
 PNCE_FMT_E4M3 = 3
 
-SYMBOLS = ("pnce_create", "pnce_destroy", "pnce_get_sequence", "pnce_get_shape",
+SYMBOLS = ("pnce_create", "pnce_create_ex", "pnce_destroy", "pnce_get_sequence",
+           "pnce_get_lags", "pnce_get_feedback", "pnce_get_shape",
            "pnce_estimate", "pnce_pack", "pnce_estimate_packed", "pnce_adjoint",
            "pnce_refine", "pnce_debias", "pnce_estimate_ls", "pnce_estimate_cp", "pnce_pack_cp",
            "pnce_varlen_create", "pnce_varlen_destroy", "pnce_varlen_estimate",
@@ -62,6 +66,9 @@ def _load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "pnce_create": ([ctypes.POINTER(_P), _I, _I, _I, _I], _I),
+        "pnce_create_ex": ([ctypes.POINTER(_P), _I, _I, _I, _I, ctypes.c_uint, _I], _I),
+        "pnce_get_lags": ([_P, _P], _I),
+        "pnce_get_feedback": ([_P, ctypes.POINTER(ctypes.c_uint)], _I),
         "pnce_destroy": ([_P], _I),
         "pnce_get_sequence": ([_P, _P], _I),
         "pnce_get_shape": ([_P, _P, _P, _P, _P], _I),
@@ -113,6 +120,24 @@ def pnce_create(N: int, T: int, L: int, R: int):
     h = _P()
     st = check(lib.pnce_create(ctypes.byref(h), N, T, L, R), "pnce_create")
     return h, st
+
+
+def pnce_create_ex(N: int, T: int, L: int, R: int, feedback: int, spacing: int):
+    """Returns (plan handle, status); status may be PNCE_W_LAG_ALIAS."""
+    h = _P()
+    st = check(lib.pnce_create_ex(ctypes.byref(h), N, T, L, R, feedback, spacing),
+               "pnce_create_ex")
+    return h, st
+
+
+def pnce_get_lags(plan, out_ptr: int) -> int:
+    return check(lib.pnce_get_lags(plan, out_ptr), "pnce_get_lags")
+
+
+def pnce_get_feedback(plan) -> int:
+    f = ctypes.c_uint()
+    check(lib.pnce_get_feedback(plan, ctypes.byref(f)), "pnce_get_feedback")
+    return f.value
 
 
 def pnce_destroy(plan) -> int:

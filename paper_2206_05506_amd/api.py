@@ -52,13 +52,26 @@ def _need(t: torch.Tensor, shape, dtype, name):
         raise ValueError(f"{name} must be contiguous")
 
 
-class Plan:
-    """A plan for sequence length N, T transmitters, L taps, R antennas."""
+SPACINGS = {"adjacent": _lib.PNCE_LAGS_ADJACENT, "eq8": _lib.PNCE_LAGS_EQ8}
 
-    def __init__(self, N: int, T: int, L: int, R: int):
-        self.handle, self.status = _lib.pnce_create(N, T, L, R)
+
+class Plan:
+    """A plan for sequence length N, T transmitters, L taps, R antennas.
+
+    feedback: taps of another primitive feedback polynomial (0: the built-in
+    one), i.e. another cell's m-sequence; spacing: "adjacent" (transmitter t
+    at lags t*L + l) or "eq8" (lags floor(N/T)*t + l, Eq. 8).
+    """
+
+    def __init__(self, N: int, T: int, L: int, R: int, feedback: int = 0,
+                 spacing: str = "adjacent"):
+        if spacing not in SPACINGS:
+            raise ValueError(f"spacing must be one of {sorted(SPACINGS)}")
+        self.handle, self.status = _lib.pnce_create_ex(N, T, L, R, int(feedback),
+                                                       SPACINGS[spacing])
         self.N, self.T, self.L, self.R = N, T, L, R
         self.K = T * L
+        self.spacing = spacing
         self.lag_alias = self.status == PNCE_W_LAG_ALIAS
 
     def close(self):
@@ -83,6 +96,15 @@ class Plan:
         s = np.zeros(self.N, dtype=np.int8)
         _lib.pnce_get_sequence(self.handle, s.ctypes.data)
         return s
+
+    def lags(self) -> np.ndarray:
+        """Lag of every column of H, int32 [T*L]."""
+        k = np.zeros(self.K, dtype=np.int32)
+        _lib.pnce_get_lags(self.handle, k.ctypes.data)
+        return k
+
+    def feedback(self) -> int:
+        return _lib.pnce_get_feedback(self.handle)
 
     # ---------------------------------------------------------------- a4
     def estimate(self, Y: torch.Tensor, precision: str = "f32s", out=None,

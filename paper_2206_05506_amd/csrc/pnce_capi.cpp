@@ -20,6 +20,9 @@
 
 struct pnce_plan {
   int N, T, L, R, K, d;
+  unsigned feedback;             // taps of the sequence's feedback polynomial
+  int spacing;                   // PNCE_LAGS_*
+  int D;                         // Eq. 8: lag of transmitter t's first tap is t*D
   int device;
   int nbw;                       // words of each periodic bit stream
   std::vector<signed char> seq;  // +-1, N entries
@@ -66,16 +69,20 @@ constexpr uint32_t kFeedback[17] = {
 // m-sequence of degree d (Section II-A, Eq. 1). A d-bit window register
 // holds bits b[n .. n+d-1] (b[n] in bit 0); the next bit is the parity of the
 // window masked by the feedback taps, i.e. b[n+d] = XOR_i b[n+i]. The window
-// starts as 1,0,...,0; bit 0 is sent as +1 and bit 1 as -1.
-std::vector<signed char> make_sequence(int d) {
+// starts as 1,0,...,0; bit 0 is sent as +1 and bit 1 as -1. Empty when the
+// taps do not give a maximal-length sequence (the window returns to its
+// start before N steps, or not after N).
+std::vector<signed char> make_sequence(int d, uint32_t taps) {
   const int N = (1 << d) - 1;
   std::vector<signed char> s(N);
   uint32_t win = 1u;
   for (int n = 0; n < N; ++n) {
+    if (n > 0 && win == 1u) return {};
     s[n] = (win & 1u) ? -1 : 1;
-    const uint32_t fb = (uint32_t)__builtin_parity(win & kFeedback[d]);
+    const uint32_t fb = (uint32_t)__builtin_parity(win & taps);
     win = (win >> 1) | (fb << (d - 1));
   }
+  if (win != 1u) return {};
   return s;
 }
 
@@ -114,12 +121,19 @@ pnce_status check_batch(const pnce_plan *p, int batch) {
 }
 
 // Contraction through the tiled kernels or the FP64 vector kernel.
+struct Segs {
+  int len = 0, lag = 0, poff = 0;  // column segments and sequence shift (TgArgs)
+  int rlen = 0, rlag = 0, rn = 0;  // reduction blocks: rows of lag blocks
+};
+
 pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
                    const void *in, int t_len, int ld_in, void *out, int c_len,
                    const void *cin, const uint32_t *bits, const float *scales,
-                   int batch, double alpha, double beta, bool ls = false) {
+                   int batch, double alpha, double beta, bool ls = false, Segs sg = {}) {
   hipError_t e;
-  if (precision == PNCE_PREC_F64 || (in_fmt == pnce::IN_C64 && t_len < 2)) {
+  // rows of lag blocks: t_len terms spread over (rn-1)*rlag + rlen positions
+  const int positions = sg.rlag ? (sg.rn - 1) * sg.rlag + sg.rlen : t_len;
+  if (precision == PNCE_PREC_F64 || (in_fmt == pnce::IN_C64 && positions < 2)) {
     // FP64 vector kernel: the FP64 path, and complex64 rows of one term
     // (the tiled loaders read sample pairs).
     pnce::Tg64Args a{};
@@ -139,6 +153,11 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.beta = beta;
     a.in_f64 = precision == PNCE_PREC_F64;
     a.out_f64 = precision == PNCE_PREC_F64;
+    a.seg_len = sg.len;
+    a.seg_lag = sg.lag;
+    a.poff = sg.poff;
+    a.rseg_len = sg.rlen;
+    a.rseg_lag = sg.rlag;
     e = pnce::launch_tg64(a, s);
   } else {
     pnce::TgArgs a{};
@@ -149,7 +168,7 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.scales = scales;
     a.R = p->R;
     a.batch = batch;
-    a.t_len = t_len;
+    a.t_len = positions;
     a.ld_in = ld_in;
     a.c_len = c_len;
     a.ld_out = c_len;
@@ -158,11 +177,47 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.alpha = (float)alpha;
     a.beta = (float)beta;
     a.ls = ls ? 1 : 0;
-    e = precision == PNCE_PREC_F64ACC ? pnce::launch_f64mm(a, s)
-                                      : pnce::launch_tg(precision, in_fmt, a, s);
+    a.seg_len = sg.len;
+    a.seg_lag = sg.lag;
+    a.poff = sg.poff;
+    a.rseg_len = sg.rlen;
+    a.rseg_lag = sg.rlag;
+    a.rseg_n = sg.rn;
+    e = precision == PNCE_PREC_F64ACC
+            ? pnce::launch_f64mm(a, s)
+            : pnce::launch_tg(precision, sg.rlag ? pnce::IN_C64_LAGS : in_fmt, a, s);
   }
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return PNCE_OK;
+}
+
+// Correlator direction: the output columns are the plan's T*L lags.
+pnce_status run_fwd(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
+                    const void *in, int t_len, int ld_in, void *out, const void *cin,
+                    const float *scales, int batch, double alpha, double beta,
+                    bool ls = false) {
+  Segs sg;
+  if (p->D != p->L) {  // Eq. 8 with guard lags (D == L is the adjacent layout)
+    sg.len = p->L;
+    sg.lag = p->D;
+  }
+  return run_tg(p, s, precision, in_fmt, in, t_len, ld_in, out, p->K, cin, p->d_fwd, scales,
+                batch, alpha, beta, ls, sg);
+}
+
+// Adjoint direction: the reduction runs over the plan's lags. With Eq. 8's
+// spacing the rows are read as lag blocks (transmitter t's L terms at lags
+// t*D ...), zero in the guard lags, so one contraction covers them all.
+pnce_status run_adj(const pnce_plan *p, hipStream_t s, int precision, const void *in,
+                    void *out, const void *cin, int batch, double alpha, double beta) {
+  Segs sg;
+  if (p->D != p->L) {
+    sg.rlen = p->L;
+    sg.rlag = p->D;
+    sg.rn = p->T;
+  }
+  return run_tg(p, s, precision, pnce::IN_C64, in, p->K, p->K, out, p->N, cin, p->d_rev,
+                nullptr, batch, alpha, beta, false, sg);
 }
 
 }  // namespace
@@ -170,6 +225,11 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
 extern "C" {
 
 pnce_status pnce_create(pnce_plan **plan, int N, int T, int L, int R) {
+  return pnce_create_ex(plan, N, T, L, R, 0u, PNCE_LAGS_ADJACENT);
+}
+
+pnce_status pnce_create_ex(pnce_plan **plan, int N, int T, int L, int R, unsigned feedback,
+                           int spacing) {
   try {
     if (!plan) return fail(PNCE_E_INVALID, "plan output pointer is NULL");
     *plan = nullptr;
@@ -179,6 +239,14 @@ pnce_status pnce_create(pnce_plan **plan, int N, int T, int L, int R) {
     if (N <= 0 || d < 2 || d > 16 || (1 << d) - 1 != N)
       return fail(PNCE_E_UNSUPPORTED, "N must be 2^d - 1 with 2 <= d <= 16");
     if ((long)T * L > 16L * N) return fail(PNCE_E_INVALID, "T*L exceeds 16*N");
+    if (spacing != PNCE_LAGS_ADJACENT && spacing != PNCE_LAGS_EQ8)
+      return fail(PNCE_E_INVALID, "unknown lag spacing");
+    if (spacing == PNCE_LAGS_EQ8 && (long)T * L > N)
+      return fail(PNCE_E_INVALID, "Eq. 8 spacing needs T*L <= N (Eq. 7)");
+    if ((feedback >> d) != 0u) return fail(PNCE_E_INVALID, "feedback taps at or above degree d");
+    const uint32_t taps = feedback ? feedback : kFeedback[d];
+    std::vector<signed char> seq = make_sequence(d, taps);
+    if (seq.empty()) return fail(PNCE_E_INVALID, "feedback polynomial is not primitive");
     if (R > 65535) return fail(PNCE_E_INVALID, "R exceeds 65535");
     const int K = T * L;
     // The kernels address one frame (rows of N or K complex64) with 32-bit
@@ -194,7 +262,10 @@ pnce_status pnce_create(pnce_plan **plan, int N, int T, int L, int R) {
     p->R = R;
     p->K = K;
     p->d = d;
-    p->seq = make_sequence(d);
+    p->feedback = taps;
+    p->spacing = spacing;
+    p->D = spacing == PNCE_LAGS_EQ8 ? N / T : L;
+    p->seq = std::move(seq);
     // Positions read by the kernels stay below N + max(N, K) + 16 * 16 + 64
     // bits (the direct kernel runs up to 16 k-steps past the last one).
     const long bits = (long)N + (K > N ? K : N) + 352;
@@ -255,6 +326,21 @@ pnce_status pnce_get_sequence(const pnce_plan *plan, signed char *s_host) {
   return PNCE_OK;
 }
 
+pnce_status pnce_get_lags(const pnce_plan *plan, int *lags_host) {
+  if (pnce_status st = check_plan(plan)) return st;
+  if (!lags_host) return fail(PNCE_E_INVALID, "output pointer is NULL");
+  for (int t = 0; t < plan->T; ++t)
+    for (int l = 0; l < plan->L; ++l) lags_host[t * plan->L + l] = t * plan->D + l;
+  return PNCE_OK;
+}
+
+pnce_status pnce_get_feedback(const pnce_plan *plan, unsigned *feedback) {
+  if (pnce_status st = check_plan(plan)) return st;
+  if (!feedback) return fail(PNCE_E_INVALID, "output pointer is NULL");
+  *feedback = plan->feedback;
+  return PNCE_OK;
+}
+
 pnce_status pnce_get_shape(const pnce_plan *plan, int *N, int *T, int *L, int *R) {
   if (pnce_status st = check_plan(plan)) return st;
   if (N) *N = plan->N;
@@ -271,8 +357,8 @@ pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y, vo
   if (!Y || !H) return fail(PNCE_E_INVALID, "Y and H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
   if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
-  return run_tg(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
-                plan->K, beta != 0.0 ? H : nullptr, plan->d_fwd, scales, batch, alpha, beta);
+  return run_fwd(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
+                 beta != 0.0 ? H : nullptr, scales, batch, alpha, beta);
 }
 
 pnce_status pnce_debias(const pnce_plan *plan, void *stream, void *H, int batch) {
@@ -296,8 +382,8 @@ pnce_status pnce_estimate_ls(const pnce_plan *plan, void *stream, const void *Y,
     return fail(PNCE_E_INVALID, "estimate_ls precision must be F32, F32S or BF16");
   if (plan->K > plan->N)
     return fail(PNCE_E_UNSUPPORTED, "T*L > N: least squares is not unique");
-  return run_tg(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
-                plan->K, nullptr, plan->d_fwd, scales, batch, 1.0 / plan->N, 0.0, true);
+  return run_fwd(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
+                 nullptr, scales, batch, 1.0 / plan->N, 0.0, true);
 }
 
 pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y, void *Yq,
@@ -330,8 +416,8 @@ pnce_status pnce_estimate_cp(const pnce_plan *plan, void *stream, const void *Y_
   if (pnce_status st = check_cp(plan, cp)) return st;
   const size_t esz = precision == PNCE_PREC_F64 ? 16 : 8;
   const void *Y = (const char *)Y_raw + (size_t)cp * esz;
-  return run_tg(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N + cp, H,
-                plan->K, nullptr, plan->d_fwd, scales, batch, 1.0 / plan->N, 0.0);
+  return run_fwd(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N + cp,
+                 H, nullptr, scales, batch, 1.0 / plan->N, 0.0);
 }
 
 pnce_status pnce_pack_cp(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
@@ -360,8 +446,8 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream, const void
                                               : pnce::IN_E4M3;
   const int Np = plan->N + 1;
   // The zero pad sample is part of the reduction (it contributes nothing).
-  return run_tg(plan, (hipStream_t)stream, pnce::MODE_BF16, in_fmt, Yq, Np, Np, H, plan->K,
-                beta != 0.0 ? H : nullptr, plan->d_fwd, scales, batch, 1.0 / plan->N, beta);
+  return run_fwd(plan, (hipStream_t)stream, pnce::MODE_BF16, in_fmt, Yq, Np, Np, H,
+                 beta != 0.0 ? H : nullptr, scales, batch, 1.0 / plan->N, beta);
 }
 
 pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G, void *A,
@@ -371,8 +457,8 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G, voi
   if (beta != 0.0 && !C) return fail(PNCE_E_INVALID, "C must be non-NULL when beta != 0");
   if (pnce_status st = check_batch(plan, batch)) return st;
   if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
-  return run_tg(plan, (hipStream_t)stream, precision, pnce::IN_C64, G, plan->K, plan->K, A,
-                plan->N, beta != 0.0 ? C : nullptr, plan->d_rev, nullptr, batch, alpha, beta);
+  return run_adj(plan, (hipStream_t)stream, precision, G, A, beta != 0.0 ? C : nullptr, batch,
+                 alpha, beta);
 }
 
 pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void *X,
@@ -385,12 +471,10 @@ pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void
   for (int j = 0; j < steps; ++j) {
     // r = y - P x   (P x = sum_k x[k] s[(n-k) mod N]: adjoint stream, alpha -1)
     const int prec = (j + 1 < steps) ? PNCE_PREC_F32S : PNCE_PREC_F64ACC;
-    if (pnce_status st = run_tg(plan, s, prec, pnce::IN_C64, X, plan->K, plan->K, work, plan->N,
-                                y, plan->d_rev, nullptr, batch, -1.0, 1.0))
-      return st;
+    if (pnce_status st = run_adj(plan, s, prec, X, work, y, batch, -1.0, 1.0)) return st;
     // x = x + P^T r / N
-    if (pnce_status st = run_tg(plan, s, PNCE_PREC_F32S, pnce::IN_C64, work, plan->N, plan->N,
-                                X, plan->K, X, plan->d_fwd, nullptr, batch, 1.0 / plan->N, 1.0))
+    if (pnce_status st = run_fwd(plan, s, PNCE_PREC_F32S, pnce::IN_C64, work, plan->N, plan->N,
+                                 X, X, nullptr, batch, 1.0 / plan->N, 1.0))
       return st;
   }
   return PNCE_OK;
@@ -588,7 +672,7 @@ pnce_status pnce_varlen_create(pnce_varlen_plan **vplan, const pnce_frame_desc *
     for (const auto &kv : kmax) {
       int deg = 0;
       while ((1 << deg) - 1 < kv.first) ++deg;
-      const std::vector<signed char> s = make_sequence(deg);
+      const std::vector<signed char> s = make_sequence(deg, kFeedback[deg]);
       const int nbw = (int)(((long)kv.first + std::max(kv.first, kv.second) + 352 + 31) / 32);
       const std::vector<uint32_t> w = bit_stream(s, nbw, +1);
       boff[kv.first] = {(int)bits.size(), nbw};

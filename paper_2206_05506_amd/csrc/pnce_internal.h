@@ -9,13 +9,17 @@ namespace pnce {
 // Contraction modes of the Toeplitz +-1 kernels (same values as PNCE_PREC_*).
 enum Mode { MODE_F32 = 0, MODE_F32S = 1, MODE_BF16 = 2, MODE_F64 = 3 };
 
-// Input encodings of the tiled kernel.
-enum InFmt { IN_C64 = 0, IN_BF16 = 1, IN_F16 = 2, IN_E4M3 = 3 };
+// Input encodings of the tiled kernel. IN_C64_LAGS: complex64 rows of
+// rseg_n blocks of rseg_len terms, block j's terms sitting at reduction
+// positions j * rseg_lag + l (zero between blocks); t_len counts positions.
+enum InFmt { IN_C64 = 0, IN_BF16 = 1, IN_F16 = 2, IN_E4M3 = 3, IN_C64_LAGS = 4 };
 
 // One Toeplitz +-1 contraction over a batch of row blocks:
-//   out[b][r][c] = alpha_b * sum_{t < t_len} in[b][r][t] * sgn(bits[(t - c) mod N])
+//   out[b][r][c] = alpha_b * sum_{t < t_len} in[b][r][t] * sgn(bits[(t - lag(c) + poff) mod N])
 //                  + beta * cin[b][r][c],        c < c_len,
 // sgn(0) = +1, sgn(1) = -1, alpha_b = alpha * (scales ? scales[b] : 1).
+// lag(c) = c, or with column segments (seg_lag > 0, Eq. 8's lag spacing)
+// lag(j * seg_len + l) = j * seg_lag + l for l < seg_len.
 // Complex rows are interleaved; packed inputs hold a real plane then an
 // imaginary plane per row, each ld_in codes long.
 struct TgArgs {
@@ -32,7 +36,21 @@ struct TgArgs {
   // Nonzero: least-squares rows, out <- N/(N+1) (out + sum(out)/(N+1-c_len))
   // (complex64 input, beta = 0, c_len <= N).
   int ls;
+  int seg_len, seg_lag;  // column segments (seg_lag = 0: none)
+  int poff;              // shift of every sequence position, in [0, N)
+  int rseg_len, rseg_lag, rseg_n;  // reduction blocks of IN_C64_LAGS rows
 };
+
+// Columns as the kernels deal them out: segments of seg_len columns are
+// padded to a multiple of `gran` (the columns one wave or block holds, so
+// none straddles two segments); without segments the layout is the output.
+__host__ __device__ inline int seg_pad(int seg_len, int seg_lag, int gran) {
+  return seg_lag ? (seg_len + gran - 1) / gran * gran : (1 << 30);
+}
+inline int virtual_cols(int c_len, int seg_len, int seg_lag, int gran) {
+  if (!seg_lag) return c_len;
+  return (c_len + seg_len - 1) / seg_len * seg_pad(seg_len, seg_lag, gran);
+}
 
 hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s);
 
@@ -56,6 +74,11 @@ struct Tg64Args {
   int N;
   double alpha, beta;
   bool in_f64, out_f64;
+  int seg_len, seg_lag;  // as in TgArgs
+  int poff;
+  // reduction blocks (rseg_lag = 0: none): term t = j * rseg_len + l of a
+  // row sits at position j * rseg_lag + l; t_len counts terms
+  int rseg_len, rseg_lag;
 };
 hipError_t launch_tg64(const Tg64Args &a, hipStream_t s);
 

@@ -33,6 +33,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
 typedef float f2a8 __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kRows = 32;      // antennas per tile
 constexpr int kWaves = 4;
@@ -56,6 +57,7 @@ template <int IN> struct StageGeom<MODE_F32, IN> { static constexpr int ch = 32,
 template <int IN> struct StageGeom<MODE_F32S, IN> { static constexpr int ch = 32, planes = 6, rs = 20; };
 template <int IN> struct StageGeom<MODE_BF16, IN> { static constexpr int ch = 128, planes = 2, rs = 68; };
 template <> struct StageGeom<MODE_BF16, IN_C64> { static constexpr int ch = 64, planes = 2, rs = 36; };
+template <> struct StageGeom<MODE_BF16, IN_C64_LAGS> : StageGeom<MODE_BF16, IN_C64> {};
 
 template <int MODE, int IN = IN_C64> constexpr int stage_dwords() {
   return StageGeom<MODE, IN>::planes * kRows * StageGeom<MODE, IN>::rs;
@@ -158,6 +160,39 @@ __device__ __forceinline__ void mask_stage(RawC64<CH> &raw, int n0, int t_len, i
     } else if (n + 1 == t_len) {
       raw.v[i] = f32x4{raw.v[i].z, raw.v[i].w, 0.f, 0.f};
     }
+  }
+}
+
+// Rows of lag blocks (IN_C64_LAGS): reduction position u holds term
+// j * len + l of the row when u = j * step + l, l < len, j < n, and zero
+// otherwise (the guard lags between blocks). Each sample is one 8-byte load;
+// a position without a term is read at an offset past any frame (zero).
+// rowoff[i]: byte offset of the row of this thread's pair i.
+struct LagBlocks {
+  int len, step, n;
+};
+template <int CH>
+__device__ __forceinline__ void load_stage_lags(RawC64<CH> &raw, __amdgpu_buffer_rsrc_t rsrc,
+                                                const uint32_t (&rowoff)[CH / 16], int n0,
+                                                LagBlocks g, int tid) {
+  const int u = n0 + 2 * (tid % (CH / 2));
+  uint32_t src[2], off_frame[2];  // byte offset in the row; bit 31 if no term
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int j = (u + e) / g.step;
+    const int l = u + e - j * g.step;
+    src[e] = 8u * (uint32_t)(j * g.len + l);
+    off_frame[e] = (j < g.n && l < g.len) ? 0u : 0x80000000u;
+  }
+#pragma unroll
+  for (int i = 0; i < CH / 16; ++i) {
+    const f32x2 lo = __builtin_bit_cast(
+        f32x2,
+        __builtin_amdgcn_raw_buffer_load_b64(rsrc, (rowoff[i] + src[0]) | off_frame[0], 0, 0));
+    const f32x2 hi = __builtin_bit_cast(
+        f32x2,
+        __builtin_amdgcn_raw_buffer_load_b64(rsrc, (rowoff[i] + src[1]) | off_frame[1], 0, 0));
+    raw.v[i] = f32x4{lo.x, lo.y, hi.x, hi.y};
   }
 }
 
@@ -323,6 +358,19 @@ __device__ __forceinline__ int pos_mod(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Where a run of columns starting at dealt-out column v0 sits: its first lag,
+// its first stored column, and how many of its columns are stored (<= 0:
+// none). The run must not cross a segment (see seg_pad).
+struct SegPos {
+  int lag0, ocol0, n_out;
+};
+__device__ __forceinline__ SegPos seg_pos(int v0, int pad, int seg_len, int seg_lag, int c_len) {
+  if (!seg_lag) return {v0, v0, c_len - v0};
+  const int j = v0 / pad;
+  const int l0 = v0 - j * pad;
+  return {j * seg_lag + l0, j * seg_len + l0, min(seg_len, c_len - j * seg_len) - l0};
+}
+
 // ---------------------------------------------------------------------------
 // The tiled kernel.
 // ---------------------------------------------------------------------------
@@ -376,9 +424,15 @@ struct Tile {
   int a0, colg;
   float alpha, beta;
   bool ls;  // least-squares rows (the tile holds every lag of its rows)
+  int seg_len, seg_lag, poff;  // column segments and sequence shift (TgArgs)
+  int rseg_len, rseg_lag, rseg_n;  // reduction blocks of IN_C64_LAGS rows
 };
 
-template <int MODE, int IN, int NC, bool AL>
+// SB: column segments (Eq. 8 lags) with every 32-column block in its own
+// segment: each block has its own first lag and builds its own B fragment per
+// k-step (no reuse across blocks), so a wave's blocks may sit in different
+// transmitters' segments and segments are padded to 32 columns only.
+template <int MODE, int IN, int NC, bool AL, bool SB = false>
 __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
                                          const uint32_t *lut, uint32_t *stage) {
   constexpr int NWIN = 2 * NC;
@@ -387,7 +441,8 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   constexpr int SDW = stage_dwords<MODE, IN>();
   constexpr int CH = StageGeom<MODE, IN>::ch;  // samples per stage
   constexpr int KS = CH / 16;                // k-steps per stage
-  constexpr bool C64 = IN == IN_C64;
+  constexpr bool LAGS = IN == IN_C64_LAGS;   // gathered by lag blocks
+  constexpr bool C64 = IN == IN_C64 || LAGS;
   constexpr int PF = RegDepth<MODE, IN>::value;  // stages in flight
   // Chunks per unrolled body: the window rotation (NWIN k-steps) and the
   // register-set rotation (PF) both repeat after CPB chunks.
@@ -401,7 +456,21 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   const int m = lane & 31;
   const int h = lane >> 5;
   const int a0 = tl.a0;
-  const int col0 = tl.colg + wave * 32 * NC;
+  // this wave's 32*NC columns: lags sp.lag0 + j, stored at sp.ocol0 + j for
+  // j < sp.n_out (SB: block c's 32 columns from sb[c] likewise)
+  const int v0 = tl.colg + wave * 32 * NC;
+  const SegPos sp = seg_pos(v0, seg_pad(tl.seg_len, tl.seg_lag, SB ? 32 : 32 * NC), tl.seg_len,
+                            tl.seg_lag, tl.c_len);
+  [[maybe_unused]] SegPos sb[SB ? NC : 1];
+  if constexpr (SB) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      sb[c] = seg_pos(v0 + 32 * c, seg_pad(tl.seg_len, tl.seg_lag, 32), tl.seg_len, tl.seg_lag,
+                      tl.c_len);
+  }
+  // block c: first stored column, and how many of its 32 columns are stored
+  auto ocol = [&](int c) { return SB ? sb[c].ocol0 : sp.ocol0 + 32 * c; };
+  auto nout = [&](int c) { return SB ? sb[c].n_out : sp.n_out - 32 * c; };
 
   const int nchunks = (tl.t_len + CH - 1) / CH;
   const int last = nchunks - 1;
@@ -412,18 +481,24 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   // frame-bounded buffer resource, masked once in the last chunk.
   constexpr bool BUF = C64 || AL;
   // the frame ends with its last row's last term (rows may be strided past it)
+  const int row_terms = LAGS ? tl.rseg_n * tl.rseg_len : tl.t_len;
   const __amdgpu_buffer_rsrc_t rsrc = frame_rsrc(
-      tl.in, C64 ? ((long long)(tl.R - 1) * tl.ld_in + tl.t_len) * 8
+      tl.in, C64 ? ((long long)(tl.R - 1) * tl.ld_in + row_terms) * 8
                  : ((long long)(2 * tl.R - 1) * tl.ld_in + tl.t_len) * 2);
   uint32_t voff[CH / 16] = {};
 #pragma unroll
   for (int i = 0; i < CH / 16; ++i)
-    voff[i] = C64 ? pair_voff<CH>(i, a0, tl.ld_in, tid) : piece_voff<CH>(i, a0, tl.ld_in, tid);
+    voff[i] = LAGS  ? pair_voff<CH>(i, a0, tl.ld_in, tid) - 16u * (uint32_t)(tid % (CH / 2))
+              : C64 ? pair_voff<CH>(i, a0, tl.ld_in, tid)
+                    : piece_voff<CH>(i, a0, tl.ld_in, tid);
   // chunk -> register set ISET; past the end: re-read the last chunk
   auto fetch = [&](int chunk, auto iset) {
     constexpr int S = decltype(iset)::value;
     const int c = chunk < last ? chunk : last;
-    if constexpr (C64)
+    if constexpr (LAGS)
+      load_stage_lags<CH>(raw[S], rsrc, voff, c * CH, LagBlocks{tl.rseg_len, tl.rseg_lag, tl.rseg_n},
+                          tid);
+    else if constexpr (C64)
       load_stage<CH>(raw[S], rsrc, voff, c * CH, tl.t_len, tid);
     else if constexpr (BUF)
       load_stage<CH>(raw[S], rsrc, voff, c * CH);
@@ -434,7 +509,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   // register set ISET (holding `chunk`) -> LDS stage st
   auto land = [&](int chunk, auto iset, uint32_t *st) {
     constexpr int S = decltype(iset)::value;
-    if constexpr (BUF) {
+    if constexpr (BUF && !LAGS) {
       if (chunk == last) mask_stage<CH>(raw[S], chunk * CH, tl.t_len, tid);
     }
     store_stage<MODE>(st, raw[S], tid);
@@ -447,18 +522,36 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   __syncthreads();
 
   // Bit position of this lane's B fragment for block 0 at k-step 0:
-  // reduction index t0 = 8h (+ e), output column col0 + m.
-  const int p_base = pos_mod(8 * h - m - col0, tl.N);
+  // reduction index t0 = 8h (+ e), lag sp.lag0 + m.
+  const int p_base = pos_mod(8 * h - m - sp.lag0 + tl.poff, tl.N);
 
-  Win<MODE> win[NWIN];
-  // Prologue: fragments of k-steps -(NWIN-2) .. -1 (used by blocks c >= 1
-  // during the first 2c k-steps).
+  Win<MODE> win[SB ? 1 : NWIN];
+  // SB: block c's fragments of k-steps i (slot i & 1) and i + 1
+  [[maybe_unused]] Win<MODE> wb[SB ? NC : 1][2];
+  [[maybe_unused]] int pb[SB ? NC : 1];
+  if constexpr (SB) {
 #pragma unroll
-  for (int j = 1; j <= NWIN - 2; ++j) {
-    const int p = pos_mod(p_base - 16 * j, tl.N);
-    make_window<MODE, IN>(win[NWIN - j], window8(sbits, p), lut);
+    for (int c = 0; c < NC; ++c) {
+      pb[c] = pos_mod(8 * h - m - sb[c].lag0 + tl.poff, tl.N);
+      make_window<MODE, IN>(wb[c][0], window8(sbits, pb[c]), lut);
+    }
+  } else {
+    // Prologue: fragments of k-steps -(NWIN-2) .. -1 (used by blocks c >= 1
+    // during the first 2c k-steps).
+#pragma unroll
+    for (int j = 1; j <= NWIN - 2; ++j) {
+      const int p = pos_mod(p_base - 16 * j, tl.N);
+      make_window<MODE, IN>(win[NWIN - j], window8(sbits, p), lut);
+    }
+    make_window<MODE, IN>(win[0], window8(sbits, p_base), lut);  // k-step 0
   }
-  make_window<MODE, IN>(win[0], window8(sbits, p_base), lut);  // k-step 0
+  // B fragment of block c at k-step i (slot q of the rotation)
+  auto bfrag = [&](int c, int q, int i) -> const Win<MODE> & {
+    if constexpr (SB)
+      return wb[c][i & 1];
+    else
+      return win[(q - 2 * c + NWIN) % NWIN];
+  };
 
   f32x16 acc_re[NC], acc_im[NC];
 #pragma unroll
@@ -494,7 +587,14 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
     for (int u = 0; u < KS; ++u) {
       const int q = (KS * cc + u) % NWIN;  // slot of k-step i = KS*chunk + u
       const int i = KS * chunk + u;
-      make_window<MODE, IN>(win[(q + 1) % NWIN], window8(sbits, p_base + 16 * (i + 1)), lut);
+      // (KS is even, so i & 1 == u & 1 is known at compile time)
+      if constexpr (SB) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          make_window<MODE, IN>(wb[c][(u + 1) & 1], window8(sbits, pb[c] + 16 * (i + 1)), lut);
+      } else {
+        make_window<MODE, IN>(win[(q + 1) % NWIN], window8(sbits, p_base + 16 * (i + 1)), lut);
+      }
       if constexpr (MODE == MODE_F32) {
         const float *pre = (const float *)st + m * RS + 16 * u + 8 * h;
         const float *pim = pre + PS;
@@ -506,7 +606,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
         for (int j = 0; j < 8; ++j) {
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            const uint32_t x = win[(q - 2 * c + NWIN) % NWIN].f;
+            const uint32_t x = bfrag(c, q, u).f;
             const float bv =
                 __builtin_bit_cast(float, 0x3F800000u | ((x << (31 - j)) & 0x80000000u));
             acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(fre[j], bv, acc_re[c], 0, 0, 0);
@@ -526,7 +626,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
         for (int s = 0; s < NP; ++s) {
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            const u32x4 bw = win[(q - 2 * c + NWIN) % NWIN].f;
+            const u32x4 bw = bfrag(c, q, u).f;
             if constexpr (IN == IN_F16) {
               acc_re[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                   __builtin_bit_cast(f16x8, are[cur][s]), __builtin_bit_cast(f16x8, bw),
@@ -581,12 +681,13 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
     }
   });
 
-  // Epilogue: lane (m, h) holds, for block c, output column col0 + 32c + m
-  // and rows 8*(v/4) + 4*h + (v%4) of the 32x32 accumulator.
+  // Epilogue: lane (m, h) holds, for block c, output column ocol(c) + m
+  // (stored when m < nout(c)) and rows 8*(v/4) + 4*h + (v%4) of the 32x32
+  // accumulator.
   float alpha = tl.alpha;
   f32x16 tot_re = {}, tot_im = {};  // least squares: alpha * row sums
   if (tl.ls) {
-    // Row sums over this wave's columns (those < c_len), then over the 32
+    // Row sums over this wave's stored columns, then over the 32
     // lanes of each half-wave, then over the 4 waves through LDS (the stage
     // is no longer read); every lane then holds the sums of its 16 rows.
 #pragma unroll
@@ -594,7 +695,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
       float sr = 0.f, si = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const bool in = col0 + 32 * c + m < tl.c_len;
+        const bool in = m < nout(c);
         sr += in ? acc_re[c][v] : 0.f;
         si += in ? acc_im[c][v] : 0.f;
       }
@@ -630,8 +731,8 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int col = col0 + 32 * c + m;
-    if (col < tl.c_len) {
+    const int col = ocol(c) + m;
+    if (m < nout(c)) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int ant = a0 + 8 * (v >> 2) + 4 * h + (v & 3);
@@ -654,7 +755,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
 
 
 // One tile per workgroup over a uniform batch.
-template <int MODE, int IN, int NC, bool AL>
+template <int MODE, int IN, int NC, bool AL, bool SB>
 __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, int tiles_c,
                                                          int nbw_pad) {
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
@@ -672,7 +773,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
   for (int i = threadIdx.x; i < a.nbw; i += kThreads) smem[i] = a.bits[i];
   fill_lut<IN>(smem + nbw_pad);
   Tile tl;
-  if constexpr (IN == IN_C64)
+  if constexpr (IN == IN_C64 || IN == IN_C64_LAGS)
     tl.in = (const float *)a.in + (size_t)b * a.R * a.ld_in * 2;
   else
     tl.in = (const uint16_t *)a.in + (size_t)b * a.R * 2 * a.ld_in;
@@ -689,7 +790,13 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
   tl.alpha = a.alpha * (a.scales ? a.scales[b] : 1.0f);
   tl.beta = a.beta;
   tl.ls = a.ls != 0;
-  run_tile<MODE, IN, NC, AL>(tl, smem, smem + nbw_pad, smem + nbw_pad + kLutDw);
+  tl.seg_len = a.seg_len;
+  tl.seg_lag = a.seg_lag;
+  tl.poff = a.poff;
+  tl.rseg_len = a.rseg_len;
+  tl.rseg_lag = a.rseg_lag;
+  tl.rseg_n = a.rseg_n;
+  run_tile<MODE, IN, NC, AL, SB>(tl, smem, smem + nbw_pad, smem + nbw_pad + kLutDw);
 }
 
 // Persistent kernel over an uneven batch: workgroup w walks its slice of a
@@ -728,6 +835,10 @@ __global__ __launch_bounds__(kThreads, 2) void varlen_kernel(VArgs a) {
     tl.alpha = (a.scales ? a.scales[vt.frame] : 1.0f) / (float)f.N;
     tl.beta = 0.0f;
     tl.ls = false;
+    tl.seg_len = 0;
+    tl.seg_lag = 0;
+    tl.poff = 0;
+    tl.rseg_len = tl.rseg_lag = tl.rseg_n = 0;
     if (f.N >= 7) {  // N + 1 = 2^d, d >= 3: rows 8-code aligned
       if (vt.nc == 4)
         run_tile<MODE, IN, 4, true>(tl, smem, lut, stage);
@@ -780,7 +891,8 @@ hipError_t launch_varlen(int in_fmt, const VArgs &a, int n_wg, hipStream_t s) {
 // ---------------------------------------------------------------------------
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
 
-template <int NB>
+// GA: rows of lag blocks (IN_C64_LAGS), gathered sample by sample.
+template <int NB, bool GA>
 __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int tiles_r,
                                                                int tiles_c, int nbw_pad) {
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
@@ -806,23 +918,35 @@ __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int til
   const int b = rest / tiles_r;
   const int a0 = rb * kRows;
   const int col0 = cg * (kWaves * 16 * NB) + wave * 16 * NB;
+  // column block c: lags sp[c].lag0 + j, stored at sp[c].ocol0 + j, j < n_out
+  SegPos sp[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    sp[c] = seg_pos(col0 + 16 * c, seg_pad(a.seg_len, a.seg_lag, 16), a.seg_len, a.seg_lag,
+                    a.c_len);
 
   const float *fin = (const float *)a.in + (size_t)b * a.R * a.ld_in * 2;
   constexpr int CH = 32;  // 8 k-steps of 4 terms per stage
   const int nchunks = (a.t_len + CH - 1) / CH;
   const int last = nchunks - 1;
+  const int row_terms = GA ? a.rseg_n * a.rseg_len : a.t_len;
   const __amdgpu_buffer_rsrc_t rsrc =
-      frame_rsrc(fin, ((long long)(a.R - 1) * a.ld_in + a.t_len) * 8);
+      frame_rsrc(fin, ((long long)(a.R - 1) * a.ld_in + row_terms) * 8);
   uint32_t voff[CH / 16];
 #pragma unroll
-  for (int i = 0; i < CH / 16; ++i) voff[i] = pair_voff<CH>(i, a0, a.ld_in, tid);
+  for (int i = 0; i < CH / 16; ++i)
+    voff[i] = pair_voff<CH>(i, a0, a.ld_in, tid) - (GA ? 16u * (uint32_t)(tid % (CH / 2)) : 0u);
   // chunk -> set (past the end: the last chunk again); set -> stage, masked
   // when it holds the last chunk
   auto fetch = [&](RawC64<CH> &r, int chunk) {
-    load_stage<CH>(r, rsrc, voff, (chunk < last ? chunk : last) * CH, a.t_len, tid);
+    const int n0 = (chunk < last ? chunk : last) * CH;
+    if constexpr (GA)
+      load_stage_lags<CH>(r, rsrc, voff, n0, LagBlocks{a.rseg_len, a.rseg_lag, a.rseg_n}, tid);
+    else
+      load_stage<CH>(r, rsrc, voff, n0, a.t_len, tid);
   };
   auto land = [&](uint32_t *st, RawC64<CH> &r, int chunk) {
-    if (chunk == last) mask_stage<CH>(r, chunk * CH, a.t_len, tid);
+    if (!GA && chunk == last) mask_stage<CH>(r, chunk * CH, a.t_len, tid);
     store_stage<MODE_F32>(st, r, tid);
   };
   RawC64<CH> raw[PF];
@@ -833,7 +957,9 @@ __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int til
   fetch(raw[0], PF);
   __syncthreads();
 
-  const int p_base = pos_mod(g - j16 - col0, a.N);
+  int p_base[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) p_base[c] = pos_mod(g - j16 - sp[c].lag0 + a.poff, a.N);
   f64x4 acc[2][2][NB];  // [row block][re, im][column block]
 #pragma unroll
   for (int r2 = 0; r2 < 2; ++r2)
@@ -848,11 +974,11 @@ __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int til
       const int chunk = chunk0 + cc;
       if (chunk < nchunks) {
         const float *st = (const float *)(stage + (chunk & 1) * SDW);
-        // 32-bit windows: bits p_base - 16c + 32*chunk + 4j, j = 0..7
+        // 32-bit windows: bits p_base[c] + 32*chunk + 4j, j = 0..7
         uint32_t w[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c)
-          w[c] = window32(sbits, pos_mod(p_base - 16 * c + 32 * chunk, a.N));
+          w[c] = window32(sbits, pos_mod(p_base[c] + 32 * chunk, a.N));
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           double av[2][2];
@@ -881,14 +1007,14 @@ __global__ __launch_bounds__(kThreads, 2) void tg_f64mm_kernel(TgArgs a, int til
     }
   }
 
-  // Lane (j, g) holds, per block, column col0 + 16c + j and rows g + 4v (the
+  // Lane (j, g) holds, per block, column sp[c].ocol0 + j and rows g + 4v (the
   // FP64 16x16 result interleaves rows across the four lane groups).
   const double alpha = (double)a.alpha * (a.scales ? (double)a.scales[b] : 1.0);
   const double beta = (double)a.beta;
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
-    const int col = col0 + 16 * c + j16;
-    if (col < a.c_len) {
+    const int col = sp[c].ocol0 + j16;
+    if (j16 < sp[c].n_out) {
 #pragma unroll
       for (int r2 = 0; r2 < 2; ++r2) {
 #pragma unroll
@@ -915,19 +1041,23 @@ hipError_t launch_f64mm(const TgArgs &a, hipStream_t s) {
   constexpr int NB = 4;
   const int tiles_r = (a.R + kRows - 1) / kRows;
   const int cols_per_tile = kWaves * 16 * NB;
-  const int tiles_c = (a.c_len + cols_per_tile - 1) / cols_per_tile;
+  const int tiles_c =
+      (virtual_cols(a.c_len, a.seg_len, a.seg_lag, 16) + cols_per_tile - 1) / cols_per_tile;
   const long nt = (long)a.batch * tiles_r * tiles_c;
   if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
   const int nbw_pad = (a.nbw + 3) & ~3;
   const size_t lds = (size_t)(nbw_pad + 2 * stage_dwords<MODE_F32>()) * 4;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)tg_f64mm_kernel<NB>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL((tg_f64mm_kernel<NB>), dim3((unsigned)nt), dim3(kThreads), lds, s, a,
-                     tiles_r, tiles_c, nbw_pad);
-  return hipGetLastError();
+  auto go = [&](auto kern) -> hipError_t {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)nt), dim3(kThreads), lds, s, a, tiles_r, tiles_c,
+                       nbw_pad);
+    return hipGetLastError();
+  };
+  return a.rseg_lag ? go(tg_f64mm_kernel<NB, true>) : go(tg_f64mm_kernel<NB, false>);
 }
 
 // ---------------------------------------------------------------------------
@@ -993,7 +1123,10 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
   const int rb = rest % tiles_r;
   const int b = rest / tiles_r;
   const int a0 = rb * kRows;
-  const int col0 = cg * (kWaves * 32 * NC) + wave * 32 * NC;
+  // this wave's columns (see run_tile)
+  const SegPos sp = seg_pos(cg * (kWaves * 32 * NC) + wave * 32 * NC,
+                            seg_pad(a.seg_len, a.seg_lag, 32 * NC), a.seg_len, a.seg_lag,
+                            a.c_len);
 
   const int nchunks = (a.t_len + CH - 1) / CH;
   const int last = nchunks - 1;
@@ -1070,7 +1203,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
   fetch(raw[0], PF);
   __syncthreads();
 
-  const int p_base = pos_mod(32 * h - m - col0, a.N);
+  const int p_base = pos_mod(32 * h - m - sp.lag0 + a.poff, a.N);
   i32x8 win[NW];
   // windows W(j), j = -(NC-1) .. -1, for blocks c >= 1 of the first k-steps
 #pragma unroll
@@ -1144,8 +1277,8 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
   const float alpha = a.alpha * (a.scales ? a.scales[b] : 1.0f);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int col = col0 + 32 * c + m;
-    if (col < a.c_len) {
+    const int col = sp.ocol0 + 32 * c + m;
+    if (32 * c + m < sp.n_out) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int ant = a0 + 8 * (v >> 2) + 4 * h + (v & 3);
@@ -1169,7 +1302,8 @@ template <int NC, bool AL>
 static hipError_t launch_fp8_nc_al(const TgArgs &a, hipStream_t s) {
   const int tiles_r = (a.R + kRows - 1) / kRows;
   const int cols_per_tile = kWaves * 32 * NC;
-  const int tiles_c = (a.c_len + cols_per_tile - 1) / cols_per_tile;
+  const int tiles_c =
+      (virtual_cols(a.c_len, a.seg_len, a.seg_lag, 32 * NC) + cols_per_tile - 1) / cols_per_tile;
   const long nt = (long)a.batch * tiles_r * tiles_c;
   if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
   const int nbw_pad = (a.nbw + 3) & ~3;
@@ -1190,17 +1324,19 @@ static hipError_t launch_fp8_nc(const TgArgs &a, hipStream_t s) {
   return launch_fp8_nc_al<NC, false>(a, s);
 }
 
-template <int MODE, int IN, int NC, bool AL>
-static hipError_t launch_tg_nc_al(const TgArgs &a, hipStream_t s) {
+template <int MODE, int IN, int NC, bool AL, bool SB>
+static hipError_t launch_tg_nc_al_sb(const TgArgs &a, hipStream_t s) {
   const int tiles_r = (a.R + kRows - 1) / kRows;
   const int cols_per_tile = kWaves * 32 * NC;
-  const int tiles_c = (a.c_len + cols_per_tile - 1) / cols_per_tile;
+  const int tiles_c =
+      (virtual_cols(a.c_len, a.seg_len, a.seg_lag, SB ? 32 : 32 * NC) + cols_per_tile - 1) /
+      cols_per_tile;
   const long nt = (long)a.batch * tiles_r * tiles_c;
   if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
   const int nbw_pad = (a.nbw + 3) & ~3;
   const size_t lds = (size_t)tile_lds_dwords<MODE, IN>(nbw_pad) * 4;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)tg_kernel<MODE, IN, NC, AL>,
+    hipError_t e = hipFuncSetAttribute((const void *)tg_kernel<MODE, IN, NC, AL, SB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
@@ -1209,39 +1345,66 @@ static hipError_t launch_tg_nc_al(const TgArgs &a, hipStream_t s) {
     // least-squares correction as a second launch
     TgArgs b = a;
     b.ls = 0;
-    hipLaunchKernelGGL((tg_kernel<MODE, IN, NC, AL>), dim3((unsigned)nt), dim3(kThreads), lds, s,
-                       b, tiles_r, tiles_c, nbw_pad);
+    hipLaunchKernelGGL((tg_kernel<MODE, IN, NC, AL, SB>), dim3((unsigned)nt), dim3(kThreads), lds,
+                       s, b, tiles_r, tiles_c, nbw_pad);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_debias(a.out, (long)a.batch * a.R, a.c_len, a.N, s);
   }
-  hipLaunchKernelGGL((tg_kernel<MODE, IN, NC, AL>), dim3((unsigned)nt), dim3(kThreads), lds, s,
+  hipLaunchKernelGGL((tg_kernel<MODE, IN, NC, AL, SB>), dim3((unsigned)nt), dim3(kThreads), lds, s,
                      a, tiles_r, tiles_c, nbw_pad);
   return hipGetLastError();
+}
+
+// Column segments (Eq. 8 lags) take the per-block variant; rows of lag
+// blocks (the adjoint's input) never have column segments.
+template <int MODE, int IN, int NC, bool AL>
+static hipError_t launch_tg_nc_al(const TgArgs &a, hipStream_t s) {
+  if constexpr (IN == IN_C64_LAGS) {
+    if (a.seg_lag) return hipErrorInvalidValue;
+    return launch_tg_nc_al_sb<MODE, IN, NC, AL, false>(a, s);
+  } else {
+    if (a.seg_lag) return launch_tg_nc_al_sb<MODE, IN, NC, AL, true>(a, s);
+    return launch_tg_nc_al_sb<MODE, IN, NC, AL, false>(a, s);
+  }
 }
 
 // Packed rows take the branch-free loader when rows are 8-code aligned and
 // the reduction length is a multiple of 8; complex64 rows always do.
 template <int MODE, int IN, int NC>
 static hipError_t launch_tg_nc(const TgArgs &a, hipStream_t s) {
-  if (IN == IN_C64 || ((a.ld_in & 7) == 0 && (a.t_len & 7) == 0))
+  if constexpr (IN == IN_C64 || IN == IN_C64_LAGS) {
     return launch_tg_nc_al<MODE, IN, NC, true>(a, s);
-  return launch_tg_nc_al<MODE, IN, NC, false>(a, s);
+  } else {
+    if ((a.ld_in & 7) == 0 && (a.t_len & 7) == 0) return launch_tg_nc_al<MODE, IN, NC, true>(a, s);
+    return launch_tg_nc_al<MODE, IN, NC, false>(a, s);
+  }
 }
 
 // Column width per wave: the widest that the output needs (fewest re-reads
 // of the input), narrowed while the launch has fewer tiles than the chip has
 // compute units, so small batches (one frame) spread over more of them.
-static int pick_nc(const TgArgs &a) {
-  int nc = a.c_len > 256 ? 4 : (a.c_len > 128 ? 2 : 1);
+// Column segments are padded to `gran(nc)` columns: 32 for the tiled kernel
+// (a segment per 32-column block), 32*nc for the e4m3 kernel (a segment per
+// wave), which is then kept no wider than a segment (rounded up to 32) needs.
+static int pick_nc(const TgArgs &a, bool per_block) {
+  auto gran = [&](int n) { return per_block ? 32 : 32 * n; };
+  const int width = virtual_cols(a.c_len, a.seg_len, a.seg_lag, 32);
+  int nc = width > 256 ? 4 : (width > 128 ? 2 : 1);
+  if (a.seg_lag && !per_block)
+    while (nc > 1 && seg_pad(a.seg_len, 1, 32 * nc) != seg_pad(a.seg_len, 1, 32)) nc /= 2;
   const long rows = (long)a.batch * ((a.R + kRows - 1) / kRows);
-  while (nc > 1 && rows * ((a.c_len + kWaves * 32 * nc - 1) / (kWaves * 32 * nc)) < 256) nc /= 2;
+  auto tiles = [&](int n) {
+    const int w = kWaves * 32 * n;
+    return rows * ((virtual_cols(a.c_len, a.seg_len, a.seg_lag, gran(n)) + w - 1) / w);
+  };
+  while (nc > 1 && tiles(nc) < 256) nc /= 2;
   return nc;
 }
 
 template <int MODE, int IN>
 static hipError_t launch_tg_mode(const TgArgs &a, hipStream_t s) {
-  const int nc = pick_nc(a);
+  const int nc = pick_nc(a, true);
   if (nc == 4) return launch_tg_nc<MODE, IN, 4>(a, s);
   if (nc == 2) return launch_tg_nc<MODE, IN, 2>(a, s);
   return launch_tg_nc<MODE, IN, 1>(a, s);
@@ -1270,10 +1433,18 @@ hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s) {
       default: return hipErrorInvalidValue;
     }
   }
+  if (in_fmt == IN_C64_LAGS) {
+    switch (mode) {
+      case MODE_F32: return launch_tg_mode<MODE_F32, IN_C64_LAGS>(a, s);
+      case MODE_F32S: return launch_tg_mode<MODE_F32S, IN_C64_LAGS>(a, s);
+      case MODE_BF16: return launch_tg_mode<MODE_BF16, IN_C64_LAGS>(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (in_fmt == IN_BF16) return launch_tg_mode<MODE_BF16, IN_BF16>(a, s);
   if (in_fmt == IN_F16) return launch_tg_mode<MODE_BF16, IN_F16>(a, s);
   if (in_fmt == IN_E4M3) {
-    const int nc = pick_nc(a);
+    const int nc = pick_nc(a, false);
     if (nc == 4) return launch_fp8_nc<4>(a, s);
     if (nc == 2) return launch_fp8_nc<2>(a, s);
     return launch_fp8_nc<1>(a, s);
@@ -1294,7 +1465,13 @@ __global__ __launch_bounds__(256) void tg64_kernel(Tg64Args a, int cblocks) {
   if (col >= a.c_len) return;
   const int b = (int)(row / a.R);
   const TI *x = (const TI *)a.in + (size_t)row * a.ld_in * 2;
-  int p = (a.N - col % a.N) % a.N;  // (0 - col) mod N
+  const int lag = a.seg_lag ? col / a.seg_len * a.seg_lag + col % a.seg_len : col;
+  int p = (int)(((long)a.poff - lag % a.N + a.N) % a.N);  // (poff - lag) mod N
+  // with reduction blocks, the position jumps by rseg_lag - rseg_len after
+  // every block of rseg_len terms
+  const int blk_len = a.rseg_lag ? a.rseg_len : a.t_len;
+  const int jump = a.rseg_lag ? (a.rseg_lag - a.rseg_len) % a.N : 0;
+  int in_blk = 0;
   double re = 0.0, im = 0.0;
   for (int t = 0; t < a.t_len; ++t) {
     const bool neg = (a.bits[p >> 5] >> (p & 31)) & 1u;
@@ -1302,6 +1479,11 @@ __global__ __launch_bounds__(256) void tg64_kernel(Tg64Args a, int cblocks) {
     re += neg ? -xr : xr;
     im += neg ? -xi : xi;
     if (++p == a.N) p = 0;
+    if (++in_blk == blk_len) {
+      in_blk = 0;
+      p += jump;
+      if (p >= a.N) p -= a.N;
+    }
   }
   const double alpha = a.alpha * (a.scales ? (double)a.scales[b] : 1.0);
   re *= alpha;

@@ -121,3 +121,52 @@ def test_alloc_fault_hook():
     out = subprocess.run([sys.executable, "-c", code, LIB], capture_output=True, text=True,
                          env=env, check=True).stdout.split(None, 1)
     assert out[0] == "-3" and "PNCE_FAULT" in out[1]
+
+
+def _create_ex(lib, N, T, L, R, fb, spacing):
+    h = ctypes.c_void_p()
+    lib.pnce_create_ex.argtypes = ([ctypes.POINTER(ctypes.c_void_p)] + [ctypes.c_int] * 4 +
+                                   [ctypes.c_uint, ctypes.c_int])
+    st = lib.pnce_create_ex(ctypes.byref(h), N, T, L, R, fb, spacing)
+    return st, h
+
+
+@pytest.mark.parametrize("N,T,L,fb,spacing", [
+    (127, 4, 16, 0, 2),        # unknown spacing
+    (127, 8, 16, 0, 1),        # Eq. 8 with T*L > N: blocks overlap (Eq. 7)
+    (127, 4, 16, 0x80, 0),     # a tap at or above degree 7
+    (63, 4, 8, 0x9, 1),        # x^6 + x^3 + 1: irreducible, not primitive
+    (31, 2, 4, 0x3, 0),        # x^5 + x + 1 = (x^2+x+1)(x^3+x^2+1)
+])
+def test_create_ex_validates_before_touching_the_device(lib, N, T, L, fb, spacing):
+    st, h = _create_ex(lib, N, T, L, 4, fb, spacing)
+    assert st == -1
+    assert not h.value
+
+
+def test_create_ex_accepts_exactly_the_primitive_polynomials():
+    """The library's maximal-length check agrees with the oracle's list for
+    every feedback mask of degrees 5 and 6 (accepted masks reach the device
+    allocation, which the fault hook fails)."""
+    sys.path.insert(0, ROOT)
+    import oracle
+    want = {d: set(oracle.primitive_masks(d)) for d in (5, 6)}
+    code = ("import ctypes,sys; l=ctypes.CDLL(sys.argv[1]); h=ctypes.c_void_p();"
+            "l.pnce_create_ex.argtypes=[ctypes.c_void_p]+[ctypes.c_int]*4+[ctypes.c_uint,ctypes.c_int];"
+            "print(' '.join(str(l.pnce_create_ex(ctypes.byref(h),(1<<d)-1,2,4,4,m,0))"
+            " for d in (5,6) for m in range(1,1<<d)))")
+    env = dict(os.environ, PNCE_FAULT="alloc")
+    out = subprocess.run([sys.executable, "-c", code, LIB], capture_output=True, text=True,
+                         env=env, check=True).stdout.split()
+    got = iter(int(x) for x in out)
+    for d in (5, 6):
+        for m in range(1, 1 << d):
+            assert next(got) == (-3 if m in want[d] else -1), (d, m)
+
+
+def test_lag_and_feedback_queries_reject_null_plan(lib):
+    P = ctypes.c_void_p
+    lib.pnce_get_lags.argtypes = [P, P]
+    assert lib.pnce_get_lags(None, None) == -1
+    lib.pnce_get_feedback.argtypes = [P, P]
+    assert lib.pnce_get_feedback(None, None) == -1
