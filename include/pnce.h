@@ -88,8 +88,11 @@ typedef int pnce_status;
  * state 1,0,...,0; bit 0 sent as +1 and bit 1 as -1) and uploads its bits
  * (a few KiB) to the current device. Synchronous.
  * Errors: plan == NULL or T, L, R <= 0 -> PNCE_E_INVALID; N not 2^d - 1 with
- * 2 <= d <= 16, or one frame too large for 32-bit offsets
- * ((R + 32) * (max(N, T*L) + 1) * 8 >= 2^31) -> PNCE_E_UNSUPPORTED;
+ * 2 <= d <= 16, one frame too large for 32-bit offsets
+ * ((R + 32) * (max(N, T*L) + 1) * 8 >= 2^31), or a sequence bit stream of
+ * N + max(N, T*L) + 352 bits that does not fit a workgroup's 160 KiB of LDS
+ * next to the kernels' stages (only d = 16 with T*L above about 14 N)
+ * -> PNCE_E_UNSUPPORTED;
  * T*L > 16*N or R > 65535 -> PNCE_E_INVALID. Warning: T*L > N (Eq. 7's bound N_batch <= floor(N/L)
  * broken) -> PNCE_W_LAG_ALIAS, with a valid plan. On error *plan = NULL.
  */

@@ -253,6 +253,10 @@ pnce_status pnce_create_ex(pnce_plan **plan, int N, int T, int L, int R, unsigne
     // byte offsets, including reads up to 32 rows past its end.
     if (((long long)R + 32) * ((K > N ? K : N) + 1) * 8 >= (1LL << 31))
       return fail(PNCE_E_UNSUPPORTED, "frame exceeds 2 GiB: (R + 32) * max(N, T*L) too large");
+    // Every workgroup keeps the bit stream in LDS.
+    const long stream_bits = (long)N + (K > N ? K : N) + 352;
+    if (pnce::max_lds_bytes((int)((stream_bits + 31) / 32)) > pnce::kLdsLimitBytes)
+      return fail(PNCE_E_UNSUPPORTED, "sequence bit stream exceeds LDS: T*L too large for N");
 
     pnce_plan *p = new (std::nothrow) pnce_plan();
     if (!p) return fail(PNCE_E_NOMEM, "host allocation failed");
@@ -266,10 +270,8 @@ pnce_status pnce_create_ex(pnce_plan **plan, int N, int T, int L, int R, unsigne
     p->spacing = spacing;
     p->D = spacing == PNCE_LAGS_EQ8 ? N / T : L;
     p->seq = std::move(seq);
-    // Positions read by the kernels stay below N + max(N, K) + 16 * 16 + 64
-    // bits (the direct kernel runs up to 16 k-steps past the last one).
-    const long bits = (long)N + (K > N ? K : N) + 352;
-    p->nbw = (int)((bits + 31) / 32);
+    // Positions read by the kernels stay below N + max(N, K) + 352 bits.
+    p->nbw = (int)((stream_bits + 31) / 32);
     const std::vector<uint32_t> fwd = bit_stream(p->seq, p->nbw, +1);
     const std::vector<uint32_t> rev = bit_stream(p->seq, p->nbw, -1);
 
@@ -673,11 +675,16 @@ pnce_status pnce_varlen_create(pnce_varlen_plan **vplan, const pnce_frame_desc *
       int deg = 0;
       while ((1 << deg) - 1 < kv.first) ++deg;
       const std::vector<signed char> s = make_sequence(deg, kFeedback[deg]);
-      const int nbw = (int)(((long)kv.first + std::max(kv.first, kv.second) + 352 + 31) / 32);
+      // the correlator reads bit positions below 2N + 352 (lags taken mod N)
+      const int nbw = (int)((2L * kv.first + 352 + 31) / 32);
       const std::vector<uint32_t> w = bit_stream(s, nbw, +1);
       boff[kv.first] = {(int)bits.size(), nbw};
       bits.insert(bits.end(), w.begin(), w.end());
       v->nbw_max = std::max(v->nbw_max, nbw);
+    }
+    if (pnce::max_lds_bytes(v->nbw_max) > pnce::kLdsLimitBytes) {
+      delete v;
+      return fail(PNCE_E_UNSUPPORTED, "sequence bit stream exceeds LDS");
     }
     v->frames.resize((size_t)nframes);
     for (int f = 0; f < nframes; ++f) {

@@ -54,6 +54,11 @@ inline int virtual_cols(int c_len, int seg_len, int seg_lag, int gran) {
 
 hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s);
 
+// LDS one workgroup needs, at most over the kernels, for a bit stream of
+// nbw words, and what a gfx950 workgroup may have.
+size_t max_lds_bytes(int nbw);
+constexpr size_t kLdsLimitBytes = 160 * 1024;
+
 // In-place least-squares correction of `rows` rows of K complex64 values.
 hipError_t launch_debias(float *H, long rows, int K, int N, hipStream_t s);
 

@@ -386,6 +386,20 @@ constexpr int tile_lds_dwords(int nbw_pad) {
   return nbw_pad + kLutDw + 2 * stage_dwords<MODE, IN>();
 }
 
+// LDS of the largest kernel for a bit stream of nbw words: the tiled kernel
+// on packed 16-bit codes (the widest stages) holds the most besides the
+// stream; the FP64 and e4m3 kernels hold less.
+size_t max_lds_bytes(int nbw) {
+  const int nbw_pad = (nbw + 3) & ~3;
+  int d = tile_lds_dwords<MODE_BF16, IN_BF16>(nbw_pad);
+  d = std::max(d, tile_lds_dwords<MODE_F32S, IN_C64>(nbw_pad));
+  d = std::max(d, tile_lds_dwords<MODE_F32, IN_C64>(nbw_pad));
+  d = std::max(d, tile_lds_dwords<MODE_BF16, IN_C64>(nbw_pad));
+  d = std::max(d, nbw_pad + 2 * stage_dwords<MODE_F32>());
+  d = std::max(d, nbw_pad + 2 * 2 * kRows * (128 / 4 + 4));
+  return (size_t)d * 4;
+}
+
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F &&f) {

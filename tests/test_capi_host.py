@@ -71,6 +71,7 @@ def _create(lib, N, T, L, R):
     (127, 4, 16, 70000, -1),  # R above 65535
     (127, 200, 16, 1, -1),    # T*L > 16 N
     (65535, 16, 4096, 4096, -2),  # one frame beyond 32-bit byte offsets
+    (65535, 16, 65535, 100, -2),  # T*L = 16 N: the adjoint's bit stream exceeds LDS
 ])
 def test_create_validates_before_touching_the_device(lib, N, T, L, R, want):
     st, h = _create(lib, N, T, L, R)

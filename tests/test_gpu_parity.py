@@ -259,3 +259,59 @@ def test_nonfinite_inputs_propagate():
             assert np.all(np.isnan(H[0, 0].real))
             assert np.all(~np.isfinite(H[0, 1].real))
             assert np.all(np.isfinite(H[0, 1].imag))
+
+
+@pytest.mark.parametrize("d", [13, 14, 15, 16])
+def test_longest_sequences(d):
+    """The largest sequence lengths (bit streams up to 16 KiB of LDS): every
+    precision of the correlator, the adjoint, packed codes and LS rows."""
+    N = (1 << d) - 1
+    T, L, R, B = 3, 40, 5, 2
+    K = T * L
+    y = _rand_frames(N, R, B, d)
+    G = synth.gaussian((B, R, K), d + 1).astype(np.complex64)
+    with _plan(N, T, L, R) as p:
+        s = p.sequence()
+        yd = dev(y)
+        H = {prec: host(p.estimate(yd, prec)) for prec in ("f32", "f32s", "bf16", "f64acc")}
+        X = host(p.estimate_ls(yd, "f32s"))
+        A = host(p.adjoint(dev(G), "f32s"))
+        q, sc = p.pack(yd, "e4m3")
+        He = host(p.estimate_packed(q, sc, "e4m3"))
+        qh, sch = host(q), host(sc)
+    ref = oracle.correlate(y, s, K)
+    for prec in ("f32", "f32s"):
+        assert oracle.relerr(H[prec], ref) <= TOL32
+    assert oracle.relerr(H["f64acc"], ref) <= TOL_F64ACC
+    assert oracle.relerr(H["bf16"], oracle.correlate(bf16_round(y), s, K)) <= TOL32
+    assert oracle.relerr(X, oracle.ls_closed_form(ref, N)) <= TOL32
+    assert oracle.relerr(A, oracle.adjoint(G, s)) <= TOL32
+    xe = oracle.dequantize(qh.view(np.uint8), sch, "e4m3", N)
+    assert oracle.relerr(He, oracle.correlate(xe, s, K)) <= TOL32
+
+
+def test_longest_sequence_with_lag_alias():
+    """d = 16 with T*L > N: the lags wrap mod N; the adjoint reduces over more
+    lags than the sequence is long."""
+    N, T, L, R, B = 65535, 1, 65600, 1, 1
+    y = _rand_frames(N, R, B, 77)
+    G = synth.gaussian((B, R, T * L), 78).astype(np.complex64)
+    with _plan(N, T, L, R) as p:
+        assert p.lag_alias
+        s = p.sequence()
+        H = host(p.estimate(dev(y), "f32s"))
+        A = host(p.adjoint(dev(G), "f32s"))
+    assert np.array_equal(H[..., N:], H[..., :T * L - N])
+    assert oracle.relerr(H[..., :4096], oracle.correlate(y, s, 4096)) <= TOL32
+    assert oracle.relerr(A, oracle.adjoint(G, s)) <= TOL32
+
+
+def test_most_antennas():
+    """R = 65535 (the largest plan): 2048 antenna blocks, the last ragged."""
+    N, T, L, R, B = 7, 1, 3, 65535, 1
+    y = _rand_frames(N, R, B, 79)
+    with _plan(N, T, L, R) as p:
+        s = p.sequence()
+        H = {prec: host(p.estimate(dev(y), prec)) for prec in ("f32s", "bf16")}
+    assert oracle.relerr(H["f32s"], oracle.correlate(y, s, T * L)) <= TOL32
+    assert oracle.relerr(H["bf16"], oracle.correlate(bf16_round(y), s, T * L)) <= TOL32
