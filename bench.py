@@ -256,8 +256,14 @@ def uneven_batch(torch, args):
     Yq = torch.randn((vp.n_codes,), generator=g, device="cuda").to(torch.bfloat16)
     Yq = Yq.view(torch.int16).contiguous()
     H = torch.empty((vp.n_out,), dtype=torch.complex64, device="cuda")
+    start = vp.tuning()
     vp.tune(Yq, None, out=H, reps=3)
+    tuned = vp.tuning()
     ms_p, _ = time_steps(lambda: vp.estimate(Yq, None, out=H), args.steps, 2, torch)
+    # the default schedule, timed in the same (warm) state for comparison
+    vp.set_tuning(start)
+    ms_u, _ = time_steps(lambda: vp.estimate(Yq, None, out=H), args.steps, 2, torch)
+    vp.set_tuning(tuned)
     ms_e, _ = time_steps(lambda: vp.estimate_each(Yq, None, out=H), 3, 1, torch)
     # the persistent launch captured once in a HIP graph and replayed
     side = torch.cuda.Stream()
@@ -275,7 +281,8 @@ def uneven_batch(torch, args):
     flops = sum(4.0 * R * N * T * L for R, N, T, L in shapes)
     st = vp.stats()
     vp.close()
-    return {"frames": len(shapes), "persistent_ms": ms_p, "graph_replay_ms": ms_g,
+    return {"frames": len(shapes), "persistent_ms": ms_p, "untuned_ms": ms_u,
+            "graph_replay_ms": ms_g,
             "per_frame_launches_ms": ms_e,
             "speedup": ms_e / ms_p, "CIR/s": cirs / (ms_p * 1e-3),
             "GB/s": byt / ms_p / 1e6, "hbm_frac": byt / ms_p / 1e6 / HBM_PEAK_GBS,

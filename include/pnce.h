@@ -297,11 +297,18 @@ pnce_status pnce_varlen_estimate_each(const pnce_varlen_plan *vplan, void *strea
                                       const void *Yq, const float *scales, void *H);
 
 /*
- * Autotuner: for each (N, T*L) class, times the column widths 32, 64 and 128
- * lags per wave on up to 16 frames of that class (`reps` timed launches
- * each, HIP events on `stream`), keeps the fastest, uses its measured time
- * per (frame, 32-antenna) unit as the scheduling cost and rebuilds the work
- * list. Synchronous. Writes H of the sampled frames.
+ * Autotuner: for each (N, T*L) class and each column width (32, 64 and 128
+ * lags per wave) it measures the marginal time of one (frame, 32-antenna)
+ * unit in a full persistent launch: the units of up to 16 frames of the
+ * class, repeated to give every workgroup slot about 2 and then 4 of them,
+ * are timed (`reps` launches each, HIP events on `stream`), and the
+ * difference divided by the extra units per slot cancels launch and start
+ * overheads. From these it builds candidate work lists (the plan's current
+ * one; the fastest widths with measured costs; the default widths with
+ * measured costs; the fastest widths with the default cost model), times
+ * each on the whole batch and keeps the fastest, so tuning does not lose to
+ * the plan's previous schedule beyond timing noise. Synchronous. Writes H
+ * (the repeated units write the same values).
  */
 pnce_status pnce_varlen_tune(pnce_varlen_plan *vplan, void *stream, const void *Yq,
                              const float *scales, void *H, int reps);
