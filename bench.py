@@ -65,6 +65,11 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only 3 bf16 estimates and 3 plain copies of the frames (for "
                          "rocprofv3 --pmc byte counters and their copy-kernel calibration)")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="only 3 launches each of the matrix-bound kernels (precision-study "
+                         "packed bf16 and e4m3 estimates on 64 frames, FP32-accurate and bf16 "
+                         "estimates of the benchmark frames), for rocprofv3 --pmc counters of "
+                         "matrix-core activity")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the quantiser/adjoint/refinement/uneven-batch timings")
     ap.add_argument("--no-workloads", action="store_true",
@@ -399,6 +404,34 @@ def front_end(plan, cfg, y, torch, lat_h2d_us, args):
                     "airtime per multiplexed block of Eq. 11 at each sample rate"}
 
 
+def mfma_probe(torch):
+    """Three launches each of the matrix-core-bound kernels on fixed seeded
+    data, nothing timed: the workload of a rocprofv3 --pmc run."""
+    from paper_2206_05506_amd import Plan
+    N, T, L, R, B = 4095, 32, 64, 256, 64      # the precision study, 64 frames
+    p = Plan(N, T, L, R)
+    y = _randn_c64((B, R, N), 11, torch)
+    H = torch.empty((B, R, T * L), dtype=torch.complex64, device="cuda")
+    for fmt in ("bf16", "e4m3"):
+        q, sc = p.pack(y, fmt)
+        for _ in range(3):
+            p.estimate_packed(q, sc, fmt, out=H)
+        del q, sc
+    p.close()
+    del y, H
+    import synth
+    cfg = synth.FP32
+    p = Plan(cfg.N, cfg.T, cfg.L, cfg.R)
+    y = _randn_c64((cfg.B, cfg.R, cfg.N), 12, torch)
+    H = torch.empty((cfg.B, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
+    for prec in ("f32s", "bf16"):
+        for _ in range(3):
+            p.estimate(y, prec, out=H)
+    torch.cuda.synchronize()
+    p.close()
+    print(json.dumps({"mfma_probe": True}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -411,6 +444,9 @@ def main():
     import synth
     from paper_2206_05506_amd import Plan
 
+    if args.mfma_probe:
+        mfma_probe(torch)
+        return
     cfg = synth.FP32
     plan = Plan(cfg.N, cfg.T, cfg.L, cfg.R)
     y, h = make_inputs(plan, cfg, torch)
@@ -459,6 +495,9 @@ def main():
 
     spin_up(step_bf16, 0.3, torch)
     ms_bf, wall_bf = time_steps(step_bf16, args.steps, args.warmup, torch)
+    # context for the roofline: a plain device copy of the same frame buffers
+    # (rotated likewise), read + write bytes over its time
+    ms_cp, _ = time_steps(lambda: ys[rot()].copy_(ys[(ctr[0] + 2) % n_rot]), args.steps, 2, torch)
     # the same launch on one resident buffer (frames and CIRs cache-resident)
     ms_bf_cached, _ = time_steps(lambda: plan.estimate(y, "bf16", out=H_bf), args.steps,
                                  args.warmup, torch)
@@ -531,6 +570,7 @@ def main():
                            "CIR buffer (5 x 201 MB > the 256 MB Infinity Cache), so frames stream "
                            "from HBM",
                    "cache_resident_ms_per_step": ms_bf_cached,
+                   "hbm_copy_GB/s": 2 * y.numel() * 8 / (ms_cp * 1e-3) / 1e9,
                    "cache_resident_GB/s": bytes_ / (ms_bf_cached * 1e-3) / 1e9},
         "roofline": {"bound": "hbm", "achieved": ach_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": ach_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),

@@ -315,3 +315,48 @@ def test_most_antennas():
         H = {prec: host(p.estimate(dev(y), prec)) for prec in ("f32s", "bf16")}
     assert oracle.relerr(H["f32s"], oracle.correlate(y, s, T * L)) <= TOL32
     assert oracle.relerr(H["bf16"], oracle.correlate(bf16_round(y), s, T * L)) <= TOL32
+
+
+def test_graph_replays_match_eager():
+    """Correlator, LS rows, quantiser + packed e4m3 estimate and adjoint
+    captured in one HIP graph. Every replay, with eager work and
+    synchronisations between replays, equals the eager results bit for bit
+    (the quantiser clears its counters with a kernel, not a memset)."""
+    N, T, L, R, B = 1023, 16, 32, 64, 4
+    y = dev(_rand_frames(N, R, B, 90))
+    with _plan(N, T, L, R) as p:
+        H_e = p.estimate(y, "bf16")
+        X_e = p.estimate_ls(y, "f32s")
+        q_e, sc_e = p.pack(y, "e4m3")
+        Hq_e = p.estimate_packed(q_e, sc_e, "e4m3")
+        A_e = p.adjoint(H_e, "f32s")
+        torch.cuda.synchronize()
+        H, X, Hq = torch.empty_like(H_e), torch.empty_like(X_e), torch.empty_like(Hq_e)
+        q, sc, A = torch.empty_like(q_e), torch.empty_like(sc_e), torch.empty_like(A_e)
+
+        def work():
+            p.estimate(y, "bf16", out=H)
+            p.estimate_ls(y, "f32s", out=X)
+            p.pack(y, "e4m3", out=q, scales=sc)
+            p.estimate_packed(q, sc, "e4m3", out=Hq)
+            p.adjoint(H, "f32s", out=A)
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            work()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            work()
+        for _ in range(3):
+            for t in (H, X, Hq, A, sc):
+                t.zero_()
+            q.fill_(0x7F)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(H, H_e) and torch.equal(X, X_e) and torch.equal(A, A_e)
+            assert torch.equal(q, q_e) and torch.equal(sc, sc_e) and torch.equal(Hq, Hq_e)
+        del g
