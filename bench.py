@@ -153,6 +153,17 @@ def p50_latency_us(fn, iters, torch):
     return statistics.median(ts)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(y_dev, cfg, target_s):
     """The FP64 oracle on a bounded sample of the same frames, on the host's
     cores (OpenMP): whole passes over the first n frames, repeated until about
@@ -169,7 +180,14 @@ def cpu_baseline(y_dev, cfg, target_s):
     for _ in range(reps):
         oracle.correlate(y[:n], s, cfg.K)
     dt = time.perf_counter() - t0
+    # one thread, on a quarter of the sample
+    n1 = max(1, n // 4)
+    t0 = time.perf_counter()
+    oracle.correlate(y[:n1], s, cfg.K, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": reps * n * cfg.R * cfg.T / dt, "unit": "CIR estimates/s",
+            "one_thread_value": n1 * cfg.R * cfg.T / dt1, "cpu_model": cpu_model(),
+            "nproc": os.cpu_count(),
             "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{reps} pass(es) over {n} of {cfg.B} frames (N={cfg.N}, T*L={cfg.K}, "
                       f"R={cfg.R}), FP64 direct correlation, {dt:.1f} s"}
@@ -341,7 +359,58 @@ def precision_workload(torch, args):
     plan.close()
     del y, H, work, X
     torch.cuda.empty_cache()
+    res["accuracy"] = precision_accuracy(torch, cfg)
     return res
+
+
+def precision_accuracy(torch, cfg, frames=8):
+    """Accuracy of the precision study's forms on `frames` frames of the
+    channel model (seeded device draws, y = P h + sigma w by the library's
+    adjoint): for the bf16- and e4m3-packed starts and k = 0..5 refinement
+    steps, the normwise error against the FP64 iterate with the same k (the
+    library's FP64 vector kernel on complex128 copies) and the NMSE against
+    h; and the FP32-accurate correlator's NMSE beside bf16's (k = 0)."""
+    from paper_2206_05506_amd import Plan
+    import synth
+    N, K, R = cfg.N, cfg.K, cfg.R
+    plan = Plan(N, cfg.T, cfg.L, R)
+    d = synth.device_draws(cfg, torch, frames=frames)
+    h = d["h"].reshape(frames, R, K)
+    y0 = plan.adjoint(h, "f32s", alpha=1.0)
+    p = (y0.abs() ** 2).mean(dim=(1, 2)).double()
+    sigma = torch.sqrt(p / 10.0 ** (d["snr_db"].double() / 10.0)).float()
+    y = (y0 + sigma[:, None, None] * d["w"]).contiguous()
+    del y0, d
+    # FP64 iterates x_{k+1} = x_k + P^T (y - P x_k) / N
+    y64 = y.to(torch.complex128)
+    x64 = [plan.estimate(y64, "f64")]
+    for _ in range(5):
+        r = y64 - plan.adjoint(x64[-1], "f64", alpha=1.0)
+        x64.append(x64[-1] + plan.estimate(r, "f64"))
+    del y64
+
+    def relerr(x, ref):
+        e = ((x.to(torch.complex128) - ref).abs() ** 2).reshape(frames, -1).sum(1)
+        n = (ref.abs() ** 2).reshape(frames, -1).sum(1)
+        return float(torch.sqrt(e / n).max())
+
+    out = {"frames": frames, "reference": "FP64 iterate with the same k (library FP64 kernel)"}
+    work = torch.empty_like(y)
+    for fmt in ("bf16", "e4m3"):
+        q, sc = plan.pack(y, fmt)
+        x0 = plan.estimate_packed(q, sc, fmt)
+        rows = []
+        for k in range(6):
+            X = x0.clone()
+            if k:
+                plan.refine(y, X, k, work=work)
+            rows.append({"k": k, "relerr_vs_fp64": relerr(X, x64[k]), "nmse_db": nmse_db(X, h)})
+        out[fmt] = rows
+        del q, sc, x0
+    out["fp32_k0_nmse_db"] = nmse_db(plan.estimate(y, "f32s"), h)
+    out["fp64_k5_nmse_db"] = nmse_db(x64[5].to(torch.complex64), h)
+    plan.close()
+    return out
 
 
 def differentiation_workload(torch, args):
@@ -539,6 +608,7 @@ def main():
     out = {
         "metric": "CIR estimates/s + p50 frame latency; BF16-MFMA vs FP32 at matched NMSE",
         "value": cirs / (ms_bf * 1e-3),
+        "frames_per_s": cfg.B / (ms_bf * 1e-3),
         "unit": "CIR estimates/s",
         "n_gpus": 1,
         "steps": args.steps,

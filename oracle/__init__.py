@@ -62,6 +62,8 @@ def _load():
         fn.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -162,11 +164,12 @@ def _lag_array(K: int, lag) -> np.ndarray:
     return lag
 
 
-def correlate(Y, s, K: int, lag=None) -> np.ndarray:
+def correlate(Y, s, K: int, lag=None, threads=None) -> np.ndarray:
     """H[b,r,k] = (1/N) sum_n Y[b,r,n] s[(n-lag[k]) mod N], k < K (Eq. 3, Eq. 10).
 
-    Y: [B, R, N] complex; lag: [K] ints (default k, the adjacent blocks).
-    Returns [B, R, K] complex128. The CIR of transmitter t sits at
+    Y: [B, R, N] complex; lag: [K] ints (default k, the adjacent blocks);
+    threads: OpenMP threads for this call (default: all). Returns
+    [B, R, K] complex128. The CIR of transmitter t sits at
     H[..., t*L:(t+1)*L] (the de-multiplexing of Eq. 10).
     """
     Y = _as_c128(Y, 3)
@@ -176,8 +179,16 @@ def correlate(Y, s, K: int, lag=None) -> np.ndarray:
         raise ValueError("sequence length does not match Y")
     lag = _lag_array(int(K), lag)
     H = np.empty((B, R, K), dtype=np.complex128)
-    _load().oracle_correlate(_dp(Y.view(np.float64)), _sp(s), N, _ip(lag), int(K), B, R,
+    lib = _load()
+    before = lib.oracle_threads()
+    if threads:
+        lib.oracle_set_threads(int(threads))
+    try:
+        lib.oracle_correlate(_dp(Y.view(np.float64)), _sp(s), N, _ip(lag), int(K), B, R,
                              _dp(H.view(np.float64)))
+    finally:
+        if threads:
+            lib.oracle_set_threads(before)
     return H
 
 

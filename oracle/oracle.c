@@ -177,6 +177,17 @@ void oracle_adjoint(const double *G, const signed char *s, int N,
     }
 }
 
+/* Threads for later parallel regions (n <= 0 leaves the setting). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of OpenMP threads a parallel region of this library will use. */
 int oracle_threads(void)
 {
