@@ -579,7 +579,7 @@ def main():
 
     y1 = y[:1].contiguous()
     H1 = torch.empty((1, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
-    lat_bf = lat_32 = lat_h2d = None
+    lat_bf = lat_32 = lat_h2d = lat_plain = None
     if args.latency_iters > 0:
         lat_bf = p50_latency_us(lambda: plan.estimate(y1, "bf16", out=H1), args.latency_iters,
                                 torch)
@@ -595,6 +595,14 @@ def main():
             plan.estimate(y1_dev, "bf16", out=H1)
 
         lat_h2d = p50_latency_us(h2d_then_estimate, args.latency_iters, torch)
+        # the plain workload (N=127, T=4, L=16, R=16, one frame)
+        pc = synth.PLAIN
+        pp = Plan(pc.N, pc.T, pc.L, pc.R)
+        yp = _randn_c64((1, pc.R, pc.N), 13, torch)
+        Hp = torch.empty((1, pc.R, pc.K), dtype=torch.complex64, device="cuda")
+        lat_plain = {prec: p50_latency_us(lambda: pp.estimate(yp, prec, out=Hp),
+                                          args.latency_iters, torch) for prec in ("bf16", "f32s")}
+        pp.close()
 
     nmse_bf = nmse_db(H_bf, h)
     nmse_32 = nmse_db(H_32, h)
@@ -622,7 +630,8 @@ def main():
         "config": {"workload": cfg.name, "N": cfg.N, "T": cfg.T, "L": cfg.L, "R": cfg.R,
                    "frames": cfg.B, "input": "complex64", "snr_db": [cfg.snr_lo, cfg.snr_hi]},
         "p50_frame_latency_us": {"bf16": lat_bf, "fp32": lat_32,
-                                 "bf16_with_h2d_copy": lat_h2d},
+                                 "bf16_with_h2d_copy": lat_h2d,
+                                 "plain_workload": lat_plain},
         "fp32_path": {"value": cirs / (ms_32 * 1e-3), "ms_per_step": ms_32,
                       "precision": "f32s (3-way bf16 split, exact)"},
         "fp32_mfma_path": {"value": cirs / (ms_mf * 1e-3), "ms_per_step": ms_mf,
