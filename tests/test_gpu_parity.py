@@ -360,3 +360,53 @@ def test_graph_replays_match_eager():
             assert torch.equal(H, H_e) and torch.equal(X, X_e) and torch.equal(A, A_e)
             assert torch.equal(q, q_e) and torch.equal(sc, sc_e) and torch.equal(Hq, Hq_e)
         del g
+
+
+def _random_cases(n, seed):
+    """Seeded random shapes: degree 2..12, any T and L with T*L <= 4N, R up to
+    100, 1..3 frames, adjacent or Eq. 8 lags (when T*L <= N), the built-in or
+    another primitive polynomial (d <= 10); oracle work kept under 4e7."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        d = int(rng.integers(2, 13))
+        N = (1 << d) - 1
+        T = int(rng.integers(1, 9))
+        L = int(rng.integers(1, max(2, (4 * N) // T) + 1))
+        R = int(rng.integers(1, 101))
+        B = int(rng.integers(1, 4))
+        if T * L > 4 * N or B * R * N * T * L > 4e7:
+            continue
+        spacing = "eq8" if T * L <= N and rng.random() < 0.5 else "adjacent"
+        fb = 0
+        if d <= 10 and rng.random() < 0.5:
+            masks = oracle.primitive_masks(d)
+            fb = int(masks[int(rng.integers(len(masks)))])
+        out.append((N, T, L, R, B, spacing, fb))
+    return out
+
+
+@pytest.mark.parametrize("case", _random_cases(40, 2026),
+                         ids=lambda c: "N%d_T%d_L%d_R%d_B%d_%s_fb%x" % c)
+def test_random_shapes(case):
+    N, T, L, R, B, spacing, fb = case
+    K = T * L
+    y = _rand_frames(N, R, B, N + K + R)
+    G = synth.gaussian((B, R, K), K + 7).astype(np.complex64)
+    from paper_2206_05506_amd import Plan
+    with Plan(N, T, L, R, feedback=fb, spacing=spacing) as p:
+        s, lag = p.sequence(), p.lags()
+        yd = dev(y)
+        Hb = host(p.estimate(yd, "bf16"))
+        Hs = host(p.estimate(yd, "f32s"))
+        A = host(p.adjoint(dev(G), "f32s"))
+        X = host(p.estimate_ls(yd, "f32s")) if K <= N else None
+    if fb:
+        assert np.array_equal(s, oracle.mseq_mask(oracle.degree_of(N), fb))
+    assert np.array_equal(lag, oracle.lags(N, T, L, "eq8" if spacing == "eq8" else "contiguous"))
+    ref = oracle.correlate(y, s, K, lag)
+    assert oracle.relerr(Hs, ref) <= TOL32
+    assert oracle.relerr(Hb, oracle.correlate(bf16_round(y), s, K, lag)) <= TOL32
+    assert oracle.relerr(A, oracle.adjoint(G, s, lag)) <= TOL32
+    if X is not None:
+        assert oracle.relerr(X, oracle.ls_closed_form(ref, N)) <= TOL32
