@@ -410,3 +410,29 @@ def test_random_shapes(case):
     assert oracle.relerr(A, oracle.adjoint(G, s, lag)) <= TOL32
     if X is not None:
         assert oracle.relerr(X, oracle.ls_closed_form(ref, N)) <= TOL32
+
+
+def test_one_plan_on_two_streams_concurrently():
+    """A plan is immutable: estimates and adjoints enqueued on two streams at
+    once, interleaved, give the same bits as the same calls one at a time."""
+    N, T, L, R, B = 1023, 16, 32, 64, 8
+    ya = dev(_rand_frames(N, R, B, 91))
+    yb = dev(_rand_frames(N, R, B, 92))
+    with _plan(N, T, L, R) as p:
+        ref_a, ref_b = p.estimate(ya, "bf16"), p.estimate(yb, "f32s")
+        ref_aa = p.adjoint(ref_a, "f32s")
+        torch.cuda.synchronize()
+        sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+        sa.wait_stream(torch.cuda.current_stream())
+        sb.wait_stream(torch.cuda.current_stream())
+        outs = []
+        for _ in range(4):
+            with torch.cuda.stream(sa):
+                Ha = p.estimate(ya, "bf16")
+                Aa = p.adjoint(Ha, "f32s")
+            with torch.cuda.stream(sb):
+                Hb = p.estimate(yb, "f32s")
+            outs.append((Ha, Aa, Hb))
+        torch.cuda.synchronize()
+        for Ha, Aa, Hb in outs:
+            assert torch.equal(Ha, ref_a) and torch.equal(Hb, ref_b) and torch.equal(Aa, ref_aa)
