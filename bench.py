@@ -171,9 +171,10 @@ def cpu_baseline(y_dev, cfg, target_s):
     import oracle
     s = oracle.mseq(cfg.d)
     y = y_dev.cpu().numpy()
+    oracle.correlate(y[:2], s, cfg.K)                      # warm-up (threads, pages)
     t0 = time.perf_counter()
-    oracle.correlate(y[:2], s, cfg.K)
-    per_frame = (time.perf_counter() - t0) / 2
+    oracle.correlate(y[:8], s, cfg.K)
+    per_frame = (time.perf_counter() - t0) / 8
     n = int(max(1, min(cfg.B, round(target_s / max(per_frame, 1e-4)))))
     reps = int(max(1, round(target_s / (per_frame * n))))
     t0 = time.perf_counter()
