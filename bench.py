@@ -303,6 +303,11 @@ def uneven_batch(torch, args):
     cirs = sum(R * T for R, N, T, L in shapes)
     byt = vp.n_codes * 2 + vp.n_out * 8
     flops = sum(4.0 * R * N * T * L for R, N, T, L in shapes)
+    # per frame the tighter of the two roofs: short-lag frames are bound by
+    # HBM, long-lag ones (AI up to ~1000) by the matrix cores
+    roof_us = sum(max((R * 2 * (N + 1) * 2 + R * T * L * 8) / (HBM_PEAK_GBS * 1e3),
+                      4.0 * R * N * T * L / (BF16_PEAK_TFLOPS * 1e6))
+                  for R, N, T, L in shapes)
     st = vp.stats()
     vp.close()
     return {"frames": len(shapes), "persistent_ms": ms_p, "untuned_ms": ms_u,
@@ -311,6 +316,7 @@ def uneven_batch(torch, args):
             "speedup": ms_e / ms_p, "CIR/s": cirs / (ms_p * 1e-3),
             "GB/s": byt / ms_p / 1e6, "hbm_frac": byt / ms_p / 1e6 / HBM_PEAK_GBS,
             "mfma_frac": flops / ms_p / 1e9 / BF16_PEAK_TFLOPS,
+            "per_frame_roofline_us": roof_us, "per_frame_roofline_frac": roof_us / (ms_p * 1e3),
             "workgroups": st["workgroups"], "tiles": st["tiles"]}
 
 
