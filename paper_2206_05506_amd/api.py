@@ -50,6 +50,10 @@ def _need(t: torch.Tensor, shape, dtype, name):
         raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if t.is_conj() or t.is_neg():
+        # a lazily conjugated or negated view: its memory holds the other values
+        raise ValueError(f"{name} is a conjugate or negative view; call .resolve_conj() / "
+                         ".resolve_neg() first")
 
 
 SPACINGS = {"adjacent": _lib.PNCE_LAGS_ADJACENT, "eq8": _lib.PNCE_LAGS_EQ8}

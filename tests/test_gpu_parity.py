@@ -436,3 +436,16 @@ def test_one_plan_on_two_streams_concurrently():
         torch.cuda.synchronize()
         for Ha, Aa, Hb in outs:
             assert torch.equal(Ha, ref_a) and torch.equal(Hb, ref_b) and torch.equal(Aa, ref_aa)
+
+
+def test_lazy_conjugate_views_are_refused():
+    """torch's conj() only flips a flag; the library reads memory, so such a
+    view must be resolved first (refused, not silently mis-read)."""
+    N, T, L, R = 127, 4, 16, 4
+    y = dev(_rand_frames(N, R, 1, 93))
+    with _plan(N, T, L, R) as p:
+        with pytest.raises(ValueError):
+            p.estimate(y.conj(), "f32s")
+        H = host(p.estimate(y.conj().resolve_conj(), "f32s"))
+        ref = oracle.correlate(np.conj(host(y)), p.sequence(), T * L)
+    assert oracle.relerr(H, ref) <= TOL32
