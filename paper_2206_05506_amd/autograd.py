@@ -16,6 +16,12 @@ import torch
 from .api import Plan
 
 
+def _plain(t: torch.Tensor) -> torch.Tensor:
+    """Contiguous memory holding the tensor's values (conjugate and negative
+    views resolved): the library reads memory, not view flags."""
+    return t.resolve_conj().resolve_neg().contiguous()
+
+
 class PnceCorrelate(torch.autograd.Function):
     """H = Y P / N; grad_Y = grad_H P^T / N (pnce_adjoint with alpha = 1/N)."""
 
@@ -23,13 +29,13 @@ class PnceCorrelate(torch.autograd.Function):
     def forward(ctx, Y, plan: Plan, precision: str):
         ctx.plan = plan
         ctx.precision = precision
-        return plan.estimate(Y.contiguous(), precision)
+        return plan.estimate(_plain(Y), precision)
 
     @staticmethod
     def backward(ctx, gH):
         gY = None
         if ctx.needs_input_grad[0]:
-            gY = ctx.plan.adjoint(gH.contiguous(), ctx.precision)
+            gY = ctx.plan.adjoint(_plain(gH), ctx.precision)
         return gY, None, None
 
 
@@ -41,13 +47,13 @@ class PnceSynthesize(torch.autograd.Function):
     def forward(ctx, X, plan: Plan, precision: str):
         ctx.plan = plan
         ctx.precision = precision
-        return plan.adjoint(X.contiguous(), precision, alpha=1.0)
+        return plan.adjoint(_plain(X), precision, alpha=1.0)
 
     @staticmethod
     def backward(ctx, gY):
         gX = None
         if ctx.needs_input_grad[0]:
-            gX = ctx.plan.estimate(gY.contiguous(), ctx.precision, alpha=1.0)
+            gX = ctx.plan.estimate(_plain(gY), ctx.precision, alpha=1.0)
         return gX, None, None
 
 

@@ -92,3 +92,21 @@ def test_differentiation_workload_refinement_trajectory():
         assert err <= 1e-5
         assert np.allclose(traj[k], ref_l, rtol=1e-5)
     assert len(losses) == 6 and np.all(np.isfinite(losses))
+
+
+def test_autograd_through_conjugate_views():
+    """Inputs and incoming gradients that are lazy conjugate views are
+    resolved before the kernels read them."""
+    from paper_2206_05506_amd.autograd import correlate
+    N, T, L, R, B = 63, 3, 8, 4, 2
+    Y = synth.gaussian((B, R, N), 31).astype(np.complex64)
+    G = synth.gaussian((B, R, T * L), 32).astype(np.complex64)
+    with _plan(N, T, L, R) as p:
+        Yd = dev(Y).requires_grad_(True)
+        H = correlate(Yd.conj(), p, "f32s")
+        (gY,) = torch.autograd.grad(H, Yd, grad_outputs=dev(G).conj())
+        s = p.sequence()
+        Hh = host(H)
+    assert oracle.relerr(Hh, oracle.correlate(np.conj(Y), s, T * L)) <= 1e-5
+    # d/dY of conj(Y) P with incoming conj(G): conj(conj(G) P^T / N) = G P^T / N
+    assert oracle.relerr(host(gY), oracle.adjoint(G, s)) <= 1e-5
