@@ -1,0 +1,50 @@
+"""The C ABI from a plain C program (tests/c_client): plan, device buffers
+and one correlator call with no Python in the process; its output checked
+against the FP64 oracle, and its error statuses."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import bf16_round
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CLIENT = os.path.join(HERE, "c_client", "pnce_c_client")
+
+
+def _run(args, tmp_path, y):
+    if not os.path.exists(CLIENT):
+        pytest.fail("tests/c_client/pnce_c_client is not built (python tests/c_client/build.py)")
+    fin, fout = str(tmp_path / "y.bin"), str(tmp_path / "h.bin")
+    np.ascontiguousarray(y, dtype=np.complex64).tofile(fin)
+    p = subprocess.run([CLIENT] + [str(a) for a in args] + [fin, fout], capture_output=True,
+                       text=True, timeout=60)
+    return p, fout
+
+
+@pytest.mark.parametrize("prec", [1, 2])   # PNCE_PREC_F32S, PNCE_PREC_BF16
+@pytest.mark.parametrize("spacing,fb", [(0, 0), (1, 0x3F9)])
+def test_c_client_estimate(tmp_path, prec, spacing, fb):
+    N, T, L, R, B = 1023, 16, 32, 64, 2
+    y = synth.gaussian((B, R, N), 41).astype(np.complex64)
+    p, fout = _run([N, T, L, R, B, prec, fb, spacing], tmp_path, y)
+    assert p.returncode == 0, p.stderr
+    H = np.fromfile(fout, dtype=np.complex64).reshape(B, R, T * L)
+    s = oracle.mseq_mask(10, fb) if fb else oracle.mseq(10)
+    lag = oracle.lags(N, T, L, "eq8" if spacing else "contiguous")
+    x = bf16_round(y) if prec == 2 else y.astype(np.complex128)
+    assert oracle.relerr(H, oracle.correlate(x, s, T * L, lag)) <= 1e-5
+
+
+def test_c_client_error_statuses(tmp_path):
+    y = np.zeros((1, 4, 1000), dtype=np.complex64)
+    p, _ = _run([1000, 2, 8, 4, 1, 2, 0, 0], tmp_path, y)     # N not 2^d - 1
+    assert p.returncode == 10 - (-2) and "N must be" in p.stderr
+    y = np.zeros((1, 4, 127), dtype=np.complex64)
+    p, _ = _run([127, 2, 8, 4, 1, 9, 0, 0], tmp_path, y)      # unknown precision
+    assert p.returncode == 10 - (-1) and "precision" in p.stderr
