@@ -171,3 +171,50 @@ def test_lag_and_feedback_queries_reject_null_plan(lib):
     assert lib.pnce_get_lags(None, None) == -1
     lib.pnce_get_feedback.argtypes = [P, P]
     assert lib.pnce_get_feedback(None, None) == -1
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int), ("N", ctypes.c_int), ("T", ctypes.c_int),
+                ("L", ctypes.c_int), ("y_off", ctypes.c_longlong), ("h_off", ctypes.c_longlong)]
+
+
+@pytest.mark.parametrize("frames,fmt,want", [
+    ([(32, 1000, 4, 16, 0, 0)], 1, -2),          # N not 2^d - 1
+    ([(32, 255, 4, 16, 0, 0), (32, 511, 0, 16, 8192, 4096)], 1, -1),   # T = 0 in frame 1
+    ([(70000, 255, 4, 16, 0, 0)], 1, -1),        # R above 65535
+    ([(32, 255, 4, 16 * 255, 0, 0)], 1, -1),     # T*L > 16 N
+    ([(32, 255, 4, 16, 4, 0)], 1, -1),           # y_off not a multiple of 8
+    ([(32, 255, 4, 16, -8, 0)], 1, -1),          # negative offset
+    ([(32, 255, 4, 16, 0, 0)], 3, -1),           # e4m3 is not a varlen format
+    ([], 1, -1),                                 # no frames
+])
+def test_varlen_create_validates_before_touching_the_device(lib, frames, fmt, want):
+    arr = (_Desc * max(1, len(frames)))(*[_Desc(*f) for f in frames])
+    h = ctypes.c_void_p()
+    lib.pnce_varlen_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                       ctypes.c_int, ctypes.c_int]
+    st = lib.pnce_varlen_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p), len(frames),
+                                fmt)
+    assert st == want
+    assert not h.value
+
+
+def test_more_entry_points_reject_null_plan(lib):
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    lib.pnce_estimate_cp.argtypes = [P, P, P, I, P, I, I, P]
+    assert lib.pnce_estimate_cp(None, None, None, 0, None, 1, 1, None) == -1
+    lib.pnce_pack_cp.argtypes = [P, P, P, I, P, P, I, I]
+    assert lib.pnce_pack_cp(None, None, None, 0, None, None, 1, 1) == -1
+    lib.pnce_estimate_packed.argtypes = [P, P, P, P, P, I, I, ctypes.c_double]
+    assert lib.pnce_estimate_packed(None, None, None, None, None, 1, 1, 0.0) == -1
+    lib.pnce_get_shape.argtypes = [P, P, P, P, P]
+    assert lib.pnce_get_shape(None, None, None, None, None) == -1
+    for name in ("pnce_varlen_estimate", "pnce_varlen_estimate_each"):
+        fn = getattr(lib, name)
+        fn.argtypes = [P, P, P, P, P]
+        assert fn(None, None, None, None, None) == -1
+    lib.pnce_varlen_tune.argtypes = [P, P, P, P, P, I]
+    assert lib.pnce_varlen_tune(None, None, None, None, None, 1) == -1
+    lib.pnce_varlen_destroy.argtypes = [P]
+    assert lib.pnce_varlen_destroy(None) == 0
