@@ -70,7 +70,8 @@ def test_differentiation_workload_refinement_trajectory():
     1024 frames, complex64): 5 refinement steps as gradient descent on
     ||y - P x||^2 through autograd. Every iterate matches the oracle's FP64
     iterate with the same step count on sampled frames, and so does each
-    sampled frame's loss trajectory."""
+    sampled frame's loss trajectory; so does the library's own five-step
+    refinement of the whole batch."""
     from paper_2206_05506_amd.autograd import refine_by_gradient
     cfg = synth.DIFF
     pick = [0, 511, 1023]
@@ -84,7 +85,14 @@ def test_differentiation_workload_refinement_trajectory():
         xs, losses = refine_by_gradient(yd, p, 5, "f32s")
         traj = [host(_per_frame_loss(yd, x, p))[pick] for x in xs]
         got = [host(x[pick]) for x in xs]
+        del xs
+        X = p.estimate(yd, "f32s")
+        p.refine(yd, X, 5)                       # the library's own refinement
+        lib5 = host(X[pick])
     its = oracle.refine(y[pick], s, cfg.K, 5)
+    err = oracle.relerr(lib5, its[5])
+    print(f"library refinement, 5 steps: relerr {err:.2e}")
+    assert err <= 1e-5
     for k in range(6):
         err = oracle.relerr(got[k], its[k])
         ref_l = [oracle.loss_grad(y[pick][i:i + 1], s, its[k][i:i + 1])[0] for i in range(3)]

@@ -154,6 +154,32 @@ def test_lag_alias_when_T_L_exceeds_N():
     assert np.max(np.abs(H[..., N:] - H[..., :9])) < 1e-14
 
 
+@pytest.mark.parametrize("d", [5, 7])
+def test_refinement_with_an_aliased_lag_grows_along_one_direction(d):
+    """K = N + 1 lags (every lag once, lag 0 twice, as in the differentiation
+    workload's 16*64 > 1023): P P^T = (N+1) I - J + s s^T, whose nonzero
+    eigenvalues are N+1 (multiplicity N-2) and N+1 +- sqrt(N^2 - 1) on the
+    span of {1, s}. A step of 1/N therefore multiplies the residual along the
+    top eigenvector by (N+1+sqrt(N^2-1))/N - 1 > 1: the iteration is slightly
+    unstable there, and the oracle's refinement must show that exact rate."""
+    s = oracle.mseq(d)
+    N = s.size
+    K = N + 1
+    P = dense_P(s, K)
+    w, V = np.linalg.eigh(P @ P.T)
+    top = N + 1 + np.sqrt(N * N - 1.0)
+    assert abs(w[-1] - top) < 1e-9 * top
+    assert abs(w[0] - (N + 1 - np.sqrt(N * N - 1.0))) < 1e-9 * N
+    assert np.allclose(w[1:-1], N + 1)
+    y = (V[:, -1] * (0.8 - 0.6j)).reshape(1, 1, N)
+    its = oracle.refine(y, s, K, 4)
+    r = [np.linalg.norm(y[0, 0] - P @ x[0, 0]) for x in its]
+    rate = top / N - 1
+    assert rate > 1
+    for j in range(4):
+        assert abs(r[j + 1] / r[j] - rate) < 1e-12
+
+
 # ------------------------------------------------------------ a7: adjoint
 @pytest.mark.parametrize("d,K", [(5, 8), (5, 40), (7, 64)])
 def test_adjoint_brute_force_and_dot_identity(d, K):
