@@ -166,8 +166,8 @@ def cpu_model():
 
 def cpu_baseline(y_dev, cfg, target_s):
     """The FP64 oracle on a bounded sample of the same frames, on the host's
-    cores (OpenMP): whole passes over the first n frames, repeated until about
-    target_s seconds of work. Returns the cpu_baseline object of the JSON line."""
+    cores (OpenMP): whole passes over the first n frames, repeated until at
+    least target_s seconds of work (one pass is at most about target_s). Returns the cpu_baseline object of the JSON line."""
     import oracle
     s = oracle.mseq(cfg.d)
     y = y_dev.cpu().numpy()
@@ -176,11 +176,14 @@ def cpu_baseline(y_dev, cfg, target_s):
     oracle.correlate(y[:8], s, cfg.K)
     per_frame = (time.perf_counter() - t0) / 8
     n = int(max(1, min(cfg.B, round(target_s / max(per_frame, 1e-4)))))
-    reps = int(max(1, round(target_s / (per_frame * n))))
+    reps = 0
     t0 = time.perf_counter()
-    for _ in range(reps):
+    while True:                                  # whole passes until target_s is reached
         oracle.correlate(y[:n], s, cfg.K)
-    dt = time.perf_counter() - t0
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= target_s:
+            break
     # one thread, on a quarter of the sample
     n1 = max(1, n // 4)
     t0 = time.perf_counter()
