@@ -33,6 +33,10 @@
  *  - Return value: 0 = PNCE_OK; > 0 = a warning, the call did its work;
  *    < 0 = an error, nothing was enqueued and no output was touched. The
  *    text of the last error on the calling thread is pnce_last_error().
+ *  - An empty batch (batch == 0) is valid: once the plan and the other
+ *    scalar arguments (precision, format, cp, steps) pass their checks, the
+ *    call returns PNCE_OK without reading its tensor pointers, which may be
+ *    NULL, and enqueues nothing.
  *  - No C++ exception and no abort crosses this boundary.
  *  - A plan is immutable after pnce_create; calls on one plan from several
  *    host threads or streams are safe, except that pnce_refine uses the
@@ -144,7 +148,7 @@ pnce_status pnce_get_shape(const pnce_plan *plan, int *N, int *T, int *L, int *R
  * H: [batch][R][T*L] c64 (c128 for PNCE_PREC_F64), read only if beta != 0;
  * scales: NULL or `batch` device floats. Y and H must not overlap.
  * precision: PNCE_PREC_F32, _F32S, _BF16, _F64 or _F64ACC.
- * Errors: null Y/H, batch <= 0, unknown precision -> PNCE_E_INVALID.
+ * Errors: null Y/H, batch < 0, unknown precision -> PNCE_E_INVALID.
  */
 pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y,
                           void *H, int batch, int precision, double alpha,
@@ -161,7 +165,7 @@ pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y,
  * bf16/f16 and 1 byte for e4m3: per antenna the real plane then the
  * imaginary plane, each padded with one zero sample. scales: [batch] float.
  * Runs two kernels (per-frame max, then convert) on `stream`.
- * Errors: null pointer, batch <= 0, bad format -> PNCE_E_INVALID.
+ * Errors: null pointer, batch < 0, bad format -> PNCE_E_INVALID.
  */
 pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y,
                       void *Yq, float *scales, int batch, int format);
@@ -171,7 +175,7 @@ pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y,
  * accumulation on bf16 / f16 / fp8 matrix cores; the +-1 operand is exact in
  * every format. H = (scales[b] / N) * (Yq P) + beta * H, H [batch][R][T*L]
  * c64. scales may be NULL (all 1).
- * Errors: null Yq/H, batch <= 0, bad format -> PNCE_E_INVALID.
+ * Errors: null Yq/H, batch < 0, bad format -> PNCE_E_INVALID.
  */
 pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream,
                                  const void *Yq, const float *scales, void *H,

@@ -214,6 +214,8 @@ class Plan:
         last estimate."""
         if not Y_host.is_pinned():
             raise ValueError("Y_host must be in pinned host memory")
+        if int(chunk) < 1:
+            raise ValueError("chunk must be >= 1")
         F = Y_host.shape[0]
         _need_host(Y_host, (F, self.R, self.N + cp), torch.complex64, "Y_host")
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -280,8 +282,10 @@ class Plan:
         B = y.shape[0]
         _need(y, (B, self.R, self.N), torch.complex64, "y")
         _need(X, (B, self.R, self.K), torch.complex64, "X")
-        if work is None and steps > 0:
-            work = torch.empty((B, self.R, self.N), dtype=torch.complex64, device=y.device)
+        if steps > 0:
+            if work is None:
+                work = torch.empty((B, self.R, self.N), dtype=torch.complex64, device=y.device)
+            _need(work, (B, self.R, self.N), torch.complex64, "work")
         _lib.pnce_refine(self.handle, _stream(), _ptr(y), _ptr(X), _ptr(work), B, steps)
         return X
 

@@ -113,8 +113,10 @@ pnce_status check_plan(const pnce_plan *p) {
   return PNCE_OK;
 }
 
+// Called after the early return for an empty batch (batch == 0: nothing to
+// do, the tensor pointers are not read, PNCE_OK).
 pnce_status check_batch(const pnce_plan *p, int batch) {
-  if (batch <= 0) return fail(PNCE_E_INVALID, "batch must be positive");
+  if (batch < 0) return fail(PNCE_E_INVALID, "batch must be >= 0");
   if ((long)batch * p->R > 0x7FFFFFFFL / 2)
     return fail(PNCE_E_INVALID, "batch * R too large");
   return PNCE_OK;
@@ -356,19 +358,21 @@ pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y, vo
                           int batch, int precision, double alpha, const float *scales,
                           double beta) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
+  if (batch == 0) return PNCE_OK;
   if (!Y || !H) return fail(PNCE_E_INVALID, "Y and H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
-  if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
   return run_fwd(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
                  beta != 0.0 ? H : nullptr, scales, batch, alpha, beta);
 }
 
 pnce_status pnce_debias(const pnce_plan *plan, void *stream, void *H, int batch) {
   if (pnce_status st = check_plan(plan)) return st;
-  if (!H) return fail(PNCE_E_INVALID, "H must be non-NULL");
-  if (pnce_status st = check_batch(plan, batch)) return st;
   if (plan->K > plan->N)
     return fail(PNCE_E_UNSUPPORTED, "T*L > N: least squares is not unique");
+  if (batch == 0) return PNCE_OK;
+  if (!H) return fail(PNCE_E_INVALID, "H must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
   hipError_t e = pnce::launch_debias((float *)H, (long)batch * plan->R, plan->K, plan->N,
                                      (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "debias launch");
@@ -378,12 +382,13 @@ pnce_status pnce_debias(const pnce_plan *plan, void *stream, void *H, int batch)
 pnce_status pnce_estimate_ls(const pnce_plan *plan, void *stream, const void *Y, void *H,
                              int batch, int precision, const float *scales) {
   if (pnce_status st = check_plan(plan)) return st;
-  if (!Y || !H) return fail(PNCE_E_INVALID, "Y and H must be non-NULL");
-  if (pnce_status st = check_batch(plan, batch)) return st;
   if (precision != PNCE_PREC_F32 && precision != PNCE_PREC_F32S && precision != PNCE_PREC_BF16)
     return fail(PNCE_E_INVALID, "estimate_ls precision must be F32, F32S or BF16");
   if (plan->K > plan->N)
     return fail(PNCE_E_UNSUPPORTED, "T*L > N: least squares is not unique");
+  if (batch == 0) return PNCE_OK;
+  if (!Y || !H) return fail(PNCE_E_INVALID, "Y and H must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
   return run_fwd(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
                  nullptr, scales, batch, 1.0 / plan->N, 0.0, true);
 }
@@ -391,9 +396,10 @@ pnce_status pnce_estimate_ls(const pnce_plan *plan, void *stream, const void *Y,
 pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y, void *Yq,
                       float *scales, int batch, int format) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
+  if (batch == 0) return PNCE_OK;
   if (!Y || !Yq || !scales) return fail(PNCE_E_INVALID, "Y, Yq and scales must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
-  if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
   hipError_t e = pnce::launch_pack((const float *)Y, Yq, scales, batch, plan->R, plan->N,
                                    plan->N, format, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pack launch");
@@ -412,10 +418,11 @@ static pnce_status check_cp(const pnce_plan *plan, int cp) {
 pnce_status pnce_estimate_cp(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
                              void *H, int batch, int precision, const float *scales) {
   if (pnce_status st = check_plan(plan)) return st;
-  if (!Y_raw || !H) return fail(PNCE_E_INVALID, "Y_raw and H must be non-NULL");
-  if (pnce_status st = check_batch(plan, batch)) return st;
   if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
   if (pnce_status st = check_cp(plan, cp)) return st;
+  if (batch == 0) return PNCE_OK;
+  if (!Y_raw || !H) return fail(PNCE_E_INVALID, "Y_raw and H must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
   const size_t esz = precision == PNCE_PREC_F64 ? 16 : 8;
   const void *Y = (const char *)Y_raw + (size_t)cp * esz;
   return run_fwd(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N + cp,
@@ -425,10 +432,11 @@ pnce_status pnce_estimate_cp(const pnce_plan *plan, void *stream, const void *Y_
 pnce_status pnce_pack_cp(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
                          void *Yq, float *scales, int batch, int format) {
   if (pnce_status st = check_plan(plan)) return st;
-  if (!Y_raw || !Yq || !scales) return fail(PNCE_E_INVALID, "Y_raw, Yq and scales must be non-NULL");
-  if (pnce_status st = check_batch(plan, batch)) return st;
   if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
   if (pnce_status st = check_cp(plan, cp)) return st;
+  if (batch == 0) return PNCE_OK;
+  if (!Y_raw || !Yq || !scales) return fail(PNCE_E_INVALID, "Y_raw, Yq and scales must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
   const float *Y = (const float *)Y_raw + (size_t)cp * 2;
   hipError_t e = pnce::launch_pack(Y, Yq, scales, batch, plan->R, plan->N, plan->N + cp, format,
                                    (hipStream_t)stream);
@@ -440,9 +448,10 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream, const void
                                  const float *scales, void *H, int batch, int format,
                                  double beta) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
+  if (batch == 0) return PNCE_OK;
   if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
-  if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
   const int in_fmt = format == PNCE_FMT_BF16  ? pnce::IN_BF16
                      : format == PNCE_FMT_F16 ? pnce::IN_F16
                                               : pnce::IN_E4M3;
@@ -455,10 +464,11 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream, const void
 pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G, void *A,
                          const void *C, int batch, int precision, double alpha, double beta) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
+  if (batch == 0) return PNCE_OK;
   if (!G || !A) return fail(PNCE_E_INVALID, "G and A must be non-NULL");
   if (beta != 0.0 && !C) return fail(PNCE_E_INVALID, "C must be non-NULL when beta != 0");
   if (pnce_status st = check_batch(plan, batch)) return st;
-  if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
   return run_adj(plan, (hipStream_t)stream, precision, G, A, beta != 0.0 ? C : nullptr, batch,
                  alpha, beta);
 }
@@ -466,9 +476,10 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G, voi
 pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void *X,
                         void *work, int batch, int steps) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (steps < 0) return fail(PNCE_E_INVALID, "steps must be >= 0");
+  if (batch == 0) return PNCE_OK;
   if (!y || !X || (!work && steps > 0)) return fail(PNCE_E_INVALID, "y, X and work must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
-  if (steps < 0) return fail(PNCE_E_INVALID, "steps must be >= 0");
   hipStream_t s = (hipStream_t)stream;
   for (int j = 0; j < steps; ++j) {
     // r = y - P x   (P x = sum_k x[k] s[(n-k) mod N]: adjoint stream, alpha -1)

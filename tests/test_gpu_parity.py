@@ -449,3 +449,53 @@ def test_lazy_conjugate_views_are_refused():
         H = host(p.estimate(y.conj().resolve_conj(), "f32s"))
         ref = oracle.correlate(np.conj(host(y)), p.sequence(), T * L)
     assert oracle.relerr(H, ref) <= TOL32
+
+
+def test_empty_batch_is_a_no_op():
+    """batch == 0 through the C ABI: every batch entry point returns PNCE_OK
+    with NULL tensor pointers and enqueues nothing, while its other scalar
+    arguments are still checked; the Python wrappers return empty outputs."""
+    from paper_2206_05506_amd import _lib
+    lib = _lib.lib
+    N, T, L, R = 127, 4, 16, 4
+    with _plan(N, T, L, R) as p:
+        h = p.handle
+        assert lib.pnce_estimate(h, None, None, None, 0, 1, 1.0 / N, None, 0.0) == 0
+        assert lib.pnce_estimate_ls(h, None, None, None, 0, 1, None) == 0
+        assert lib.pnce_debias(h, None, None, 0) == 0
+        assert lib.pnce_pack(h, None, None, None, None, 0, 1) == 0
+        assert lib.pnce_estimate_packed(h, None, None, None, None, 0, 1, 0.0) == 0
+        assert lib.pnce_adjoint(h, None, None, None, None, 0, 1, 1.0 / N, 0.0) == 0
+        assert lib.pnce_refine(h, None, None, None, None, 0, 3) == 0
+        assert lib.pnce_estimate_cp(h, None, None, 8, None, 0, 1, None) == 0
+        assert lib.pnce_pack_cp(h, None, None, 8, None, None, 0, 1) == 0
+        # the scalar arguments are checked before the early return
+        assert lib.pnce_estimate(h, None, None, None, 0, 99, 1.0, None, 0.0) == -1
+        assert lib.pnce_pack(h, None, None, None, None, 0, 99) == -1
+        assert lib.pnce_refine(h, None, None, None, None, 0, -1) == -1
+        assert lib.pnce_estimate_cp(h, None, None, -1, None, 0, 1, None) == -1
+        assert lib.pnce_estimate(h, None, None, None, -1, 1, 1.0, None, 0.0) == -1
+        y = torch.empty((0, R, N), dtype=torch.complex64, device="cuda")
+        assert p.estimate(y, "bf16").shape == (0, R, T * L)
+        q, sc = p.pack(y, "e4m3")
+        assert q.shape == (0, R, 2, N + 1) and sc.shape == (0,)
+        assert p.estimate_packed(q, sc, "e4m3").shape == (0, R, T * L)
+        X = p.estimate_ls(y, "f32s")
+        assert p.refine(y, X, 2).shape == (0, R, T * L)
+        assert p.adjoint(X).shape == (0, R, N)
+        torch.cuda.synchronize()
+
+
+def test_refine_checks_the_callers_workspace():
+    """A workspace of the wrong shape is refused before any launch (a short
+    one would otherwise be written past its end)."""
+    N, T, L, R = 127, 4, 16, 4
+    y = dev(_rand_frames(N, R, 2, 94))
+    with _plan(N, T, L, R) as p:
+        X = p.estimate(y, "f32s")
+        with pytest.raises(ValueError):
+            p.refine(y, X, 1, work=torch.empty((1, R, N), dtype=torch.complex64, device="cuda"))
+        with pytest.raises(ValueError):
+            p.refine(y, X, 1, work=torch.empty((2, R, N), dtype=torch.complex128, device="cuda"))
+        p.refine(y, X, 1, work=torch.empty((2, R, N), dtype=torch.complex64, device="cuda"))
+        torch.cuda.synchronize()
