@@ -269,8 +269,10 @@ typedef struct pnce_varlen_plan pnce_varlen_plan;   /* opaque */
 
 /*
  * Build a plan for `nframes` frames described by the host array `frames`
- * (copied). format: PNCE_FMT_BF16 or PNCE_FMT_F16. Builds one m-sequence per
- * distinct N, the frame table and a work list: units of (frame, 32-antenna
+ * (copied). format: PNCE_FMT_BF16 or PNCE_FMT_F16. Every frame uses the
+ * built-in m-sequence of its length and adjacent lag blocks (the lags of
+ * pnce_create). Builds one m-sequence per distinct N, the frame table and a
+ * work list: units of (frame, 32-antenna
  * block) carrying all their column tiles, dealt to persistent workgroups
  * longest-first. Column width per (N, T*L) class defaults to 128, 64 or 32
  * lags per wave by T*L; pnce_varlen_tune replaces it with measured choices.
