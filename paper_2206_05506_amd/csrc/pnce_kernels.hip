@@ -59,6 +59,11 @@ template <int IN> struct StageGeom<MODE_BF16, IN> { static constexpr int ch = 12
 template <> struct StageGeom<MODE_BF16, IN_C64> { static constexpr int ch = 64, planes = 2, rs = 36; };
 template <> struct StageGeom<MODE_BF16, IN_C64_LAGS> : StageGeom<MODE_BF16, IN_C64> {};
 
+// e4m3 codes (tg_fp8_kernel): 256 codes per stage (four k-steps of 64), rows
+// padded by 4 dwords like the 16-bit code stages.
+constexpr int kFp8Chunk = 256;
+constexpr int kFp8RowDw = kFp8Chunk / 4 + 4;  // padded plane row in dwords
+
 template <int MODE, int IN = IN_C64> constexpr int stage_dwords() {
   return StageGeom<MODE, IN>::planes * kRows * StageGeom<MODE, IN>::rs;
 }
@@ -396,7 +401,7 @@ size_t max_lds_bytes(int nbw) {
   d = std::max(d, tile_lds_dwords<MODE_F32, IN_C64>(nbw_pad));
   d = std::max(d, tile_lds_dwords<MODE_BF16, IN_C64>(nbw_pad));
   d = std::max(d, nbw_pad + 2 * stage_dwords<MODE_F32>());
-  d = std::max(d, nbw_pad + 2 * 2 * kRows * (128 / 4 + 4));
+  d = std::max(d, nbw_pad + 2 * 2 * kRows * kFp8RowDw);
   return (size_t)d * 4;
 }
 
@@ -1076,8 +1081,8 @@ hipError_t launch_f64mm(const TgArgs &a, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // FP8 (OCP e4m3fn) correlator on quantised planes, v_mfma_f32_32x32x64_f8f6f4.
-// Same tiling as tg_kernel; one 64-sample k-step per LDS chunk (32 rows x
-// 2 planes x 64 codes). Lane (m, h) supplies codes n0 + 32h .. +31 of row m
+// Same tiling as tg_kernel; four 64-code k-steps per LDS stage (32 rows x
+// 2 planes x 256 codes), two stages in flight in registers. Lane (m, h) supplies codes n0 + 32h .. +31 of row m
 // and the matching 32 sequence bits; +-1 in e4m3 is 0x38 / 0xB8. The B
 // fragment of lag block c at k-step i is the 32-bit window at bit
 // p_base + 32(2i - c), so two new windows per k-step serve all blocks.
@@ -1100,8 +1105,6 @@ __device__ __forceinline__ i32x8 expand_e4m3(uint32_t x) {
 // 16-code piece is read by one unconditional buffer load (zeros past the
 // frame) and only the last chunk is masked; otherwise codes are read one by
 // one.
-constexpr int kFp8Chunk = 128;               // codes per stage (two k-steps)
-constexpr int kFp8RowDw = kFp8Chunk / 4 + 4;  // padded plane row in dwords
 
 template <int NC, bool AL>
 __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles_r, int tiles_c,
@@ -1114,7 +1117,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_fp8_kernel(TgArgs a, int tiles
   constexpr int PS = kRows * RS;
   constexpr int SDW = 2 * PS;
   constexpr int NPC = CH / 64;     // 16-code pieces per thread and stage
-  constexpr int PF = 4;            // stages in flight (register sets)
+  constexpr int PF = 2;            // stages in flight (register sets)
   // chunks per unrolled body: covers the register-set rotation (PF) and the
   // window rotation (NW slots, 2 per k-step)
   constexpr int CPB = (NW > 2 * KS * PF) ? NW / (2 * KS) : PF;
