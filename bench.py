@@ -376,7 +376,7 @@ def precision_workload(torch, args):
 def precision_accuracy(torch, cfg, frames=8):
     """Accuracy of the precision study's forms on `frames` frames of the
     channel model (seeded device draws, y = P h + sigma w by the library's
-    adjoint): for the bf16- and e4m3-packed starts and k = 0..5 refinement
+    adjoint): for the bf16-, f16- and e4m3-packed starts and k = 0..5 refinement
     steps, the normwise error against the FP64 iterate with the same k (the
     library's FP64 vector kernel on complex128 copies) and the NMSE against
     h; and the FP32-accurate correlator's NMSE beside bf16's (k = 0)."""
@@ -406,7 +406,7 @@ def precision_accuracy(torch, cfg, frames=8):
 
     out = {"frames": frames, "reference": "FP64 iterate with the same k (library FP64 kernel)"}
     work = torch.empty_like(y)
-    for fmt in ("bf16", "e4m3"):
+    for fmt in ("bf16", "f16", "e4m3"):
         q, sc = plan.pack(y, fmt)
         x0 = plan.estimate_packed(q, sc, fmt)
         rows = []
