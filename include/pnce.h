@@ -33,6 +33,9 @@
  *  - Return value: 0 = PNCE_OK; > 0 = a warning, the call did its work;
  *    < 0 = an error, nothing was enqueued and no output was touched. The
  *    text of the last error on the calling thread is pnce_last_error().
+ *  - A plan (and an uneven-batch plan) belongs to the device that was
+ *    current when it was made: its sequence tables live there. Compute calls
+ *    made while another device is current return PNCE_E_INVALID.
  *  - An empty batch (batch == 0) is valid: once the plan and the other
  *    scalar arguments (precision, format, cp, steps) pass their checks, the
  *    call returns PNCE_OK without reading its tensor pointers, which may be

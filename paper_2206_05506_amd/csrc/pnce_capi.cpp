@@ -113,6 +113,16 @@ pnce_status check_plan(const pnce_plan *p) {
   return PNCE_OK;
 }
 
+// Compute calls run on the device that was current when the plan was made:
+// its sequence tables (and an uneven batch's work list) live there.
+pnce_status check_device(int device) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != device) return fail(PNCE_E_INVALID, "the current device is not the plan's device");
+  return PNCE_OK;
+}
+
 // Called after the early return for an empty batch (batch == 0: nothing to
 // do, the tensor pointers are not read, PNCE_OK).
 pnce_status check_batch(const pnce_plan *p, int batch) {
@@ -358,6 +368,7 @@ pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y, vo
                           int batch, int precision, double alpha, const float *scales,
                           double beta) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
   if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
   if (batch == 0) return PNCE_OK;
   if (!Y || !H) return fail(PNCE_E_INVALID, "Y and H must be non-NULL");
@@ -368,6 +379,7 @@ pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y, vo
 
 pnce_status pnce_debias(const pnce_plan *plan, void *stream, void *H, int batch) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
   if (plan->K > plan->N)
     return fail(PNCE_E_UNSUPPORTED, "T*L > N: least squares is not unique");
   if (batch == 0) return PNCE_OK;
@@ -382,6 +394,7 @@ pnce_status pnce_debias(const pnce_plan *plan, void *stream, void *H, int batch)
 pnce_status pnce_estimate_ls(const pnce_plan *plan, void *stream, const void *Y, void *H,
                              int batch, int precision, const float *scales) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
   if (precision != PNCE_PREC_F32 && precision != PNCE_PREC_F32S && precision != PNCE_PREC_BF16)
     return fail(PNCE_E_INVALID, "estimate_ls precision must be F32, F32S or BF16");
   if (plan->K > plan->N)
@@ -396,6 +409,7 @@ pnce_status pnce_estimate_ls(const pnce_plan *plan, void *stream, const void *Y,
 pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y, void *Yq,
                       float *scales, int batch, int format) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
   if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
   if (batch == 0) return PNCE_OK;
   if (!Y || !Yq || !scales) return fail(PNCE_E_INVALID, "Y, Yq and scales must be non-NULL");
@@ -418,6 +432,7 @@ static pnce_status check_cp(const pnce_plan *plan, int cp) {
 pnce_status pnce_estimate_cp(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
                              void *H, int batch, int precision, const float *scales) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
   if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
   if (pnce_status st = check_cp(plan, cp)) return st;
   if (batch == 0) return PNCE_OK;
@@ -432,6 +447,7 @@ pnce_status pnce_estimate_cp(const pnce_plan *plan, void *stream, const void *Y_
 pnce_status pnce_pack_cp(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
                          void *Yq, float *scales, int batch, int format) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
   if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
   if (pnce_status st = check_cp(plan, cp)) return st;
   if (batch == 0) return PNCE_OK;
@@ -448,6 +464,7 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream, const void
                                  const float *scales, void *H, int batch, int format,
                                  double beta) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
   if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
   if (batch == 0) return PNCE_OK;
   if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
@@ -464,6 +481,7 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream, const void
 pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G, void *A,
                          const void *C, int batch, int precision, double alpha, double beta) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
   if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
   if (batch == 0) return PNCE_OK;
   if (!G || !A) return fail(PNCE_E_INVALID, "G and A must be non-NULL");
@@ -476,6 +494,7 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G, voi
 pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void *X,
                         void *work, int batch, int steps) {
   if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
   if (steps < 0) return fail(PNCE_E_INVALID, "steps must be >= 0");
   if (batch == 0) return PNCE_OK;
   if (!y || !X || (!work && steps > 0)) return fail(PNCE_E_INVALID, "y, X and work must be non-NULL");
@@ -501,6 +520,7 @@ pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void
 struct pnce_varlen_plan {
   int in_fmt;
   int n_cu;
+  int device;  // current when the plan was made; its tables live there
   std::vector<pnce_frame_desc> desc;
   std::vector<pnce::VFrame> frames;
   // per (N, K) class: chosen lags-per-wave / 32 and cost per unit (us)
@@ -674,6 +694,7 @@ pnce_status pnce_varlen_create(pnce_varlen_plan **vplan, const pnce_frame_desc *
     v->desc.assign(frames, frames + nframes);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
+    v->device = dev;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&v->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) {
       delete v;
@@ -752,6 +773,7 @@ pnce_status pnce_varlen_destroy(pnce_varlen_plan *vplan) {
 pnce_status pnce_varlen_estimate(const pnce_varlen_plan *vplan, void *stream, const void *Yq,
                                  const float *scales, void *H) {
   if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
+  if (pnce_status st = check_device(vplan->device)) return st;
   if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
   const pnce::VArgs a = varlen_args(vplan, Yq, scales, H, vplan->d_tiles, vplan->d_wg_start);
   hipError_t e = pnce::launch_varlen(vplan->in_fmt, a, (int)vplan->wg_start.size() - 1,
@@ -763,6 +785,7 @@ pnce_status pnce_varlen_estimate(const pnce_varlen_plan *vplan, void *stream, co
 pnce_status pnce_varlen_estimate_each(const pnce_varlen_plan *vplan, void *stream,
                                       const void *Yq, const float *scales, void *H) {
   if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
+  if (pnce_status st = check_device(vplan->device)) return st;
   if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
   for (size_t f = 0; f < vplan->frames.size(); ++f) {
     const pnce::VFrame &fr = vplan->frames[f];
@@ -792,6 +815,7 @@ pnce_status pnce_varlen_estimate_each(const pnce_varlen_plan *vplan, void *strea
 pnce_status pnce_varlen_tune(pnce_varlen_plan *vplan, void *stream, const void *Yq,
                              const float *scales, void *H, int reps) {
   if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
+  if (pnce_status st = check_device(vplan->device)) return st;
   if (!Yq || !H || reps <= 0) return fail(PNCE_E_INVALID, "Yq, H and reps > 0 required");
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
