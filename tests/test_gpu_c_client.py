@@ -1,6 +1,7 @@
 """The C ABI from a plain C program (tests/c_client): plan, device buffers
-and one correlator call with no Python in the process; its output checked
-against the FP64 oracle, and its error statuses."""
+and one operation (correlator, adjoint, quantise + packed correlator, or
+refinement) with no Python in the process; its output checked against the
+FP64 oracle, and its error statuses."""
 import os
 import subprocess
 
@@ -17,13 +18,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CLIENT = os.path.join(HERE, "c_client", "pnce_c_client")
 
 
-def _run(args, tmp_path, y):
+def _run(args, tmp_path, y, op=None):
     if not os.path.exists(CLIENT):
         pytest.fail("tests/c_client/pnce_c_client is not built (python tests/c_client/build.py)")
     fin, fout = str(tmp_path / "y.bin"), str(tmp_path / "h.bin")
     np.ascontiguousarray(y, dtype=np.complex64).tofile(fin)
-    p = subprocess.run([CLIENT] + [str(a) for a in args] + [fin, fout], capture_output=True,
-                       text=True, timeout=60)
+    p = subprocess.run([CLIENT] + [str(a) for a in args] + [fin, fout] + ([op] if op else []),
+                       capture_output=True, text=True, timeout=60)
     return p, fout
 
 
@@ -48,3 +49,38 @@ def test_c_client_error_statuses(tmp_path):
     y = np.zeros((1, 4, 127), dtype=np.complex64)
     p, _ = _run([127, 2, 8, 4, 1, 9, 0, 0], tmp_path, y)      # unknown precision
     assert p.returncode == 10 - (-1) and "precision" in p.stderr
+
+
+# ragged antenna blocks (40 = 32 + 8), two frames
+SMALL = (255, 4, 16, 40, 2)
+
+
+def test_c_client_adjoint(tmp_path):
+    N, T, L, R, B = SMALL
+    G = synth.gaussian((B, R, T * L), 42).astype(np.complex64)
+    p, fout = _run([N, T, L, R, B, 1, 0, 0], tmp_path, G, "adjoint")
+    assert p.returncode == 0, p.stderr
+    A = np.fromfile(fout, dtype=np.complex64).reshape(B, R, N)
+    assert oracle.relerr(A, oracle.adjoint(G, oracle.mseq(8))) <= 1e-5
+
+
+@pytest.mark.parametrize("fmt,name", [(1, "bf16"), (2, "f16"), (3, "e4m3")])
+def test_c_client_pack_and_packed_estimate(tmp_path, fmt, name):
+    N, T, L, R, B = SMALL
+    y = (synth.gaussian((B, R, N), 43) * 3.0).astype(np.complex64)
+    p, fout = _run([N, T, L, R, B, 1, 0, 0], tmp_path, y, f"packed:{fmt}")
+    assert p.returncode == 0, p.stderr
+    H = np.fromfile(fout, dtype=np.complex64).reshape(B, R, T * L)
+    codes, scales = oracle.quantize(y, name)
+    x = oracle.dequantize(codes, scales, name, N)
+    assert oracle.relerr(H, oracle.correlate(x, oracle.mseq(8), T * L)) <= 1e-5
+
+
+def test_c_client_refine(tmp_path):
+    N, T, L, R, B = SMALL
+    y = synth.gaussian((B, R, N), 44).astype(np.complex64)
+    p, fout = _run([N, T, L, R, B, 1, 0, 0], tmp_path, y, "refine:3")
+    assert p.returncode == 0, p.stderr
+    X = np.fromfile(fout, dtype=np.complex64).reshape(B, R, T * L)
+    its = oracle.refine(y.astype(np.complex128), oracle.mseq(8), T * L, 3)
+    assert oracle.relerr(X, its[3]) <= 1e-5
