@@ -318,8 +318,8 @@ def test_most_antennas():
 
 
 def test_graph_replays_match_eager():
-    """Correlator, LS rows, quantiser + packed e4m3 estimate and adjoint
-    captured in one HIP graph. Every replay, with eager work and
+    """Correlator, LS rows, quantiser + packed e4m3 estimate, adjoint,
+    refinement and the separate de-bias captured in one HIP graph. Every replay, with eager work and
     synchronisations between replays, equals the eager results bit for bit
     (the quantiser clears its counters with a kernel, not a memset)."""
     N, T, L, R, B = 1023, 16, 32, 64, 4
@@ -330,9 +330,13 @@ def test_graph_replays_match_eager():
         q_e, sc_e = p.pack(y, "e4m3")
         Hq_e = p.estimate_packed(q_e, sc_e, "e4m3")
         A_e = p.adjoint(H_e, "f32s")
+        W = torch.empty_like(y)
+        Xr_e = p.refine(y, p.estimate(y, "f32s"), 3, work=W)
+        D_e = p.debias(p.estimate(y, "bf16"))
         torch.cuda.synchronize()
         H, X, Hq = torch.empty_like(H_e), torch.empty_like(X_e), torch.empty_like(Hq_e)
         q, sc, A = torch.empty_like(q_e), torch.empty_like(sc_e), torch.empty_like(A_e)
+        Xr, D = torch.empty_like(Xr_e), torch.empty_like(D_e)
 
         def work():
             p.estimate(y, "bf16", out=H)
@@ -340,6 +344,10 @@ def test_graph_replays_match_eager():
             p.pack(y, "e4m3", out=q, scales=sc)
             p.estimate_packed(q, sc, "e4m3", out=Hq)
             p.adjoint(H, "f32s", out=A)
+            p.estimate(y, "f32s", out=Xr)
+            p.refine(y, Xr, 3, work=W)
+            p.estimate(y, "bf16", out=D)
+            p.debias(D)
 
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -351,7 +359,7 @@ def test_graph_replays_match_eager():
         with torch.cuda.graph(g):
             work()
         for _ in range(3):
-            for t in (H, X, Hq, A, sc):
+            for t in (H, X, Hq, A, sc, Xr, D, W):
                 t.zero_()
             q.fill_(0x7F)
             torch.cuda.synchronize()
@@ -359,6 +367,7 @@ def test_graph_replays_match_eager():
             torch.cuda.synchronize()
             assert torch.equal(H, H_e) and torch.equal(X, X_e) and torch.equal(A, A_e)
             assert torch.equal(q, q_e) and torch.equal(sc, sc_e) and torch.equal(Hq, Hq_e)
+            assert torch.equal(Xr, Xr_e) and torch.equal(D, D_e)
         del g
 
 
