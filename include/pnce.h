@@ -40,10 +40,17 @@
  *    scalar arguments (precision, format, cp, steps) pass their checks, the
  *    call returns PNCE_OK without reading its tensor pointers, which may be
  *    NULL, and enqueues nothing.
+ *  - Compute calls allocate nothing, set no memory with a memset and do not
+ *    synchronise: each enqueues kernels only, so a sequence of them can be
+ *    captured into a hipGraph and replayed. pnce_varlen_tune and
+ *    pnce_varlen_set_tuning are not compute calls: they rebuild and upload
+ *    an uneven-batch plan's work list, allocating and synchronising.
  *  - No C++ exception and no abort crosses this boundary.
  *  - A plan is immutable after pnce_create; calls on one plan from several
  *    host threads or streams are safe, except that pnce_refine uses the
- *    workspace its caller passes.
+ *    workspace its caller passes. An uneven-batch plan changes only in
+ *    pnce_varlen_tune and pnce_varlen_set_tuning, which must not overlap any
+ *    other use of that plan, including its launches still in flight.
  */
 #ifndef PNCE_H
 #define PNCE_H
@@ -317,7 +324,8 @@ pnce_status pnce_varlen_estimate_each(const pnce_varlen_plan *vplan, void *strea
  * measured costs; the fastest widths with the default cost model), times
  * each on the whole batch and keeps the fastest, so tuning does not lose to
  * the plan's previous schedule beyond timing noise. Synchronous. Writes H
- * (the repeated units write the same values).
+ * (the repeated units write the same values). Replaces the plan's work
+ * list: no launch of this plan may be in flight.
  */
 pnce_status pnce_varlen_tune(pnce_varlen_plan *vplan, void *stream, const void *Yq,
                              const float *scales, void *H, int reps);
@@ -325,7 +333,8 @@ pnce_status pnce_varlen_tune(pnce_varlen_plan *vplan, void *stream, const void *
 /*
  * Read (n_classes only when the arrays are NULL) or install the per-class
  * choice: sequence length N, T*L, lags per wave / 32 (1, 2 or 4) and cost in
- * microseconds per unit. set_tuning rebuilds the work list; classes not
+ * microseconds per unit. set_tuning rebuilds and uploads the work list
+ * (synchronous; no launch of this plan may be in flight); classes not
  * listed keep their choice. Lets a caller cache tuning results.
  */
 pnce_status pnce_varlen_get_tuning(const pnce_varlen_plan *vplan, int *n_classes, int *N,
