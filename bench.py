@@ -46,8 +46,8 @@ ROTATE_COPIES = 5              # frame / CIR buffer copies the timed steps rotat
 # HBM bytes per launch of the bf16 estimate measured with rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
 # for the kernel source with this sha256; any other source reports null.
-TRAFFIC = {"source_sha256": "701ae05e0bc9cd42199820f41f54de88195ee012b1f71dcb1750a86778f60f99",
-           "bytes_per_launch": 203467594}
+TRAFFIC = {"source_sha256": "b1ad3a2021285219d2b53587d0331c931f2ea30719b1c0cc8388b23cf1fd05a1",
+           "bytes_per_launch": 203467296}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 / f16 matrix
 FP8_PEAK_TFLOPS = 5033.2       # dense fp8 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix

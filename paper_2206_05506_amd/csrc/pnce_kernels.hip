@@ -77,6 +77,12 @@ __device__ __forceinline__ float bf16_value(uint32_t b) {
 __device__ __forceinline__ uint32_t pack2(uint32_t lo, uint32_t hi) {
   return lo | (hi << 16);
 }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// Two FP32 values rounded to bf16 (nearest even) in one packed conversion:
+// lo in bits 0-15, hi in bits 16-31.
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+}
 
 // Exact three-way bf16 split of an FP32 value: x = hi + mid + lo up to
 // 2^-24 relative (each part rounds the remainder to nearest even; the
@@ -268,8 +274,8 @@ __device__ __forceinline__ void store_pair(uint32_t *st, int row, int pr, f32x4 
     *(f2a8 *)(st + row * RS + 2 * pr) = f2a8{x.x, x.z};
     *(f2a8 *)(st + PS + row * RS + 2 * pr) = f2a8{x.y, x.w};
   } else if constexpr (MODE == MODE_BF16) {
-    st[row * RS + pr] = pack2(bf16_bits(x.x), bf16_bits(x.z));
-    st[PS + row * RS + pr] = pack2(bf16_bits(x.y), bf16_bits(x.w));
+    st[row * RS + pr] = bf16_pair(x.x, x.z);
+    st[PS + row * RS + pr] = bf16_pair(x.y, x.w);
   } else {  // MODE_F32S
     uint32_t h0, m0, l0, h1, m1, l1;
     split3(x.x, h0, m0, l0);
