@@ -304,7 +304,8 @@ _TARGET = {"bf16": 1.0, "f16": 1.0, "e4m3": 448.0}
 
 
 def frame_scale(y, fmt: str) -> np.ndarray:
-    """Per-frame power-of-two scale: the smallest 2^e with maxabs <= target*2^e.
+    """Per-frame power-of-two scale: the smallest 2^e with maxabs <= target*2^e,
+    and at least 2^-126.
 
     maxabs is the largest |re| or |im| over the frame's R*N samples; target is
     1 for bf16/f16 and 448 (the largest finite e4m3) for e4m3. A frame of
@@ -326,6 +327,10 @@ def frame_scale(y, fmt: str) -> np.ndarray:
             e += 1
         while m <= tgt * 2.0 ** (e - 1):
             e -= 1
+        # never below the smallest normal float32, 2^-126: a frame of
+        # subnormal samples would otherwise get a scale whose reciprocal
+        # overflows (the paper does not treat such frames)
+        e = max(e, -126)
         out[b] = np.float32(2.0 ** e)
     return out
 

@@ -313,6 +313,22 @@ def test_scale_is_smallest_power_of_two(fmt):
 
 
 @pytest.mark.parametrize("fmt,tol", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11), ("e4m3", 2.0 ** -4)])
+def test_subnormal_frames_get_the_smallest_normal_scale(fmt, tol):
+    """A frame whose samples are all subnormal float32 values gets scale
+    2^-126 (not a subnormal power of two, whose reciprocal would overflow),
+    and its codes decode back to the samples within the format's rounding."""
+    y = (rand_c((1, 2, 15), 53) * 1e-39).astype(np.complex64)
+    assert np.abs(y.real).max() < 2.0 ** -126
+    sc = oracle.frame_scale(y, fmt)
+    assert sc[0] == np.float32(2.0 ** -126)
+    q, sc2 = oracle.quantize(y, fmt)
+    x = oracle.dequantize(q, sc2, fmt, 15)
+    assert np.all(np.isfinite(x))
+    err = np.abs(x - y.astype(np.complex128)).max()
+    assert err <= tol * np.abs(y).max() * 2 + 2.0 ** -149
+
+
+@pytest.mark.parametrize("fmt,tol", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11), ("e4m3", 2.0 ** -4)])
 def test_dequantize_error_bound(fmt, tol):
     y = rand_c((2, 5, 63), 61).astype(np.complex64)
     codes, sc = oracle.quantize(y, fmt)
