@@ -1584,7 +1584,9 @@ __device__ float pow2_scale(float m, float target) {
   (void)frexpf(m / target, &e);
   while ((double)m > (double)target * ldexp(1.0, e)) ++e;
   while ((double)m <= (double)target * ldexp(1.0, e - 1)) --e;
-  return ldexpf(1.0f, e);
+  // at least the smallest normal float, so that the reciprocal is finite
+  // for frames of subnormal samples
+  return ldexpf(1.0f, e < -126 ? -126 : e);
 }
 
 // The frame maximum travels as the bit pattern of |v|: for non-negative
@@ -1688,22 +1690,17 @@ __device__ __forceinline__ uint32_t e4m3_code(float x) {
 // Four consecutive samples of one padded output row per thread. The padded
 // row length N + 1 is a power of two, so each thread's codes form one aligned
 // 8-byte (16-bit codes) or 4-byte (e4m3) store per plane.
+// Four samples n0 .. n0+3 of one row (those at or past N read as zero) to
+// codes n0 .. n0+3 of the row's two planes (real at q_row, imaginary at
+// q_row + Np), each value times inv, rounded to nearest even (e4m3:
+// saturating).
 template <int FMT>
-__global__ __launch_bounds__(256) void pack_kernel(const f2a8 *y, void *yq, const uint32_t *maxbits,
-                                                   int R, int N, int ld, float target,
-                                                   long total) {
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;  // (row, quad)
-  if (i >= total) return;
-  const int Np = N + 1, nq = Np >> 2;
-  const long row = i / nq;  // frame * R + antenna
-  const int n0 = (int)(i - row * nq) * 4;
-  const int b = (int)(row / R);
-  const float inv = 1.0f / scale_from_maxbits(maxbits[b], target);
+__device__ __forceinline__ void pack_quad(const f2a8 *y_row, void *yq, size_t q_row, int n0,
+                                          int N, int Np, float inv) {
   f2a8 v[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-    v[u] = n0 + u < N ? y[row * ld + n0 + u] : f2a8{0.0f, 0.0f};
-  const size_t o = (size_t)row * 2 * Np + n0;
+  for (int u = 0; u < 4; ++u) v[u] = n0 + u < N ? y_row[n0 + u] : f2a8{0.0f, 0.0f};
+  const size_t o = q_row + n0;
   if constexpr (FMT == 3) {
     uint32_t cr = 0u, ci = 0u;
 #pragma unroll
@@ -1739,12 +1736,95 @@ __global__ __launch_bounds__(256) void pack_kernel(const f2a8 *y, void *yq, cons
   }
 }
 
+template <int FMT>
+__global__ __launch_bounds__(256) void pack_kernel(const f2a8 *y, void *yq, const uint32_t *maxbits,
+                                                   int R, int N, int ld, float target,
+                                                   long total) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;  // (row, quad)
+  if (i >= total) return;
+  const int Np = N + 1, nq = Np >> 2;
+  const long row = i / nq;  // frame * R + antenna
+  const int n0 = (int)(i - row * nq) * 4;
+  const int b = (int)(row / R);
+  const float inv = 1.0f / scale_from_maxbits(maxbits[b], target);
+  pack_quad<FMT>(y + row * ld, yq, (size_t)row * 2 * Np, n0, N, Np, inv);
+}
+
+// The whole quantiser in one launch when the batch has at least one frame
+// per CU: workgroup b reduces frame b's max-abs word in LDS, then converts
+// the frame (its second read mostly served by the caches) and writes the
+// frame's scale. No atomics and no counters to clear; the codes equal those
+// of the four-launch path (same maximum, same conversions).
+constexpr int kPackFrameThreads = 1024;
+template <int FMT>
+__global__ __launch_bounds__(kPackFrameThreads) void pack_frame_kernel(
+    const f2a8 *y, void *yq, float *scales, int R, int N, int ld, float target) {
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const f2a8 *f = y + (size_t)b * R * ld;
+  uint32_t m = 0u;
+  auto fold = [&](f2a8 v) {
+    const float re = v.x, im = v.y;
+    m = max(m, __builtin_bit_cast(uint32_t, re) & 0x7FFFFFFFu);
+    m = max(m, __builtin_bit_cast(uint32_t, im) & 0x7FFFFFFFu);
+  };
+  constexpr int U = 4;
+  if (ld == N) {  // one contiguous run of R*N samples
+    const long per = (long)R * N;
+    for (long i0 = tid; i0 < per; i0 += (long)kPackFrameThreads * U) {
+      f2a8 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long i = i0 + (long)u * kPackFrameThreads;
+        v[u] = i < per ? f[i] : f2a8{0.0f, 0.0f};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) fold(v[u]);
+    }
+  } else {  // rows of N samples at a stride of ld
+    for (int r = 0; r < R; ++r)
+      for (int n = tid; n < N; n += kPackFrameThreads) fold(f[(size_t)r * ld + n]);
+  }
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
+  __shared__ uint32_t wmax[kPackFrameThreads / 64];
+  if ((tid & 63) == 0) wmax[tid >> 6] = m;
+  __syncthreads();
+  m = 0u;
+#pragma unroll
+  for (int w = 0; w < kPackFrameThreads / 64; ++w) m = max(m, wmax[w]);
+  const float scale = scale_from_maxbits(m, target);
+  const float inv = 1.0f / scale;
+  const int Np = N + 1, nq = Np >> 2;
+  const long total = (long)R * nq;
+  for (long i = tid; i < total; i += kPackFrameThreads) {
+    const int r = (int)(i / nq);
+    const int n0 = (int)(i - (long)r * nq) * 4;
+    const long row = (long)b * R + r;
+    pack_quad<FMT>(f + (size_t)r * ld, yq, (size_t)row * 2 * Np, n0, N, Np, inv);
+  }
+  if (tid == 0) scales[b] = scale;
+}
+
 // scales doubles as the per-frame max word until the last launch turns it
 // into the scale, so the four launches must stay in this order on one stream.
 hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R, int N,
                        int ld, int fmt, hipStream_t s) {
   if (fmt < 1 || fmt > 3) return hipErrorInvalidValue;
   const float target = (fmt == 3) ? 448.0f : 1.0f;
+  if (batch >= kPackFrameBatch) {
+    const dim3 grid((unsigned)batch), block(kPackFrameThreads);
+    const f2a8 *yc = (const f2a8 *)y;
+    if (fmt == 1)
+      hipLaunchKernelGGL((pack_frame_kernel<1>), grid, block, 0, s, yc, yq, scales, R, N, ld,
+                         target);
+    else if (fmt == 2)
+      hipLaunchKernelGGL((pack_frame_kernel<2>), grid, block, 0, s, yc, yq, scales, R, N, ld,
+                         target);
+    else
+      hipLaunchKernelGGL((pack_frame_kernel<3>), grid, block, 0, s, yc, yq, scales, R, N, ld,
+                         target);
+    return hipGetLastError();
+  }
   uint32_t *mb = (uint32_t *)scales;
   const f2a8 *yc = (const f2a8 *)y;
   hipLaunchKernelGGL(zero_u32_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, mb, batch);

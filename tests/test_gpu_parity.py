@@ -508,3 +508,36 @@ def test_refine_checks_the_callers_workspace():
             p.refine(y, X, 1, work=torch.empty((2, R, N), dtype=torch.complex128, device="cuda"))
         p.refine(y, X, 1, work=torch.empty((2, R, N), dtype=torch.complex64, device="cuda"))
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "e4m3"])
+@pytest.mark.parametrize("N,R,cp", [(127, 5, 0), (1023, 33, 0), (63, 3, 7), (3, 1, 0)])
+def test_pack_one_launch_path_bit_exact(fmt, N, R, cp):
+    """Batches of 256 frames or more are quantised by one launch with a
+    workgroup per frame. Its codes and scales equal the oracle's bit for
+    bit, including degenerate frames (all zero, +-inf, NaN, a maximum on a
+    power of two, subnormal-size values) and raw rows with a cyclic prefix,
+    and equal the four-launch path's on the first 255 frames."""
+    from paper_2206_05506_amd.api import _CODE_DTYPE
+    B = 256
+    rng = np.random.default_rng(N + R + cp)
+    y = (rng.standard_normal((B, R, N)) + 1j * rng.standard_normal((B, R, N))).astype(np.complex64)
+    y *= (10.0 ** rng.uniform(-6, 6, size=(B, 1, 1))).astype(np.float32)
+    y[0] = 0.0
+    y[1, 0, N - 1] = np.inf
+    y[2, R - 1, 0] = np.nan + 1j
+    y[3] *= np.float32(0.49) / max(np.abs(y[3].real).max(), np.abs(y[3].imag).max())
+    y[3, 0, 0] = 0.5
+    y[4] = np.float32(1e-39)
+    raw = np.concatenate([y[:, :, N - cp:], y], axis=2) if cp else y
+    with _plan(N, 1, 1, R) as p:
+        yd = dev(raw)
+        q, sc = (p.pack_cp(yd, cp, fmt) if cp else p.pack(yd, fmt))
+        part = yd[:B - 1].contiguous()
+        q4, sc4 = (p.pack_cp(part, cp, fmt) if cp else p.pack(part, fmt))
+        q, sc, q4, sc4 = host(q), host(sc), host(q4), host(sc4)
+    ref_q, ref_sc = oracle.quantize(y, fmt)
+    assert q.dtype == np.dtype(str(_CODE_DTYPE[fmt]).replace("torch.", ""))
+    assert np.array_equal(sc, ref_sc)
+    assert np.array_equal(q.view(ref_q.dtype), ref_q)
+    assert np.array_equal(sc4, sc[:B - 1]) and np.array_equal(q4, q[:B - 1])
