@@ -113,10 +113,13 @@ hipError_t launch_tg_frame(int in_fmt, int nc, const TgArgs &a, hipStream_t s);
 
 // Quantiser: per-frame scale, then conversion into planar codes.
 // Rows of N samples ld complex apart (ld = N: contiguous frames). Batches of
-// at least kPackFrameBatch frames (a frame per CU or more) take one launch
-// with a workgroup per frame; smaller ones spread each frame over many
-// workgroups in four launches. Both give the same codes and scales.
+// at least kPackFrameBatch frames (a frame per CU or more) of at most
+// kPackFrameMaxBytes each take one launch with a workgroup per frame (the
+// frames in flight then fit the Infinity Cache, which serves the second
+// read); other batches spread each frame over many workgroups in four
+// launches. Both give the same codes and scales.
 constexpr int kPackFrameBatch = 256;
+constexpr long long kPackFrameMaxBytes = 1LL << 20;
 hipError_t launch_pack(const float *y, void *yq, float *scales, int batch,
                        int R, int N, int ld, int fmt, hipStream_t s);
 

@@ -1811,7 +1811,7 @@ hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R
                        int ld, int fmt, hipStream_t s) {
   if (fmt < 1 || fmt > 3) return hipErrorInvalidValue;
   const float target = (fmt == 3) ? 448.0f : 1.0f;
-  if (batch >= kPackFrameBatch) {
+  if (batch >= kPackFrameBatch && (long long)R * ld * 8 <= kPackFrameMaxBytes) {
     const dim3 grid((unsigned)batch), block(kPackFrameThreads);
     const f2a8 *yc = (const f2a8 *)y;
     if (fmt == 1)
