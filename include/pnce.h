@@ -26,7 +26,10 @@
  * Conventions for every entry point
  *  - Tensor pointers are DEVICE memory owned by the caller, dense row-major,
  *    with the shapes stated per call. Complex numbers are interleaved
- *    (re, im) float pairs ("c64") or double pairs ("c128").
+ *    (re, im) float pairs ("c64") or double pairs ("c128"). Each pointer is
+ *    aligned to its element: 8 bytes for c64, 16 for c128, 8 for buffers of
+ *    16-bit codes, 4 for e4m3 codes and for scales; a misaligned pointer is
+ *    refused with PNCE_E_INVALID.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Compute calls only enqueue work and return; results are ready when the
  *    stream is. Faults of enqueued kernels surface at the caller's next sync.

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -112,6 +113,18 @@ pnce_status check_plan(const pnce_plan *p) {
   if (!p) return fail(PNCE_E_INVALID, "plan is NULL");
   return PNCE_OK;
 }
+
+// Tensor pointers must be aligned to their element: complex64 8 bytes,
+// complex128 16, 16-bit codes 8 (four codes per store), e4m3 codes and
+// scales 4. NULL passes (each call checks the pointers it requires).
+pnce_status check_align(const void *p, size_t a, const char *what) {
+  if (p && (reinterpret_cast<uintptr_t>(p) % a) != 0)
+    return fail(PNCE_E_INVALID,
+                std::string(what) + " is not aligned to " + std::to_string(a) + " bytes");
+  return PNCE_OK;
+}
+size_t c_bytes(int precision) { return precision == PNCE_PREC_F64 ? 16 : 8; }
+size_t code_align(int format) { return format == PNCE_FMT_E4M3 ? 4 : 8; }
 
 // Compute calls run on the device that was current when the plan was made:
 // its sequence tables (and an uneven batch's work list) live there.
@@ -373,6 +386,9 @@ pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y, vo
   if (batch == 0) return PNCE_OK;
   if (!Y || !H) return fail(PNCE_E_INVALID, "Y and H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(Y, c_bytes(precision), "Y")) return st;
+  if (pnce_status st = check_align(H, c_bytes(precision), "H")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
   return run_fwd(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
                  beta != 0.0 ? H : nullptr, scales, batch, alpha, beta);
 }
@@ -385,6 +401,7 @@ pnce_status pnce_debias(const pnce_plan *plan, void *stream, void *H, int batch)
   if (batch == 0) return PNCE_OK;
   if (!H) return fail(PNCE_E_INVALID, "H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(H, 8, "H")) return st;
   hipError_t e = pnce::launch_debias((float *)H, (long)batch * plan->R, plan->K, plan->N,
                                      (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "debias launch");
@@ -402,6 +419,9 @@ pnce_status pnce_estimate_ls(const pnce_plan *plan, void *stream, const void *Y,
   if (batch == 0) return PNCE_OK;
   if (!Y || !H) return fail(PNCE_E_INVALID, "Y and H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(Y, 8, "Y")) return st;
+  if (pnce_status st = check_align(H, 8, "H")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
   return run_fwd(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N, H,
                  nullptr, scales, batch, 1.0 / plan->N, 0.0, true);
 }
@@ -414,6 +434,9 @@ pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y, void *
   if (batch == 0) return PNCE_OK;
   if (!Y || !Yq || !scales) return fail(PNCE_E_INVALID, "Y, Yq and scales must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(Y, 8, "Y")) return st;
+  if (pnce_status st = check_align(Yq, code_align(format), "Yq")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
   hipError_t e = pnce::launch_pack((const float *)Y, Yq, scales, batch, plan->R, plan->N,
                                    plan->N, format, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pack launch");
@@ -438,6 +461,9 @@ pnce_status pnce_estimate_cp(const pnce_plan *plan, void *stream, const void *Y_
   if (batch == 0) return PNCE_OK;
   if (!Y_raw || !H) return fail(PNCE_E_INVALID, "Y_raw and H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(Y_raw, c_bytes(precision), "Y_raw")) return st;
+  if (pnce_status st = check_align(H, c_bytes(precision), "H")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
   const size_t esz = precision == PNCE_PREC_F64 ? 16 : 8;
   const void *Y = (const char *)Y_raw + (size_t)cp * esz;
   return run_fwd(plan, (hipStream_t)stream, precision, pnce::IN_C64, Y, plan->N, plan->N + cp,
@@ -453,6 +479,9 @@ pnce_status pnce_pack_cp(const pnce_plan *plan, void *stream, const void *Y_raw,
   if (batch == 0) return PNCE_OK;
   if (!Y_raw || !Yq || !scales) return fail(PNCE_E_INVALID, "Y_raw, Yq and scales must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(Y_raw, 8, "Y_raw")) return st;
+  if (pnce_status st = check_align(Yq, code_align(format), "Yq")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
   const float *Y = (const float *)Y_raw + (size_t)cp * 2;
   hipError_t e = pnce::launch_pack(Y, Yq, scales, batch, plan->R, plan->N, plan->N + cp, format,
                                    (hipStream_t)stream);
@@ -469,6 +498,9 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream, const void
   if (batch == 0) return PNCE_OK;
   if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(Yq, code_align(format), "Yq")) return st;
+  if (pnce_status st = check_align(H, 8, "H")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
   const int in_fmt = format == PNCE_FMT_BF16  ? pnce::IN_BF16
                      : format == PNCE_FMT_F16 ? pnce::IN_F16
                                               : pnce::IN_E4M3;
@@ -487,6 +519,9 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G, voi
   if (!G || !A) return fail(PNCE_E_INVALID, "G and A must be non-NULL");
   if (beta != 0.0 && !C) return fail(PNCE_E_INVALID, "C must be non-NULL when beta != 0");
   if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(G, c_bytes(precision), "G")) return st;
+  if (pnce_status st = check_align(A, c_bytes(precision), "A")) return st;
+  if (pnce_status st = check_align(C, c_bytes(precision), "C")) return st;
   return run_adj(plan, (hipStream_t)stream, precision, G, A, beta != 0.0 ? C : nullptr, batch,
                  alpha, beta);
 }
@@ -499,6 +534,9 @@ pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void
   if (batch == 0) return PNCE_OK;
   if (!y || !X || (!work && steps > 0)) return fail(PNCE_E_INVALID, "y, X and work must be non-NULL");
   if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(y, 8, "y")) return st;
+  if (pnce_status st = check_align(X, 8, "X")) return st;
+  if (pnce_status st = check_align(work, 8, "work")) return st;
   hipStream_t s = (hipStream_t)stream;
   for (int j = 0; j < steps; ++j) {
     // r = y - P x   (P x = sum_k x[k] s[(n-k) mod N]: adjoint stream, alpha -1)
@@ -775,6 +813,9 @@ pnce_status pnce_varlen_estimate(const pnce_varlen_plan *vplan, void *stream, co
   if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
   if (pnce_status st = check_device(vplan->device)) return st;
   if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
+  if (pnce_status st = check_align(Yq, 8, "Yq")) return st;
+  if (pnce_status st = check_align(H, 8, "H")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
   const pnce::VArgs a = varlen_args(vplan, Yq, scales, H, vplan->d_tiles, vplan->d_wg_start);
   hipError_t e = pnce::launch_varlen(vplan->in_fmt, a, (int)vplan->wg_start.size() - 1,
                                      (hipStream_t)stream);
@@ -787,6 +828,9 @@ pnce_status pnce_varlen_estimate_each(const pnce_varlen_plan *vplan, void *strea
   if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
   if (pnce_status st = check_device(vplan->device)) return st;
   if (!Yq || !H) return fail(PNCE_E_INVALID, "Yq and H must be non-NULL");
+  if (pnce_status st = check_align(Yq, 8, "Yq")) return st;
+  if (pnce_status st = check_align(H, 8, "H")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
   for (size_t f = 0; f < vplan->frames.size(); ++f) {
     const pnce::VFrame &fr = vplan->frames[f];
     pnce::TgArgs a{};
@@ -817,6 +861,9 @@ pnce_status pnce_varlen_tune(pnce_varlen_plan *vplan, void *stream, const void *
   if (!vplan) return fail(PNCE_E_INVALID, "vplan is NULL");
   if (pnce_status st = check_device(vplan->device)) return st;
   if (!Yq || !H || reps <= 0) return fail(PNCE_E_INVALID, "Yq, H and reps > 0 required");
+  if (pnce_status st = check_align(Yq, 8, "Yq")) return st;
+  if (pnce_status st = check_align(H, 8, "H")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   pnce::VTile *d_t = nullptr;

@@ -541,3 +541,42 @@ def test_pack_one_launch_path_bit_exact(fmt, N, R, cp):
     assert np.array_equal(sc, ref_sc)
     assert np.array_equal(q.view(ref_q.dtype), ref_q)
     assert np.array_equal(sc4, sc[:B - 1]) and np.array_equal(q4, q[:B - 1])
+
+
+def test_misaligned_pointers_are_refused():
+    """Every tensor pointer must be aligned to its element; a misaligned one
+    returns PNCE_E_INVALID and nothing is written."""
+    from paper_2206_05506_amd import _lib
+    lib = _lib.lib
+    N, T, L, R, B = 127, 4, 16, 4, 2
+    K = T * L
+    with _plan(N, T, L, R) as p:
+        h = p.handle
+        y = dev(_rand_frames(N, R, B, 95))
+        H = torch.zeros((B, R, K), dtype=torch.complex64, device="cuda")
+        q, sc = p.pack(y, "bf16")
+        q8, sc8 = p.pack(y, "e4m3")
+        A = torch.zeros_like(y)
+        W = torch.empty_like(y)
+        yp, Hp, qp, sp = y.data_ptr(), H.data_ptr(), q.data_ptr(), sc.data_ptr()
+        torch.cuda.synchronize()
+        assert lib.pnce_estimate(h, None, yp + 4, Hp, B, 1, 1.0 / N, None, 0.0) == -1
+        assert lib.pnce_estimate(h, None, yp, Hp + 4, B, 1, 1.0 / N, None, 0.0) == -1
+        assert lib.pnce_estimate(h, None, yp, Hp, B, 1, 1.0 / N, sp + 2, 0.0) == -1
+        assert b"aligned" in lib.pnce_last_error()
+        assert lib.pnce_estimate_packed(h, None, qp + 4, sp, Hp, B, 1, 0.0) == -1
+        assert lib.pnce_estimate_packed(h, None, q8.data_ptr() + 2, sc8.data_ptr(), Hp, B, 3,
+                                        0.0) == -1
+        assert lib.pnce_pack(h, None, yp, qp + 2, sp, B, 1) == -1
+        assert lib.pnce_adjoint(h, None, Hp + 4, A.data_ptr(), None, B, 1, 1.0 / N, 0.0) == -1
+        assert lib.pnce_refine(h, None, yp, Hp, W.data_ptr() + 4, B, 1) == -1
+        assert lib.pnce_debias(h, None, Hp + 4, B) == -1
+        assert lib.pnce_estimate_ls(h, None, yp + 4, Hp, B, 1, None) == -1
+        assert lib.pnce_estimate_cp(h, None, yp + 4, 0, Hp, B, 1, None) == -1
+        assert lib.pnce_pack_cp(h, None, yp, 0, qp, sp + 1, B, 1) == -1
+        # e4m3 codes need only 4-byte alignment: a 4-byte offset is accepted
+        # (the buffer has 4 spare bytes, so the shifted codes stay inside it)
+        q8s = torch.empty((B * R * 2 * (N + 1) + 4,), dtype=torch.uint8, device="cuda")
+        assert lib.pnce_pack(h, None, yp, q8s.data_ptr() + 4, sc8.data_ptr(), B, 3) == 0
+        torch.cuda.synchronize()
+        assert not H.abs().any() and not A.abs().any()
