@@ -218,3 +218,86 @@ def test_more_entry_points_reject_null_plan(lib):
     assert lib.pnce_varlen_tune(None, None, None, None, None, 1) == -1
     lib.pnce_varlen_destroy.argtypes = [P]
     assert lib.pnce_varlen_destroy(None) == 0
+
+
+def _expected_create_status(N, T, L, R, fb, spacing):
+    """pnce_create_ex's documented validation, in its order, restated: the
+    status a call must return when the device allocation (made only after
+    every check passes) fails through the fault hook."""
+    import oracle
+    if T <= 0 or L <= 0 or R <= 0:
+        return -1
+    d = next((k for k in range(2, 17) if (1 << k) - 1 == N), None)
+    if d is None:
+        return -2
+    K = T * L
+    if K > 16 * N:
+        return -1
+    if spacing not in (0, 1):
+        return -1
+    if spacing == 1 and K > N:
+        return -1
+    if fb >> d:
+        return -1
+    if fb and oracle.mseq_mask(d, fb) is None:
+        return -1
+    if R > 65535:
+        return -1
+    if (R + 32) * (max(N, K) + 1) * 8 >= 1 << 31:
+        return -2
+    return -3
+
+
+def test_create_ex_validation_matches_its_documented_rules():
+    """400 seeded argument sets (valid and invalid N, T, L, R, feedback masks
+    and spacings): every status equals the documented rules restated above,
+    and no call leaves a plan behind. Shapes stay far below the LDS limit of
+    the bit stream, which has its own test."""
+    import random
+    sys.path.insert(0, ROOT)
+    import oracle
+    rnd = random.Random(7)
+    cases = []
+    for _ in range(400):
+        d = rnd.randint(1, 17)
+        N = (1 << d) - 1 if rnd.random() < 0.85 else rnd.choice([0, -1, 100, 1000, (1 << d)])
+        N = min(N, 32767) if N > 0 and rnd.random() < 0.9 else N
+        T = rnd.randint(1, 64) if rnd.random() < 0.9 else rnd.choice([0, -3])
+        L = rnd.randint(1, 256) if rnd.random() < 0.9 else 0
+        Nn = max(N, 1)
+        if T > 0 and L > 0 and T * L > 4 * Nn:      # keep the stream far below the LDS limit
+            L = max(1, (4 * Nn) // T)
+        r = rnd.random()
+        R = (rnd.randint(1, 512) if r < 0.8 else 0 if r < 0.85 else
+             rnd.choice([65535, 65536]) if r < 0.93 else rnd.randint(1, 70000))
+        dd = next((k for k in range(2, 17) if (1 << k) - 1 == N), 5)
+        r = rnd.random()
+        if r < 0.55:
+            fb = 0
+        elif r < 0.75:
+            fb = rnd.choice(oracle.primitive_masks(dd)) if dd <= 12 else rnd.randint(1, (1 << dd) - 1)
+        elif r < 0.95:
+            fb = rnd.randint(1, (1 << dd) - 1)
+        else:
+            fb = rnd.randint(1 << dd, 1 << 17)
+        spacing = rnd.choice([0, 1]) if rnd.random() < 0.9 else rnd.choice([2, -1])
+        cases.append((N, T, L, R, fb, spacing))
+    code = ("import ctypes,sys,json; l=ctypes.CDLL(sys.argv[1]); "
+            "l.pnce_create_ex.argtypes=[ctypes.c_void_p]+[ctypes.c_int]*4+[ctypes.c_uint,ctypes.c_int];"
+            "out=[]\n"
+            "for N,T,L,R,fb,sp in json.loads(sys.stdin.read()):\n"
+            "  h=ctypes.c_void_p(); st=l.pnce_create_ex(ctypes.byref(h),N,T,L,R,fb,sp)\n"
+            "  out.append([st, bool(h.value)])\n"
+            "print(json.dumps(out))")
+    import json
+    env = dict(os.environ, PNCE_FAULT="alloc")
+    res = subprocess.run([sys.executable, "-c", code, LIB], input=json.dumps(cases),
+                         capture_output=True, text=True, env=env, check=True).stdout
+    got = json.loads(res)
+    seen = set()
+    for case, (st, left) in zip(cases, got):
+        want = _expected_create_status(*case)
+        assert st == want, (case, st, want)
+        assert not left, case
+        seen.add(want)
+    assert seen == {-1, -2, -3}
