@@ -301,3 +301,74 @@ def test_create_ex_validation_matches_its_documented_rules():
         assert not left, case
         seen.add(want)
     assert seen == {-1, -2, -3}
+
+
+def _expected_varlen_status(frames, fmt):
+    """pnce_varlen_create's documented validation, restated in its order;
+    None when every check passes (the call then reaches the device)."""
+    if not frames:
+        return -1
+    if fmt not in (1, 2):
+        return -1
+    for R, N, T, L, yo, ho in frames:
+        if not any((1 << k) - 1 == N for k in range(2, 17)):
+            return -2
+        if R <= 0 or T <= 0 or L <= 0 or R > 65535 or T * L > 16 * N:
+            return -1
+        if (R + 32) * 2 * (N + 1) * 2 >= 1 << 31:
+            return -2
+        if yo < 0 or ho < 0 or yo % 8:
+            return -1
+    return None
+
+
+def test_varlen_create_validation_matches_its_documented_rules():
+    """300 seeded frame lists (one to four frames, each field now and then
+    invalid) and formats: every refused list gets the documented status and
+    leaves no plan; an accepted list either builds a plan (on a GPU, then
+    destroyed) or fails at the device query (PNCE_E_HIP, here)."""
+    import json
+    import random
+    rnd = random.Random(11)
+    cases = []
+    for _ in range(300):
+        frames = []
+        for _ in range(rnd.randint(1, 4) if rnd.random() < 0.95 else 0):
+            d = rnd.randint(2, 12)
+            N = (1 << d) - 1 if rnd.random() < 0.93 else rnd.choice([0, 100, 1 << d])
+            R = rnd.randint(1, 96) if rnd.random() < 0.93 else rnd.choice([0, 65536, 40000])
+            T = rnd.randint(1, 16) if rnd.random() < 0.95 else 0
+            L = rnd.randint(1, 64) if rnd.random() < 0.95 else rnd.choice([0, 16 * max(N, 1)])
+            yo = 8 * rnd.randint(0, 1000) if rnd.random() < 0.93 else rnd.choice([-8, 4, 3])
+            ho = rnd.randint(0, 1000) if rnd.random() < 0.97 else -1
+            frames.append((R, N, T, L, yo, ho))
+        fmt = rnd.choice([1, 2]) if rnd.random() < 0.93 else rnd.choice([0, 3])
+        cases.append((frames, fmt))
+    code = ("import ctypes,sys,json\n"
+            "class D(ctypes.Structure):\n"
+            "  _fields_=[('R',ctypes.c_int),('N',ctypes.c_int),('T',ctypes.c_int),('L',ctypes.c_int),"
+            "('y_off',ctypes.c_longlong),('h_off',ctypes.c_longlong)]\n"
+            "l=ctypes.CDLL(sys.argv[1])\n"
+            "l.pnce_varlen_create.argtypes=[ctypes.c_void_p,ctypes.c_void_p,ctypes.c_int,ctypes.c_int]\n"
+            "l.pnce_varlen_destroy.argtypes=[ctypes.c_void_p]\n"
+            "out=[]\n"
+            "for frames,fmt in json.loads(sys.stdin.read()):\n"
+            "  arr=(D*max(1,len(frames)))(*[D(*f) for f in frames]); h=ctypes.c_void_p()\n"
+            "  st=l.pnce_varlen_create(ctypes.byref(h),ctypes.cast(arr,ctypes.c_void_p),len(frames),fmt)\n"
+            "  left=bool(h.value)\n"
+            "  if left: l.pnce_varlen_destroy(h)\n"
+            "  out.append([st,left])\n"
+            "print(json.dumps(out))")
+    res = subprocess.run([sys.executable, "-c", code, LIB], input=json.dumps(cases),
+                         capture_output=True, text=True, check=True).stdout
+    seen = set()
+    for (frames, fmt), (st, left) in zip(cases, json.loads(res)):
+        want = _expected_varlen_status(frames, fmt)
+        if want is None:
+            assert st in (0, 1, -4), (frames, fmt, st)
+            assert left == (st >= 0)
+        else:
+            assert st == want, (frames, fmt, st, want)
+            assert not left
+        seen.add(want)
+    assert {-1, -2, None} <= seen
