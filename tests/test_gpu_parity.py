@@ -580,3 +580,75 @@ def test_misaligned_pointers_are_refused():
         assert lib.pnce_pack(h, None, yp, q8s.data_ptr() + 4, sc8.data_ptr(), B, 3) == 0
         torch.cuda.synchronize()
         assert not H.abs().any() and not A.abs().any()
+
+
+def test_entry_point_statuses_follow_the_documented_checks():
+    """Seeded calls of the batch entry points with valid and invalid scalar
+    arguments and NULL buffers: every status follows the documented order
+    (plan, scalar arguments, empty batch, pointers, batch sign); accepted
+    calls run on correctly sized buffers and return PNCE_OK."""
+    import random
+    from paper_2206_05506_amd import _lib
+    lib = _lib.lib
+    N, T, L, R, BMAX, CP = 31, 2, 4, 3, 3, 5
+    K = T * L
+    rnd = random.Random(5)
+    with _plan(N, T, L, R) as p:
+        h = p.handle
+        y = dev(_rand_frames(N, R, BMAX, 96))
+        raw = dev(_rand_frames(N + CP, R, BMAX, 97))
+        H = torch.empty((BMAX, R, K), dtype=torch.complex64, device="cuda")
+        A = torch.empty_like(y)
+        C = torch.zeros_like(y)
+        W = torch.empty_like(y)
+        q = torch.empty((BMAX, R, 2, N + 1), dtype=torch.int16, device="cuda")
+        sc = torch.empty((BMAX,), dtype=torch.float32, device="cuda")
+        ptr = {"y": y.data_ptr(), "raw": raw.data_ptr(), "H": H.data_ptr(), "A": A.data_ptr(),
+               "C": C.data_ptr(), "W": W.data_ptr(), "q": q.data_ptr(), "sc": sc.data_ptr()}
+
+        def maybe(name):  # a buffer, or now and then NULL
+            return None if rnd.random() < 0.15 else ptr[name]
+
+        n_ok = n_err = 0
+        for _ in range(300):
+            batch = rnd.choice([0, 1, 2, 3, -1])
+            op = rnd.choice(["estimate", "pack", "estimate_cp", "refine", "adjoint"])
+            if op == "estimate":
+                prec = rnd.choice([0, 1, 2, 4, 9, -1])
+                a, b = maybe("y"), maybe("H")
+                want = (-1 if prec not in (0, 1, 2, 4) else 0 if batch == 0 else
+                        -1 if a is None or b is None or batch < 0 else 0)
+                st = lib.pnce_estimate(h, None, a, b, batch, prec, 1.0 / N, None, 0.0)
+            elif op == "pack":
+                fmt = rnd.choice([1, 2, 0, 4])
+                a, b, c = maybe("y"), maybe("q"), maybe("sc")
+                want = (-1 if fmt not in (1, 2) else 0 if batch == 0 else
+                        -1 if None in (a, b, c) or batch < 0 else 0)
+                st = lib.pnce_pack(h, None, a, b, c, batch, fmt)
+            elif op == "estimate_cp":
+                prec = rnd.choice([1, 2, 7])
+                cp = rnd.choice([CP, -1, 1 << 26])
+                a, b = maybe("raw"), maybe("H")
+                want = (-1 if prec == 7 or cp < 0 else -2 if cp == 1 << 26 else
+                        0 if batch == 0 else -1 if a is None or b is None or batch < 0 else 0)
+                st = lib.pnce_estimate_cp(h, None, a, cp, b, batch, prec, None)
+            elif op == "refine":
+                steps = rnd.choice([0, 1, 2, -1])
+                a, b, c = maybe("y"), maybe("H"), maybe("W")
+                want = (-1 if steps < 0 else 0 if batch == 0 else
+                        -1 if a is None or b is None or (c is None and steps > 0) or batch < 0
+                        else 0)
+                st = lib.pnce_refine(h, None, a, b, c, batch, steps)
+            else:
+                prec = rnd.choice([1, 2, 5])
+                beta = rnd.choice([0.0, 1.0])
+                a, b, c = maybe("H"), maybe("A"), maybe("C")
+                want = (-1 if prec == 5 else 0 if batch == 0 else
+                        -1 if a is None or b is None or (beta != 0.0 and c is None) or batch < 0
+                        else 0)
+                st = lib.pnce_adjoint(h, None, a, b, c, batch, prec, 1.0 / N, beta)
+            assert st == want, (op, batch, st, want)
+            n_ok += st == 0
+            n_err += st < 0
+        torch.cuda.synchronize()
+    assert n_ok > 50 and n_err > 50
