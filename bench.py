@@ -233,7 +233,40 @@ def other_rows(plan, cfg, y, H, torch, args):
     del q, Hq, A, X, work
     res["eq8_lags"] = eq8_lags(cfg, y, H, res, torch, args)
     res["uneven_batch"] = uneven_batch(torch, args)
+    res["frames_per_launch"] = frames_per_launch(plan, cfg, torch)
     return res
+
+
+def frames_per_launch(plan, cfg, torch):
+    """The same bf16 estimate with 16 to 4096 frames per launch, frames
+    rotated over buffers of at least 1 GB in total (streamed from HBM): time
+    per launch and the fraction of the 8 TB/s HBM peak reached. A launch of
+    256 frames is one round of tiles (two per CU) whose start and end phases
+    overlap nothing; longer launches overlap them with other tiles' streaming."""
+    R, N, K = cfg.R, cfg.N, cfg.K
+    g = torch.Generator(device="cuda")
+    g.manual_seed(31)
+    out = {}
+    for B in (16, 64, 256, 1024, 4096):
+        per = B * R * N * 8
+        nrot = max(2, min(64, (1 << 30) // per + 1))
+        ys = [torch.complex(torch.randn((B, R, N), generator=g, device="cuda"),
+                            torch.randn((B, R, N), generator=g, device="cuda")).contiguous()
+              for _ in range(nrot)]
+        Hs = [torch.empty((B, R, K), dtype=torch.complex64, device="cuda") for _ in range(nrot)]
+        c = [0]
+
+        def step():
+            c[0] = (c[0] + 1) % nrot
+            plan.estimate(ys[c[0]], "bf16", out=Hs[c[0]])
+
+        ms, _ = time_steps(step, 200 if B < 256 else 50, 10, torch)
+        gbs = B * R * (N + K) * 8 / ms / 1e6
+        out[str(B)] = {"us_per_launch": ms * 1e3, "CIR/s": B * R * cfg.T / (ms * 1e-3),
+                       "GB/s": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+        del ys, Hs
+        torch.cuda.empty_cache()
+    return out
 
 
 def eq8_lags(cfg, y, H, res, torch, args):
