@@ -46,8 +46,8 @@ ROTATE_COPIES = 5              # frame / CIR buffer copies the timed steps rotat
 # HBM bytes per launch of the bf16 estimate measured with rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
 # for the kernel source with this sha256; any other source reports null.
-TRAFFIC = {"source_sha256": "c0dcdea1c58f47c30c17afb3a27e1a3137129085f4c2b26733b346a7878cf707",
-           "bytes_per_launch": 203461582}
+TRAFFIC = {"source_sha256": "5b2ae679350dc357a5f1bb693846dad60b3ef591700604b91ffecf7ddd638203",
+           "bytes_per_launch": 203461198}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 / f16 matrix
 FP8_PEAK_TFLOPS = 5033.2       # dense fp8 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix

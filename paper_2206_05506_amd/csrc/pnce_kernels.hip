@@ -457,9 +457,17 @@ struct Tile {
 // segment: each block has its own first lag and builds its own B fragment per
 // k-step (no reuse across blocks), so a wave's blocks may sit in different
 // transmitters' segments and segments are padded to 32 columns only.
-template <int MODE, int IN, int NC, bool AL, bool SB = false>
+struct NoPre {
+  __device__ void operator()() const {}
+};
+
+// pre(): the caller's set-up of the LDS tables (sequence bits, window
+// table), run after the first stages' loads are issued so that their
+// latency overlaps it; the barrier below publishes both.
+template <int MODE, int IN, int NC, bool AL, bool SB = false, typename Pre = NoPre>
 __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
-                                         const uint32_t *lut, uint32_t *stage) {
+                                         const uint32_t *lut, uint32_t *stage,
+                                         const Pre &pre = Pre{}) {
   constexpr int NWIN = 2 * NC;
   constexpr int RS = StageGeom<MODE, IN>::rs;
   constexpr int PS = kRows * RS;
@@ -542,6 +550,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const uint32_t *sbits,
   using I0 = std::integral_constant<int, 0>;
 
   static_for<0, PF>([&](auto ij) { fetch(decltype(ij)::value, ij); });
+  pre();
   land(0, I0{}, stage);
   fetch(PF, I0{});
   __syncthreads();
@@ -795,8 +804,19 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
   const int rb = rest % tiles_r;
   const int b = rest / tiles_r;
 
-  for (int i = threadIdx.x; i < a.nbw; i += kThreads) smem[i] = a.bits[i];
-  fill_lut<IN>(smem + nbw_pad);
+  // One word of the bit stream per thread is loaded before the first
+  // stages' loads are issued and stored after them (see run_tile's pre);
+  // longer streams are copied there in a loop.
+  const bool one = a.nbw <= kThreads;
+  const uint32_t bw = (one && (int)threadIdx.x < a.nbw) ? a.bits[threadIdx.x] : 0u;
+  auto pre = [&]() {
+    if (one) {
+      if ((int)threadIdx.x < a.nbw) smem[threadIdx.x] = bw;
+    } else {
+      for (int i = threadIdx.x; i < a.nbw; i += kThreads) smem[i] = a.bits[i];
+    }
+    fill_lut<IN>(smem + nbw_pad);
+  };
   Tile tl;
   if constexpr (IN == IN_C64 || IN == IN_C64_LAGS)
     tl.in = (const float *)a.in + (size_t)b * a.R * a.ld_in * 2;
@@ -821,7 +841,7 @@ __global__ __launch_bounds__(kThreads, 2) void tg_kernel(TgArgs a, int tiles_r, 
   tl.rseg_len = a.rseg_len;
   tl.rseg_lag = a.rseg_lag;
   tl.rseg_n = a.rseg_n;
-  run_tile<MODE, IN, NC, AL, SB>(tl, smem, smem + nbw_pad, smem + nbw_pad + kLutDw);
+  run_tile<MODE, IN, NC, AL, SB>(tl, smem, smem + nbw_pad, smem + nbw_pad + kLutDw, pre);
 }
 
 // Persistent kernel over an uneven batch: workgroup w walks its slice of a
