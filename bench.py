@@ -1,29 +1,33 @@
 """Benchmark: CIR estimates per second of PN-correlation channel estimation on
-one MI355X, BF16 matrix-core path against the FP32-accurate path at matched
-NMSE, plus p50 single-frame latency.
+one MI355X, BF16 matrix-core path against the FP32 paths at matched NMSE, plus
+p50 single-frame latency.
 
-Workload (FP32-baseline shape): N = 1023 (degree-10 m-sequence), T = 16
-multiplexed transmitters, L = 32 taps (T*L = 512 lags), R = 64 antennas,
-256 frames of complex64 input, exponential power-delay profile (decay 8
-taps), SNR uniform in [0, 20] dB per frame. Synthetic frames: seeded draws
-(synth), composed into y = P h + noise by the library's own adjoint kernel.
+Headline workload (precision study): N = 4095 (degree-12 m-sequence), T = 32
+multiplexed transmitters, L = 64 taps (T*L = 2048 lags), R = 256 antennas,
+512 frames, exponential power-delay profile (decay 8 taps), SNR uniform in
+[-5, 25] dB per frame. Synthetic frames: seeded draws (synth) composed into
+y = P h + noise by torch's FFT circular convolution (no library kernel), then
+stored as bf16 codes with a per-frame power-of-two scale.
 
-A timed step is one estimation pass over the batch resident in HBM:
-  bf16 path  : pnce_estimate(precision=BF16) -- c64 frames read once, rounded
-               to bf16 in registers, +-1 operand expanded on chip, bf16
-               matrix cores, FP32 accumulation, c64 CIRs written;
-  fp32 path  : pnce_estimate(precision=F32S), FP32-accurate (timed too).
+A timed step is one estimation pass over the 512 frames resident in HBM:
+  pnce_estimate_packed(format=BF16) -- bf16 codes read once, +-1 operand
+  expanded on chip, bf16 matrix cores, FP32 accumulation, c64 CIRs written.
+The conversion of the complex64 frames into stored bf16 codes is not inside
+the step (the frames are held as bf16, as the workload states); it is timed
+beside it, and so is the variant that reads the complex64 frames and rounds
+them in registers. The FP32-accurate (3-way bf16 split) and FP32-matrix
+paths are timed on the same complex64 frames, each with its NMSE against the
+true channels.
 
-Besides the headline, the line carries timings of every other form of the
-path: the quantiser, the packed estimate, the adjoint, refinement and the
-4096-frame uneven batch (rows), the precision-study workload (N = 4095,
-T*L = 2048, R = 256, 512 frames: bf16 / f16 / e4m3 packed estimates and
-refinement) and the differentiation workload (N = 1023, T*L = 1024, R = 128,
-1024 frames: forward + backward through autograd), and a second one-frame
-latency that includes the copy of the frame from pinned host memory.
+Besides the headline the line carries the FP32-baseline workload (N = 1023,
+T*L = 512, R = 64, 256 frames: the HBM-bound shape), timings of every other
+form of the path (adjoint, refinement, least squares, Eq. 8 lags, the
+4096-frame uneven batch, the front end) and the differentiation workload
+(N = 1023, T*L = 1024, R = 128, 1024 frames: forward + backward through
+autograd).
 
 Prints one JSON line (rank 0). Usage:
-  python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-rows]
+  python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cpu] [--no-rows]
                   [--no-workloads]
 """
 from __future__ import annotations
@@ -41,13 +45,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-ROTATE_COPIES = 5              # frame / CIR buffer copies the timed steps rotate over
+ROTATE_COPIES = 5              # frame / CIR buffer copies the FP32-baseline steps rotate over
 
-# HBM bytes per launch of the bf16 estimate measured with rocprofv3 --pmc
+# HBM bytes per launch of the headline kernel measured with rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
 # for the kernel source with this sha256; any other source reports null.
-TRAFFIC = {"source_sha256": "5b2ae679350dc357a5f1bb693846dad60b3ef591700604b91ffecf7ddd638203",
-           "bytes_per_launch": 203461198}
+TRAFFIC = {"source_sha256": None, "bytes_per_launch": None}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 / f16 matrix
 FP8_PEAK_TFLOPS = 5033.2       # dense fp8 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix
@@ -63,17 +66,18 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="only 3 bf16 estimates and 3 plain copies of the frames (for "
-                         "rocprofv3 --pmc byte counters and their copy-kernel calibration)")
+                    help="only 3 headline launches (packed bf16 estimate, 512 precision-study "
+                         "frames) and 3 plain copies of the code buffer, for rocprofv3 --pmc "
+                         "byte counters and their copy-kernel calibration")
     ap.add_argument("--mfma-probe", action="store_true",
-                    help="only 3 launches each of the matrix-bound kernels (precision-study "
-                         "packed bf16 and e4m3 estimates on 64 frames, FP32-accurate and bf16 "
-                         "estimates of the benchmark frames), for rocprofv3 --pmc counters of "
-                         "matrix-core activity")
+                    help="only 3 launches each of the matrix-bound kernels (the headline "
+                         "packed bf16 estimate on all 512 precision-study frames, the e4m3 one, "
+                         "the FP32-accurate estimate of the same frames), for rocprofv3 --pmc "
+                         "counters of matrix-core activity")
     ap.add_argument("--no-rows", action="store_true",
-                    help="skip the quantiser/adjoint/refinement/uneven-batch timings")
+                    help="skip the adjoint/refinement/uneven-batch/front-end timings")
     ap.add_argument("--no-workloads", action="store_true",
-                    help="skip the precision-study and differentiation workloads")
+                    help="skip the FP32-baseline and differentiation workloads")
     return ap.parse_args()
 
 
@@ -85,19 +89,53 @@ def measured_traffic():
     return TRAFFIC["bytes_per_launch"] if sha == TRAFFIC["source_sha256"] else None
 
 
+def compose(plan, h, w, snr_db, torch, chunk=32):
+    """y = P h + sigma w on the GPU without the library: the stacked taps
+    (column k of H at the plan's lag k) circularly convolved with the plan's
+    sequence by torch's FFT (the receive model of Eq. 9), noise scaled per
+    frame to the drawn receive SNR (sigma^2 = mean clean power / 10^(SNR/10)).
+    h [F, R, K], w [F, R, N] complex64 and snr_db [F] on the device."""
+    F, R, K = h.shape
+    N = plan.N
+    S = torch.fft.fft(torch.from_numpy(plan.sequence().astype(np.float32)).cuda()
+                      .to(torch.complex64))
+    lag = torch.from_numpy(plan.lags().astype(np.int64) % N).cuda()
+    y = torch.empty((F, R, N), dtype=torch.complex64, device="cuda")
+    for f0 in range(0, F, chunk):
+        f1 = min(F, f0 + chunk)
+        g = torch.zeros((f1 - f0, R, N), dtype=torch.complex64, device="cuda")
+        g.index_add_(2, lag, h[f0:f1])
+        yc = torch.fft.ifft(torch.fft.fft(g, dim=-1) * S, dim=-1)
+        p = (yc.abs() ** 2).mean(dim=(1, 2)).double()
+        sigma = torch.sqrt(p / 10.0 ** (snr_db[f0:f1].double() / 10.0)).float()
+        y[f0:f1] = yc + sigma[:, None, None] * w[f0:f1]
+        del g, yc
+    torch.cuda.synchronize()
+    return y
+
+
 def make_inputs(plan, cfg, torch):
-    """Seeded draws -> y = P h_stack + sigma w on the GPU (library adjoint)."""
+    """Seeded host draws of every frame of cfg, composed on the GPU."""
     import synth
     d = synth.batch_draws(cfg)
     h = torch.from_numpy(d["h"].reshape(cfg.B, cfg.R, cfg.K)).to(torch.complex64).cuda()
     w = torch.from_numpy(d["w"]).to(torch.complex64).cuda()
     snr = torch.from_numpy(d["snr_db"]).cuda()
-    y_clean = plan.adjoint(h, "f32s", alpha=1.0)          # P h (no 1/N)
-    p = (y_clean.abs() ** 2).mean(dim=(1, 2)).double()
-    sigma = torch.sqrt(p / 10.0 ** (snr / 10.0)).float()
-    y = (y_clean + sigma[:, None, None] * w).contiguous()
-    torch.cuda.synchronize()
+    y = compose(plan, h, w, snr, torch)
+    del w
     return y, h
+
+
+def make_device_inputs(plan, cfg, torch, frames=None):
+    """Seeded device draws (the precision study's 537 M samples are drawn on
+    the GPU), composed on the GPU."""
+    import synth
+    d = synth.device_draws(cfg, torch, frames=frames)
+    F = d["h"].shape[0]
+    h = d["h"].reshape(F, cfg.R, cfg.K)
+    y = compose(plan, h, d["w"], d["snr_db"], torch)
+    del d
+    return y, h.contiguous()
 
 
 def nmse_db(H, h):
@@ -164,37 +202,251 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(y_dev, cfg, target_s):
-    """The FP64 oracle on a bounded sample of the same frames, on the host's
-    cores (OpenMP): whole passes over the first n frames, repeated until at
-    least target_s seconds of work (one pass is at most about target_s). Returns the cpu_baseline object of the JSON line."""
+def _elementwise(x, ref):
+    """max over frames of max|x - ref| / max|ref| (frame = leading axis)."""
+    B = ref.shape[0]
+    d = np.abs(x - ref).reshape(B, -1).max(axis=1)
+    m = np.abs(ref).reshape(B, -1).max(axis=1)
+    return float(np.max(d / np.where(m == 0, 1.0, m)))
+
+
+def cpu_baseline(plan, cfg, y_dev, q_dev, sc_dev, H_dev, target_s, torch):
+    """The FP64 oracle on the host's cores (OpenMP) over a bounded sample of
+    the headline frames: whole passes over the first n complex64 frames,
+    repeated until at least target_s seconds of work (one pass is at most
+    about target_s), then one frame on one thread. The same leg checks the
+    timed output against the oracle on a few of those frames (the correlation
+    of the dequantised bf16 codes), and the refinement iterates from each
+    packed start against the oracle's FP64 iterates with the same step count.
+    Returns the cpu_baseline object of the JSON line."""
     import oracle
     s = oracle.mseq(cfg.d)
-    y = y_dev.cpu().numpy()
-    oracle.correlate(y[:2], s, cfg.K)                      # warm-up (threads, pages)
+    if not np.array_equal(s, plan.sequence()):
+        raise RuntimeError("library sequence differs from the oracle's")
+    K = cfg.K
+    y1 = y_dev[:1].cpu().numpy()
+    oracle.correlate(y1, s, K)                               # warm-up (threads, pages)
     t0 = time.perf_counter()
-    oracle.correlate(y[:8], s, cfg.K)
-    per_frame = (time.perf_counter() - t0) / 8
+    oracle.correlate(y1, s, K)
+    per_frame = time.perf_counter() - t0
     n = int(max(1, min(cfg.B, round(target_s / max(per_frame, 1e-4)))))
+    y = y_dev[:n].cpu().numpy()
     reps = 0
     t0 = time.perf_counter()
     while True:                                  # whole passes until target_s is reached
-        oracle.correlate(y[:n], s, cfg.K)
+        oracle.correlate(y, s, K)
         reps += 1
         dt = time.perf_counter() - t0
         if dt >= target_s:
             break
-    # one thread, on a quarter of the sample
-    n1 = max(1, n // 4)
     t0 = time.perf_counter()
-    oracle.correlate(y[:n1], s, cfg.K, threads=1)
+    oracle.correlate(y1, s, K, threads=1)
     dt1 = time.perf_counter() - t0
+
+    # the headline output of the first frames against the oracle on the same codes
+    nchk = min(4, cfg.B)
+    ref = oracle.correlate(oracle.dequantize(q_dev[:nchk].cpu().numpy(),
+                                             sc_dev[:nchk].cpu().numpy(), "bf16", cfg.N), s, K)
+    got = H_dev[:nchk].cpu().numpy()
+    check = {"frames": nchk, "relerr_max": oracle.relerr(got, ref),
+             "elementwise_max": _elementwise(got, ref), "bound": 1e-5,
+             "what": "headline CIRs of the first frames vs the FP64 oracle correlation of "
+                     "the same dequantised bf16 codes (normwise per frame, and max|dH| / "
+                     "max|H_ref| per frame)"}
+    check["pass"] = bool(check["relerr_max"] <= 1e-5 and check["elementwise_max"] <= 1e-5)
+
+    # refinement from each packed start against the oracle's FP64 iterates
+    nacc = min(2, cfg.B)
+    its = oracle.refine(y[:nacc].astype(np.complex128), s, K, 5)
+    ya = y_dev[:nacc].contiguous()
+    work = torch.empty_like(ya)
+    acc = {"frames": nacc,
+           "reference": "oracle FP64 iterate with the same k, from the FP64 correlation of "
+                        "the same complex64 frames"}
+    for fmt in ("bf16", "f16", "e4m3"):
+        qa, sa = plan.pack(ya, fmt)
+        x0 = plan.estimate_packed(qa, sa, fmt)
+        rows = []
+        for k in range(6):
+            X = x0.clone()
+            if k:
+                plan.refine(ya, X, k, work=work)
+            xh = X.cpu().numpy()
+            rows.append({"k": k, "relerr_vs_fp64": oracle.relerr(xh, its[k]),
+                         "elementwise_vs_fp64": _elementwise(xh, its[k])})
+        acc[fmt] = rows
+    del ya, work
     return {"value": reps * n * cfg.R * cfg.T / dt, "unit": "CIR estimates/s",
-            "one_thread_value": n1 * cfg.R * cfg.T / dt1, "cpu_model": cpu_model(),
-            "nproc": os.cpu_count(),
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{reps} pass(es) over {n} of {cfg.B} frames (N={cfg.N}, T*L={cfg.K}, "
-                      f"R={cfg.R}), FP64 direct correlation, {dt:.1f} s"}
+            "one_thread_value": cfg.R * cfg.T / dt1, "cpu_model": cpu_model(),
+            "nproc": os.cpu_count(), "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{reps} pass(es) over {n} of {cfg.B} frames of the headline workload "
+                      f"(N={cfg.N}, T*L={K}, R={cfg.R}), FP64 direct correlation of the "
+                      f"complex64 frames, {dt:.1f} s; one-thread value from one frame",
+            "oracle_check": check, "accuracy_vs_oracle_fp64": acc}
+
+
+def headline(torch, args):
+    """The precision-study workload: the timed step (packed bf16 estimate of
+    512 frames), the other precisions on the same frames with their NMSE, the
+    quantiser, refinement and one-frame latencies. Returns (line, ctx): the
+    JSON fields of the headline and the tensors the CPU leg checks."""
+    import synth
+    from paper_2206_05506_amd import Plan
+    cfg = synth.PRECISION
+    B, R, N, K, T = cfg.B, cfg.R, cfg.N, cfg.K, cfg.T
+    plan = Plan(N, T, cfg.L, R)
+    y, h = make_device_inputs(plan, cfg, torch)
+    q, sc = plan.pack(y, "bf16")
+    H = torch.empty((B, R, K), dtype=torch.complex64, device="cuda")
+
+    def step():
+        plan.estimate_packed(q, sc, "bf16", out=H)
+
+    spin_up(step, 0.3, torch)
+    ms_bf, wall_bf = time_steps(step, args.steps, args.warmup, torch)
+    nmse = {"bf16": nmse_db(H, h)}
+
+    few = max(3, args.steps // 10)
+    H2 = torch.empty_like(H)
+    # the same estimate read straight from the complex64 frames (each sample
+    # rounded to bf16 in registers; no stored copy, no scale)
+    ms_c64, _ = time_steps(lambda: plan.estimate(y, "bf16", out=H2), few, 2, torch)
+    nmse["bf16_from_c64"] = nmse_db(H2, h)
+    # the conversion that produces the stored codes (Section III-B)
+    ms_pack, _ = time_steps(lambda: plan.pack(y, "bf16", out=q, scales=sc), few, 1, torch)
+    frame_b = B * R * N * 8
+    code_b = q.numel() * q.element_size()
+    formats = {}
+    for fmt, peak in (("f16", BF16_PEAK_TFLOPS), ("e4m3", FP8_PEAK_TFLOPS)):
+        qf, sf = plan.pack(y, fmt)
+        ms_p, _ = time_steps(lambda: plan.pack(y, fmt, out=qf, scales=sf), few, 1, torch)
+        ms_e, _ = time_steps(lambda: plan.estimate_packed(qf, sf, fmt, out=H2), few, 1, torch)
+        nmse[fmt] = nmse_db(H2, h)
+        cb = qf.numel() * qf.element_size()
+        formats[fmt] = {"estimate_ms": ms_e, "CIR/s": B * R * T / (ms_e * 1e-3),
+                        "mfma_frac": 4.0 * B * R * N * K / ms_e / 1e9 / peak,
+                        "pack_ms": ms_p, "pack_GB/s": (frame_b + cb) / ms_p / 1e6,
+                        "pack_hbm_frac": (frame_b + cb) / ms_p / 1e6 / HBM_PEAK_GBS}
+        del qf, sf
+    ms_32, _ = time_steps(lambda: plan.estimate(y, "f32s", out=H2), few, 2, torch)
+    nmse["fp32_accurate"] = nmse_db(H2, h)
+    ms_mf, _ = time_steps(lambda: plan.estimate(y, "f32", out=H2), 3, 1, torch)
+    nmse["fp32_mfma"] = nmse_db(H2, h)
+
+    # least-squares refinement from the bf16 estimate (original c64 frames)
+    work = torch.empty_like(y)
+    X = H.clone()
+    ref_ms = {}
+    for k in (1, 2, 5):
+        ref_ms[k], _ = time_steps(lambda: plan.refine(y, X, k, work=work), 2, 1, torch)
+    del X, work, H2
+    torch.cuda.empty_cache()
+
+    # one frame: kernel-only p50 latency, and with the frame's copy from
+    # pinned host memory (the paper's latency includes the transfer)
+    lat = {}
+    if args.latency_iters > 0:
+        y1, q1, s1 = y[:1].contiguous(), q[:1].contiguous(), sc[:1].contiguous()
+        H1 = torch.empty((1, R, K), dtype=torch.complex64, device="cuda")
+        it = args.latency_iters
+        lat["bf16"] = p50_latency_us(lambda: plan.estimate_packed(q1, s1, "bf16", out=H1), it,
+                                     torch)
+        lat["bf16_from_c64"] = p50_latency_us(lambda: plan.estimate(y1, "bf16", out=H1), it,
+                                              torch)
+        lat["fp32_accurate"] = p50_latency_us(lambda: plan.estimate(y1, "f32s", out=H1), it,
+                                              torch)
+        q1h = torch.empty(q1.shape, dtype=q1.dtype, pin_memory=True)
+        q1h.copy_(q1.cpu())
+        q1d = torch.empty_like(q1)
+        y1h = torch.empty(y1.shape, dtype=y1.dtype, pin_memory=True)
+        y1h.copy_(y1.cpu())
+        y1d = torch.empty_like(y1)
+
+        def codes_in():
+            q1d.copy_(q1h, non_blocking=True)
+            plan.estimate_packed(q1d, s1, "bf16", out=H1)
+
+        def c64_in():
+            y1d.copy_(y1h, non_blocking=True)
+            plan.estimate(y1d, "bf16", out=H1)
+
+        lat["bf16_with_h2d_copy_of_codes"] = p50_latency_us(codes_in, it, torch)
+        lat["bf16_from_c64_with_h2d_copy"] = p50_latency_us(c64_in, it, torch)
+        pc = synth.PLAIN
+        pp = Plan(pc.N, pc.T, pc.L, pc.R)
+        yp = _randn_c64((1, pc.R, pc.N), 13, torch)
+        Hp = torch.empty((1, pc.R, pc.K), dtype=torch.complex64, device="cuda")
+        lat["plain_workload"] = {prec: p50_latency_us(lambda: pp.estimate(yp, prec, out=Hp), it,
+                                                      torch) for prec in ("bf16", "f32s")}
+        pp.close()
+        del y1h, q1h, y1d, q1d, H1
+
+    cirs = B * R * T
+    flops = 4.0 * B * R * N * K
+    out_b = B * R * K * 8
+    ach = flops / (ms_bf * 1e-3) / 1e12
+    line = {
+        "metric": "CIR estimates/s + p50 frame latency; BF16-MFMA vs FP32 at matched NMSE",
+        "value": cirs / (ms_bf * 1e-3),
+        "frames_per_s": B / (ms_bf * 1e-3),
+        "unit": "CIR estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_bf,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded device draws; y = P h + noise by torch FFT circular "
+                "convolution; stored as bf16 codes with a per-frame power-of-two scale)",
+        "config": {"workload": cfg.name, "N": N, "T": T, "L": cfg.L, "R": R, "frames": B,
+                   "input": "bf16 codes [B][R][2][N+1] + per-frame scale, resident in HBM",
+                   "snr_db": [cfg.snr_lo, cfg.snr_hi],
+                   "step": "one pnce_estimate_packed(bf16) launch over all frames; the "
+                           "conversion to bf16 codes is not in the step (timed in "
+                           "pack_bf16_ms)"},
+        "p50_frame_latency_us": lat,
+        "fp32_path": {"value": cirs / (ms_32 * 1e-3), "ms_per_step": ms_32,
+                      "precision": "f32s: FP32-accurate, each FP32 sample split exactly into "
+                                   "three bf16 parts, three bf16 matrix-core products",
+                      "input": "complex64 frames"},
+        "fp32_mfma_path": {"value": cirs / (ms_mf * 1e-3), "ms_per_step": ms_mf,
+                           "precision": "f32: v_mfma_f32_32x32x2_f32",
+                           "mfma_frac": flops / ms_mf / 1e9 / FP32_PEAK_TFLOPS},
+        "bf16_speedup_vs_fp32": {"fp32_accurate": ms_32 / ms_bf, "fp32_mfma": ms_mf / ms_bf,
+                                 "delta_nmse_db_vs_fp32_accurate":
+                                     nmse["bf16"] - nmse["fp32_accurate"],
+                                 "matched_nmse": abs(nmse["bf16"] - nmse["fp32_accurate"])
+                                 <= 0.05,
+                                 "note": "same frames; matched NMSE = within 0.05 dB"},
+        "nmse_db": nmse,
+        "bf16_from_c64": {"ms_per_step": ms_c64, "CIR/s": cirs / (ms_c64 * 1e-3),
+                          "mfma_frac": flops / ms_c64 / 1e9 / BF16_PEAK_TFLOPS,
+                          "note": "pnce_estimate(bf16) on the complex64 frames: each sample "
+                                  "rounded to bf16 in registers, no stored copy"},
+        "pack_bf16_ms": ms_pack,
+        "pack_bf16_GB/s": (frame_b + code_b) / ms_pack / 1e6,
+        "pack_bf16_hbm_frac": (frame_b + code_b) / ms_pack / 1e6 / HBM_PEAK_GBS,
+        "pack_plus_estimate_ms": ms_pack + ms_bf,
+        "other_formats": formats,
+        "refine_ms": {f"{k}_steps": v for k, v in ref_ms.items()},
+        "bf16_plus_2_refine_steps": {
+            "ms": ms_bf + ref_ms[2], "CIR/s": cirs / ((ms_bf + ref_ms[2]) * 1e-3),
+            "note": "bf16 estimate then 2 FP32 refinement steps (the last residual with FP64 "
+                    "sums): within 1e-5 of the FP64 iterate (accuracy_vs_oracle_fp64)"},
+        "wall_ms_per_step": wall_bf,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
+                     "traffic": measured_traffic(),
+                     "kernel": "tg_kernel<BF16, bf16 codes, NC=4>",
+                     "flops_per_launch": flops,
+                     "algorithmic_bytes_per_launch": code_b + out_b,
+                     "hbm_GB/s": (code_b + out_b) / (ms_bf * 1e-3) / 1e9},
+    }
+    ctx = {"plan": plan, "cfg": cfg, "y": y, "q": q, "sc": sc, "H": H}
+    del h
+    return line, ctx
 
 
 def other_rows(plan, cfg, y, H, torch, args):
@@ -367,96 +619,138 @@ def _randn_c64(shape, seed, torch):
     return torch.complex(re, im).contiguous()
 
 
-def precision_workload(torch, args):
-    """Precision-study shape (N=4095, T=32, L=64, R=256, 512 frames): quantiser,
-    packed estimates in bf16 / f16 / e4m3, and least-squares refinement from
-    the original complex64 frames (parity is in the GPU tests; here, time)."""
+def fp32_baseline_workload(torch, args):
+    """The FP32-baseline shape (N = 1023, T*L = 512, R = 64, 256 frames),
+    HBM-bound for bf16 (AI 171 < ridge 315): the bf16 estimate with frames
+    streamed from HBM (rotated buffers) and cache-resident, pipelined over two
+    streams, the FP32 paths, p50 latency, and the other rows of the path on
+    these frames."""
     import synth
     from paper_2206_05506_amd import Plan
-    cfg = synth.PRECISION
-    B, R, N, K = cfg.B, cfg.R, cfg.N, cfg.K
-    plan = Plan(N, cfg.T, cfg.L, R)
-    y = _randn_c64((B, R, N), 21, torch)
-    H = torch.empty((B, R, K), dtype=torch.complex64, device="cuda")
-    flops = 4.0 * B * R * N * K
-    res = {"workload": cfg.name, "frames": B, "R": R, "N": N, "T*L": K}
-    steps = max(2, args.steps // 4)
-    for fmt, peak in (("bf16", BF16_PEAK_TFLOPS), ("f16", BF16_PEAK_TFLOPS),
-                      ("e4m3", FP8_PEAK_TFLOPS)):
-        q, sc = plan.pack(y, fmt)
-        ms_p, _ = time_steps(lambda: plan.pack(y, fmt, out=q, scales=sc), steps, 1, torch)
-        ms_e, _ = time_steps(lambda: plan.estimate_packed(q, sc, fmt, out=H), steps, 1, torch)
-        code_b = q.numel() * q.element_size()
-        res[fmt] = {"pack_ms": ms_p, "pack_GB/s": (B * R * N * 8 * 2 + code_b) / ms_p / 1e6,
-                    "estimate_ms": ms_e, "TFLOP/s": flops / ms_e / 1e9,
-                    "mfma_frac": flops / ms_e / 1e9 / peak,
-                    "GB/s": (code_b + B * R * K * 8) / ms_e / 1e6,
-                    "CIR/s": B * R * cfg.T / (ms_e * 1e-3)}
-        del q, sc
-    ms_s, _ = time_steps(lambda: plan.estimate(y, "f32s", out=H), steps, 1, torch)
-    res["f32s_estimate_ms"] = ms_s
-    work = torch.empty_like(y)
-    X = H.clone()
-    ms_1, _ = time_steps(lambda: plan.refine(y, X, 1, work=work), 2, 1, torch)
-    ms_5, _ = time_steps(lambda: plan.refine(y, X, 5, work=work), 2, 1, torch)
-    res["refine"] = {"steps_1_ms": ms_1, "steps_5_ms": ms_5,
-                     "note": "every step: residual y - P x then x += P^T r / N (f32s); the "
-                             "last step's residual accumulates in FP64 on FP64 matrix cores"}
+    cfg = synth.FP32
+    plan = Plan(cfg.N, cfg.T, cfg.L, cfg.R)
+    y, h = make_inputs(plan, cfg, torch)
+    H_bf = torch.empty((cfg.B, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
+    H_32 = torch.empty_like(H_bf)
+    H_mf = torch.empty_like(H_bf)
+
+    # The 201 MB working set of one step fits in the 256 MB Infinity Cache, so
+    # a step that re-reads the frames of the previous step is served partly
+    # from that cache. Timed steps therefore rotate over ROT copies of the
+    # frames and of the CIR buffers (ROT * 201 MB > 4x the cache): every step
+    # streams its frames from HBM, as fresh frames would. The same data is in
+    # every copy.
+    n_rot = ROTATE_COPIES
+    ys = [y] + [y.clone() for _ in range(n_rot - 1)]
+    Hs = [H_bf] + [torch.empty_like(H_bf) for _ in range(n_rot - 1)]
+    ctr = [0]
+
+    def rot():
+        ctr[0] = (ctr[0] + 1) % n_rot
+        return ctr[0]
+
+    def step(prec):
+        i = rot()
+        plan.estimate(ys[i], prec, out=Hs[i])
+
+    spin_up(lambda: step("bf16"), 0.3, torch)
+    ms_bf, _ = time_steps(lambda: step("bf16"), args.steps, args.warmup, torch)
+    # context for the roofline: a plain device copy of the same frame buffers
+    # (rotated likewise), read + write bytes over its time
+    ms_cp, _ = time_steps(lambda: ys[rot()].copy_(ys[(ctr[0] + 2) % n_rot]), args.steps, 2, torch)
+    ms_bf_cached, _ = time_steps(lambda: plan.estimate(y, "bf16", out=H_bf), args.steps,
+                                 args.warmup, torch)
+    ms_32, _ = time_steps(lambda: step("f32s"), args.steps, args.warmup, torch)
+    H_32.copy_(Hs[ctr[0]])
+    ms_mf, _ = time_steps(lambda: step("f32"), max(2, args.steps // 4), 2, torch)
+    H_mf.copy_(Hs[ctr[0]])
+    # Independent batches pipelined over two streams (default priority), as a
+    # serving loop would issue them: step k runs on stream k % 2 with buffer
+    # k % 6, so each buffer always belongs to the same stream and its reuse is
+    # ordered. One launch's end phase then overlaps the next one's start.
+    ys.append(y.clone())
+    Hs.append(torch.empty_like(H_bf))
+    pipe = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def pipelined(k0, n):
+        for k in range(k0, k0 + n):
+            with torch.cuda.stream(pipe[k % 2]):
+                plan.estimate(ys[k % 6], "bf16", out=Hs[k % 6])
+
+    cur = torch.cuda.current_stream()
+    for st in pipe:
+        st.wait_stream(cur)
+    spin_up(lambda: pipelined(0, 2), 0.2, torch)
+    pipelined(0, args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(cur)
+    for st in pipe:
+        st.wait_stream(cur)
+    pipelined(args.warmup, args.steps)
+    for st in pipe:
+        cur.wait_stream(st)
+    e1.record(cur)
+    torch.cuda.synchronize()
+    ms_pipe = e0.elapsed_time(e1) / args.steps
+    plan.estimate(y, "bf16", out=H_bf)
+    del ys, Hs
+
+    lat = {}
+    lat_h2d = None
+    if args.latency_iters > 0:
+        y1 = y[:1].contiguous()
+        H1 = torch.empty((1, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
+        lat["bf16"] = p50_latency_us(lambda: plan.estimate(y1, "bf16", out=H1),
+                                     args.latency_iters, torch)
+        lat["fp32_accurate"] = p50_latency_us(lambda: plan.estimate(y1, "f32s", out=H1),
+                                              args.latency_iters, torch)
+        y1_host = torch.empty(y1.shape, dtype=y1.dtype, pin_memory=True)
+        y1_host.copy_(y1.cpu())
+        y1_dev = torch.empty_like(y1)
+
+        def h2d_then_estimate():
+            y1_dev.copy_(y1_host, non_blocking=True)
+            plan.estimate(y1_dev, "bf16", out=H1)
+
+        lat_h2d = lat["bf16_with_h2d_copy"] = p50_latency_us(h2d_then_estimate,
+                                                             args.latency_iters, torch)
+
+    cirs = cfg.B * cfg.R * cfg.T
+    bytes_ = cfg.B * (cfg.R * cfg.N * 8 + cfg.R * cfg.K * 8)
+    ach_gbs = bytes_ / (ms_bf * 1e-3) / 1e9
+    res = {
+        "workload": cfg.name, "frames": cfg.B, "input": "complex64",
+        "bf16_ms_per_step": ms_bf, "bf16_CIR/s": cirs / (ms_bf * 1e-3),
+        "fp32_accurate_ms_per_step": ms_32, "fp32_mfma_ms_per_step": ms_mf,
+        "bf16_speedup_vs_fp32": {"fp32_accurate": ms_32 / ms_bf, "fp32_mfma": ms_mf / ms_bf},
+        "nmse_db": {"bf16": nmse_db(H_bf, h), "fp32_accurate": nmse_db(H_32, h),
+                    "fp32_mfma": nmse_db(H_mf, h)},
+        "p50_frame_latency_us": lat,
+        "roofline_hbm": {"achieved_GB/s": ach_gbs, "peak_GB/s": HBM_PEAK_GBS,
+                         "frac": ach_gbs / HBM_PEAK_GBS,
+                         "kernel": "tg_kernel<BF16, c64 in, NC=4>",
+                         "algorithmic_bytes_per_launch": bytes_},
+        "timing": {"rotated_buffers": ROTATE_COPIES,
+                   "note": "each timed step reads its own copy of the frames and writes its own "
+                           "CIR buffer (5 x 201 MB > the 256 MB Infinity Cache), so frames stream "
+                           "from HBM",
+                   "cache_resident_ms_per_step": ms_bf_cached,
+                   "hbm_copy_GB/s": 2 * y.numel() * 8 / (ms_cp * 1e-3) / 1e9},
+        "pipelined_two_streams": {
+            "ms_per_step": ms_pipe, "CIR/s": cirs / (ms_pipe * 1e-3),
+            "hbm_frac": bytes_ / (ms_pipe * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "note": "the same steps issued alternately on two streams, as a serving loop "
+                    "pipelines independent batches"},
+    }
+    if not args.no_rows:
+        res["rows"] = other_rows(plan, cfg, y, H_32, torch, args)
+        res["rows"]["front_end"] = front_end(plan, cfg, y, torch, lat_h2d, args)
     plan.close()
-    del y, H, work, X
+    del y, h, H_bf, H_32, H_mf
     torch.cuda.empty_cache()
-    res["accuracy"] = precision_accuracy(torch, cfg)
     return res
-
-
-def precision_accuracy(torch, cfg, frames=8):
-    """Accuracy of the precision study's forms on `frames` frames of the
-    channel model (seeded device draws, y = P h + sigma w by the library's
-    adjoint): for the bf16-, f16- and e4m3-packed starts and k = 0..5 refinement
-    steps, the normwise error against the FP64 iterate with the same k (the
-    library's FP64 vector kernel on complex128 copies) and the NMSE against
-    h; and the FP32-accurate correlator's NMSE beside bf16's (k = 0)."""
-    from paper_2206_05506_amd import Plan
-    import synth
-    N, K, R = cfg.N, cfg.K, cfg.R
-    plan = Plan(N, cfg.T, cfg.L, R)
-    d = synth.device_draws(cfg, torch, frames=frames)
-    h = d["h"].reshape(frames, R, K)
-    y0 = plan.adjoint(h, "f32s", alpha=1.0)
-    p = (y0.abs() ** 2).mean(dim=(1, 2)).double()
-    sigma = torch.sqrt(p / 10.0 ** (d["snr_db"].double() / 10.0)).float()
-    y = (y0 + sigma[:, None, None] * d["w"]).contiguous()
-    del y0, d
-    # FP64 iterates x_{k+1} = x_k + P^T (y - P x_k) / N
-    y64 = y.to(torch.complex128)
-    x64 = [plan.estimate(y64, "f64")]
-    for _ in range(5):
-        r = y64 - plan.adjoint(x64[-1], "f64", alpha=1.0)
-        x64.append(x64[-1] + plan.estimate(r, "f64"))
-    del y64
-
-    def relerr(x, ref):
-        e = ((x.to(torch.complex128) - ref).abs() ** 2).reshape(frames, -1).sum(1)
-        n = (ref.abs() ** 2).reshape(frames, -1).sum(1)
-        return float(torch.sqrt(e / n).max())
-
-    out = {"frames": frames, "reference": "FP64 iterate with the same k (library FP64 kernel)"}
-    work = torch.empty_like(y)
-    for fmt in ("bf16", "f16", "e4m3"):
-        q, sc = plan.pack(y, fmt)
-        x0 = plan.estimate_packed(q, sc, fmt)
-        rows = []
-        for k in range(6):
-            X = x0.clone()
-            if k:
-                plan.refine(y, X, k, work=work)
-            rows.append({"k": k, "relerr_vs_fp64": relerr(X, x64[k]), "nmse_db": nmse_db(X, h)})
-        out[fmt] = rows
-        del q, sc, x0
-    out["fp32_k0_nmse_db"] = nmse_db(plan.estimate(y, "f32s"), h)
-    out["fp64_k5_nmse_db"] = nmse_db(x64[5].to(torch.complex64), h)
-    plan.close()
-    return out
 
 
 def differentiation_workload(torch, args):
@@ -551,29 +845,46 @@ def front_end(plan, cfg, y, torch, lat_h2d_us, args):
                     "airtime per multiplexed block of Eq. 11 at each sample rate"}
 
 
+def pmc_probe(torch):
+    """Three headline launches and three plain copies of the code buffer,
+    nothing timed: the workload of a rocprofv3 --pmc byte-counter run."""
+    import synth
+    from paper_2206_05506_amd import Plan
+    cfg = synth.PRECISION
+    plan = Plan(cfg.N, cfg.T, cfg.L, cfg.R)
+    y = _randn_c64((cfg.B, cfg.R, cfg.N), 21, torch)
+    q, sc = plan.pack(y, "bf16")
+    del y
+    H = torch.empty((cfg.B, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
+    q2 = torch.empty_like(q)
+    for _ in range(3):
+        plan.estimate_packed(q, sc, "bf16", out=H)
+    for _ in range(3):
+        q2.copy_(q)
+    torch.cuda.synchronize()
+    code_b = q.numel() * q.element_size()
+    print(json.dumps({"pmc_probe": True, "estimate_bytes_read": code_b,
+                      "estimate_bytes_written": H.numel() * 8,
+                      "copy_bytes_each_way": code_b}), flush=True)
+    plan.close()
+
+
 def mfma_probe(torch):
     """Three launches each of the matrix-core-bound kernels on fixed seeded
     data, nothing timed: the workload of a rocprofv3 --pmc run."""
+    import synth
     from paper_2206_05506_amd import Plan
-    N, T, L, R, B = 4095, 32, 64, 256, 64      # the precision study, 64 frames
-    p = Plan(N, T, L, R)
-    y = _randn_c64((B, R, N), 11, torch)
-    H = torch.empty((B, R, T * L), dtype=torch.complex64, device="cuda")
+    cfg = synth.PRECISION
+    p = Plan(cfg.N, cfg.T, cfg.L, cfg.R)
+    y = _randn_c64((cfg.B, cfg.R, cfg.N), 11, torch)
+    H = torch.empty((cfg.B, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
     for fmt in ("bf16", "e4m3"):
         q, sc = p.pack(y, fmt)
         for _ in range(3):
             p.estimate_packed(q, sc, fmt, out=H)
         del q, sc
-    p.close()
-    del y, H
-    import synth
-    cfg = synth.FP32
-    p = Plan(cfg.N, cfg.T, cfg.L, cfg.R)
-    y = _randn_c64((cfg.B, cfg.R, cfg.N), 12, torch)
-    H = torch.empty((cfg.B, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
-    for prec in ("f32s", "bf16"):
-        for _ in range(3):
-            p.estimate(y, prec, out=H)
+    for _ in range(3):
+        p.estimate(y, "f32s", out=H)
     torch.cuda.synchronize()
     p.close()
     print(json.dumps({"mfma_probe": True}), flush=True)
@@ -588,198 +899,23 @@ def main():
         sys.exit(2)
 
     import torch
-    import synth
-    from paper_2206_05506_amd import Plan
 
     if args.mfma_probe:
         mfma_probe(torch)
         return
-    cfg = synth.FP32
-    plan = Plan(cfg.N, cfg.T, cfg.L, cfg.R)
-    y, h = make_inputs(plan, cfg, torch)
-    H_bf = torch.empty((cfg.B, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
     if args.pmc_probe:
-        y2 = torch.empty_like(y)
-        for _ in range(3):
-            plan.estimate(y, "bf16", out=H_bf)
-        for _ in range(3):
-            y2.copy_(y)
-        torch.cuda.synchronize()
-        print(json.dumps({"pmc_probe": True, "estimate_bytes_read": cfg.B * cfg.R * cfg.N * 8,
-                          "estimate_bytes_written": cfg.B * cfg.R * cfg.K * 8,
-                          "copy_bytes_each_way": y.numel() * 8}), flush=True)
-        plan.close()
+        pmc_probe(torch)
         return
-    H_32 = torch.empty_like(H_bf)
-    H_mf = torch.empty_like(H_bf)
-
-    # The 201 MB working set of one step fits in the 256 MB Infinity Cache, so
-    # a step that re-reads the frames of the previous step is served partly
-    # from that cache. Timed steps therefore rotate over ROT copies of the
-    # frames and of the CIR buffers (ROT * 201 MB > 4x the cache): every step
-    # streams its frames from HBM, as fresh frames would. The same data is in
-    # every copy.
-    n_rot = ROTATE_COPIES
-    ys = [y] + [y.clone() for _ in range(n_rot - 1)]
-    Hs = [H_bf] + [torch.empty_like(H_bf) for _ in range(n_rot - 1)]
-    ctr = [0]
-
-    def rot():
-        ctr[0] = (ctr[0] + 1) % n_rot
-        return ctr[0]
-
-    def step_bf16():
-        i = rot()
-        plan.estimate(ys[i], "bf16", out=Hs[i])
-
-    def step_f32s():
-        i = rot()
-        plan.estimate(ys[i], "f32s", out=Hs[i])
-
-    def step_f32():
-        i = rot()
-        plan.estimate(ys[i], "f32", out=Hs[i])
-
-    spin_up(step_bf16, 0.3, torch)
-    ms_bf, wall_bf = time_steps(step_bf16, args.steps, args.warmup, torch)
-    # context for the roofline: a plain device copy of the same frame buffers
-    # (rotated likewise), read + write bytes over its time
-    ms_cp, _ = time_steps(lambda: ys[rot()].copy_(ys[(ctr[0] + 2) % n_rot]), args.steps, 2, torch)
-    # the same launch on one resident buffer (frames and CIRs cache-resident)
-    ms_bf_cached, _ = time_steps(lambda: plan.estimate(y, "bf16", out=H_bf), args.steps,
-                                 args.warmup, torch)
-    ms_32, _ = time_steps(step_f32s, args.steps, args.warmup, torch)
-    H_32.copy_(Hs[ctr[0]])
-    ms_mf, _ = time_steps(step_f32, max(2, args.steps // 4), 2, torch)
-    H_mf.copy_(Hs[ctr[0]])
-    # Independent batches pipelined over two streams (default priority), as a
-    # serving loop would issue them: step k runs on stream k % 2 with buffer
-    # k % 6, so each buffer always belongs to the same stream and its reuse is
-    # ordered. One launch's end phase then overlaps the next one's start.
-    ys.append(y.clone())
-    Hs.append(torch.empty_like(H_bf))
-    pipe = [torch.cuda.Stream(), torch.cuda.Stream()]
-
-    def pipelined(k0, n):
-        for k in range(k0, k0 + n):
-            with torch.cuda.stream(pipe[k % 2]):
-                plan.estimate(ys[k % 6], "bf16", out=Hs[k % 6])
-
-    cur = torch.cuda.current_stream()
-    for st in pipe:
-        st.wait_stream(cur)
-    spin_up(lambda: pipelined(0, 2), 0.2, torch)
-    pipelined(0, args.warmup)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(cur)
-    for st in pipe:
-        st.wait_stream(cur)
-    pipelined(args.warmup, args.steps)
-    for st in pipe:
-        cur.wait_stream(st)
-    e1.record(cur)
-    torch.cuda.synchronize()
-    ms_pipe = e0.elapsed_time(e1) / args.steps
-    plan.estimate(y, "bf16", out=H_bf)
-    del ys, Hs
-
-    y1 = y[:1].contiguous()
-    H1 = torch.empty((1, cfg.R, cfg.K), dtype=torch.complex64, device="cuda")
-    lat_bf = lat_32 = lat_h2d = lat_plain = None
-    if args.latency_iters > 0:
-        lat_bf = p50_latency_us(lambda: plan.estimate(y1, "bf16", out=H1), args.latency_iters,
-                                torch)
-        lat_32 = p50_latency_us(lambda: plan.estimate(y1, "f32s", out=H1), args.latency_iters,
-                                torch)
-        # the same frame handed over in pinned host memory: copy in, then estimate
-        y1_host = torch.empty(y1.shape, dtype=y1.dtype, pin_memory=True)
-        y1_host.copy_(y1.cpu())
-        y1_dev = torch.empty_like(y1)
-
-        def h2d_then_estimate():
-            y1_dev.copy_(y1_host, non_blocking=True)
-            plan.estimate(y1_dev, "bf16", out=H1)
-
-        lat_h2d = p50_latency_us(h2d_then_estimate, args.latency_iters, torch)
-        # the plain workload (N=127, T=4, L=16, R=16, one frame)
-        pc = synth.PLAIN
-        pp = Plan(pc.N, pc.T, pc.L, pc.R)
-        yp = _randn_c64((1, pc.R, pc.N), 13, torch)
-        Hp = torch.empty((1, pc.R, pc.K), dtype=torch.complex64, device="cuda")
-        lat_plain = {prec: p50_latency_us(lambda: pp.estimate(yp, prec, out=Hp),
-                                          args.latency_iters, torch) for prec in ("bf16", "f32s")}
-        pp.close()
-
-    nmse_bf = nmse_db(H_bf, h)
-    nmse_32 = nmse_db(H_32, h)
-    nmse_mf = nmse_db(H_mf, h)
-
-    cirs = cfg.B * cfg.R * cfg.T
-    flops = 4.0 * cfg.B * cfg.R * cfg.N * cfg.K
-    bytes_ = cfg.B * (cfg.R * cfg.N * 8 + cfg.R * cfg.K * 8)
-    ach_gbs = bytes_ / (ms_bf * 1e-3) / 1e9
-
-    out = {
-        "metric": "CIR estimates/s + p50 frame latency; BF16-MFMA vs FP32 at matched NMSE",
-        "value": cirs / (ms_bf * 1e-3),
-        "frames_per_s": cfg.B / (ms_bf * 1e-3),
-        "unit": "CIR estimates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_bf,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16",
-        "data": "synthetic (seeded draws, y = P h + noise composed on the GPU)",
-        "config": {"workload": cfg.name, "N": cfg.N, "T": cfg.T, "L": cfg.L, "R": cfg.R,
-                   "frames": cfg.B, "input": "complex64", "snr_db": [cfg.snr_lo, cfg.snr_hi]},
-        "p50_frame_latency_us": {"bf16": lat_bf, "fp32": lat_32,
-                                 "bf16_with_h2d_copy": lat_h2d,
-                                 "plain_workload": lat_plain},
-        "fp32_path": {"value": cirs / (ms_32 * 1e-3), "ms_per_step": ms_32,
-                      "precision": "f32s (3-way bf16 split, exact)"},
-        "fp32_mfma_path": {"value": cirs / (ms_mf * 1e-3), "ms_per_step": ms_mf,
-                           "precision": "f32 (v_mfma_f32_32x32x2_f32)"},
-        "bf16_speedup_vs_fp32": {"fp32_mfma": ms_mf / ms_bf, "fp32_accurate_bf16x3": ms_32 / ms_bf,
-                                 "note": "fp32_mfma: the FP32 matrix-core path "
-                                         "(v_mfma_f32_32x32x2_f32); fp32_accurate_bf16x3: the "
-                                         "faster FP32-accurate path (exact 3-way bf16 split); "
-                                         "all at equal NMSE (see nmse_db)"},
-        "nmse_db": {"bf16": nmse_bf, "fp32": nmse_32, "fp32_mfma": nmse_mf,
-                    "delta_bf16_fp32": nmse_bf - nmse_32},
-        "wall_ms_per_step": wall_bf,
-        "timing": {"rotated_buffers": ROTATE_COPIES,
-                   "note": "each timed step reads its own copy of the frames and writes its own "
-                           "CIR buffer (5 x 201 MB > the 256 MB Infinity Cache), so frames stream "
-                           "from HBM",
-                   "cache_resident_ms_per_step": ms_bf_cached,
-                   "hbm_copy_GB/s": 2 * y.numel() * 8 / (ms_cp * 1e-3) / 1e9,
-                   "cache_resident_GB/s": bytes_ / (ms_bf_cached * 1e-3) / 1e9},
-        "pipelined_two_streams": {
-            "ms_per_step": ms_pipe, "CIR/s": cirs / (ms_pipe * 1e-3),
-            "GB/s": bytes_ / (ms_pipe * 1e-3) / 1e9,
-            "hbm_frac": bytes_ / (ms_pipe * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "note": "the same steps (one launch each, frames streamed from HBM) issued "
-                    "alternately on two streams, as a serving loop pipelines independent "
-                    "batches; value above is the one-stream figure"},
-        "roofline": {"bound": "hbm", "achieved": ach_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": ach_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "tg_kernel<BF16, c64 in, NC=4>",
-                     "mfma_frac": flops / (ms_bf * 1e-3) / 1e12 / BF16_PEAK_TFLOPS},
-    }
-    if not args.no_rows:
-        out["rows"] = other_rows(plan, cfg, y, H_32, torch, args)
-        out["rows"]["front_end"] = front_end(plan, cfg, y, torch, lat_h2d, args)
-    if not args.no_workloads:
-        out["precision_workload"] = precision_workload(torch, args)
-        out["differentiation_workload"] = differentiation_workload(torch, args)
+    out, ctx = headline(torch, args)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(y, cfg, args.cpu_seconds)
-    plan.close()
+        out["cpu_baseline"] = cpu_baseline(ctx["plan"], ctx["cfg"], ctx["y"], ctx["q"],
+                                           ctx["sc"], ctx["H"], args.cpu_seconds, torch)
+    ctx["plan"].close()
+    ctx.clear()
+    torch.cuda.empty_cache()
+    if not args.no_workloads:
+        out["fp32_baseline_workload"] = fp32_baseline_workload(torch, args)
+        out["differentiation_workload"] = differentiation_workload(torch, args)
     print(json.dumps(out), flush=True)
 
 
