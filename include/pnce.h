@@ -306,6 +306,10 @@ pnce_status pnce_varlen_destroy(pnce_varlen_plan *vplan);
  * Yq: device codes of all frames (at their y_off); H: device complex64 (at
  * their h_off); the caller keeps the frames' regions disjoint. The launch
  * reads only plan-owned static tables, so it can be captured in a hipGraph.
+ * The device work list is allocated once, by pnce_varlen_create, at its
+ * largest possible size, and pnce_varlen_tune / pnce_varlen_set_tuning copy
+ * the new list over it in place: a graph captured before tuning keeps valid
+ * addresses and its replays run the current schedule.
  */
 pnce_status pnce_varlen_estimate(const pnce_varlen_plan *vplan, void *stream, const void *Yq,
                                  const float *scales, void *H);

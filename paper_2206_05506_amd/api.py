@@ -226,6 +226,10 @@ class Plan:
         copy = torch.cuda.Stream()
         bufs = [torch.empty((chunk, self.R, self.N + cp), dtype=torch.complex64, device=dev)
                 for _ in range(2)]
+        # The staging buffers come from the compute stream's pool: a block
+        # freed there may still be read by kernels queued on it, so the first
+        # copies wait for everything already enqueued on the compute stream.
+        copy.wait_stream(compute)
         copied = [torch.cuda.Event() for _ in range(2)]
         used = [torch.cuda.Event() for _ in range(2)]
         starts = list(range(0, F, chunk))

@@ -639,23 +639,34 @@ void schedule(const pnce_varlen_plan *v, std::vector<Unit> units, int n_wg, int 
   wg_start[(size_t)n_wg] = (int)tiles.size();
 }
 
+// Tiles of the longest possible work list: every unit at the narrowest width
+// (32 lags per wave, 128 per tile). The persistent workgroup count does not
+// depend on the widths either, so the device list is allocated once, at
+// create, and a rebuilt list is copied over it in place: a graph captured
+// before tuning replays the current schedule from the same addresses.
+size_t max_tiles(const pnce_varlen_plan *v) {
+  size_t n = 0;
+  for (const pnce::VFrame &fr : v->frames)
+    n += (size_t)((fr.R + 31) / 32) * (size_t)((fr.K + 127) / 128);
+  return n;
+}
+
 pnce_status upload_list(pnce_varlen_plan *v, const std::vector<pnce::VTile> &tiles,
                         const std::vector<int> &wg_start) {
   hipError_t e;
-  if (tiles.size() > v->cap_tiles) {
-    (void)hipFree(v->d_tiles);
-    v->d_tiles = nullptr;
-    e = hipMalloc((void **)&v->d_tiles, tiles.size() * sizeof(pnce::VTile));
+  if (!v->d_tiles) {
+    const size_t cap = max_tiles(v);
+    e = hipMalloc((void **)&v->d_tiles, cap * sizeof(pnce::VTile));
     if (e != hipSuccess) return fail(PNCE_E_NOMEM, "hipMalloc work list");
-    v->cap_tiles = tiles.size();
+    v->cap_tiles = cap;
   }
-  if (wg_start.size() > v->cap_wg) {
-    (void)hipFree(v->d_wg_start);
-    v->d_wg_start = nullptr;
+  if (!v->d_wg_start) {
     e = hipMalloc((void **)&v->d_wg_start, wg_start.size() * sizeof(int));
     if (e != hipSuccess) return fail(PNCE_E_NOMEM, "hipMalloc work list");
     v->cap_wg = wg_start.size();
   }
+  if (tiles.size() > v->cap_tiles || wg_start.size() != v->cap_wg)
+    return fail(PNCE_E_INVALID, "work list larger than its allocation");
   e = hipMemcpy(v->d_tiles, tiles.data(), tiles.size() * sizeof(pnce::VTile),
                 hipMemcpyHostToDevice);
   if (e == hipSuccess)

@@ -58,6 +58,24 @@ def device_frames(cfg, s):
     return y.contiguous(), h
 
 
+def perr(x, ref) -> float:
+    """Parity error of a float result against the oracle: per frame (leading
+    axis) the larger of the normwise relative error ||x - ref||_F / ||ref||_F
+    and the element-wise max|x - ref| / max|ref|, maximised over frames. One
+    tolerance bounds both, so neither a frame-wide drift nor a single wrong
+    element (a lag column, an antenna) can hide under the other."""
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    B = ref.shape[0]
+    d = np.abs(x - ref).reshape(B, -1)
+    a = np.abs(ref).reshape(B, -1)
+    nw = np.sqrt(np.sum(d ** 2, axis=1)) / np.where(np.any(a > 0, axis=1),
+                                                     np.sqrt(np.sum(a ** 2, axis=1)), 1.0)
+    mx = a.max(axis=1) if a.size else np.zeros(B)
+    ew = (d.max(axis=1) if d.size else np.zeros(B)) / np.where(mx == 0, 1.0, mx)
+    return float(max(np.max(nw), np.max(ew)))
+
+
 def rows_of(x, rows):
     """Gather (frame, antenna) rows of a [B, R, ...] array into [1, n, ...]."""
     return np.stack([x[b, r] for b, r in rows])[None]

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import synth
-from gpu_helpers import dev, frames, host
+from gpu_helpers import dev, frames, host, perr
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +41,7 @@ def test_backward_equals_oracle_adjoint(prec):
         H = correlate(Yd, p, prec)
         (gY,) = torch.autograd.grad(H, Yd, grad_outputs=dev(G))
         s = p.sequence()
-    assert oracle.relerr(host(gY), oracle.adjoint(G, s)) <= 1e-5
+    assert perr(host(gY), oracle.adjoint(G, s)) <= 1e-5
 
 
 def test_loss_gradient_equals_oracle():
@@ -56,7 +56,7 @@ def test_loss_gradient_equals_oracle():
         s = p.sequence()
     ref_loss, ref_g = oracle.loss_grad(y, s, x)
     assert abs(float(loss.detach()) - ref_loss) <= 1e-5 * ref_loss
-    assert oracle.relerr(host(g), ref_g) <= 1e-5
+    assert perr(host(g), ref_g) <= 1e-5
 
 
 def _per_frame_loss(y, x, p):
@@ -90,11 +90,11 @@ def test_differentiation_workload_refinement_trajectory():
         p.refine(yd, X, 5)                       # the library's own refinement
         lib5 = host(X[pick])
     its = oracle.refine(y[pick], s, cfg.K, 5)
-    err = oracle.relerr(lib5, its[5])
+    err = perr(lib5, its[5])
     print(f"library refinement, 5 steps: relerr {err:.2e}")
     assert err <= 1e-5
     for k in range(6):
-        err = oracle.relerr(got[k], its[k])
+        err = perr(got[k], its[k])
         ref_l = [oracle.loss_grad(y[pick][i:i + 1], s, its[k][i:i + 1])[0] for i in range(3)]
         print(f"step {k}: iterate relerr {err:.2e}, loss {traj[k]} vs {ref_l}")
         assert err <= 1e-5
@@ -115,6 +115,6 @@ def test_autograd_through_conjugate_views():
         (gY,) = torch.autograd.grad(H, Yd, grad_outputs=dev(G).conj())
         s = p.sequence()
         Hh = host(H)
-    assert oracle.relerr(Hh, oracle.correlate(np.conj(Y), s, T * L)) <= 1e-5
+    assert perr(Hh, oracle.correlate(np.conj(Y), s, T * L)) <= 1e-5
     # d/dY of conj(Y) P with incoming conj(G): conj(conj(G) P^T / N) = G P^T / N
-    assert oracle.relerr(host(gY), oracle.adjoint(G, s)) <= 1e-5
+    assert perr(host(gY), oracle.adjoint(G, s)) <= 1e-5

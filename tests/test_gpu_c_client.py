@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import bf16_round
+from gpu_helpers import bf16_round, perr
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +39,7 @@ def test_c_client_estimate(tmp_path, prec, spacing, fb):
     s = oracle.mseq_mask(10, fb) if fb else oracle.mseq(10)
     lag = oracle.lags(N, T, L, "eq8" if spacing else "contiguous")
     x = bf16_round(y) if prec == 2 else y.astype(np.complex128)
-    assert oracle.relerr(H, oracle.correlate(x, s, T * L, lag)) <= 1e-5
+    assert perr(H, oracle.correlate(x, s, T * L, lag)) <= 1e-5
 
 
 def test_c_client_error_statuses(tmp_path):
@@ -61,7 +61,7 @@ def test_c_client_adjoint(tmp_path):
     p, fout = _run([N, T, L, R, B, 1, 0, 0], tmp_path, G, "adjoint")
     assert p.returncode == 0, p.stderr
     A = np.fromfile(fout, dtype=np.complex64).reshape(B, R, N)
-    assert oracle.relerr(A, oracle.adjoint(G, oracle.mseq(8))) <= 1e-5
+    assert perr(A, oracle.adjoint(G, oracle.mseq(8))) <= 1e-5
 
 
 @pytest.mark.parametrize("fmt,name", [(1, "bf16"), (2, "f16"), (3, "e4m3")])
@@ -73,7 +73,7 @@ def test_c_client_pack_and_packed_estimate(tmp_path, fmt, name):
     H = np.fromfile(fout, dtype=np.complex64).reshape(B, R, T * L)
     codes, scales = oracle.quantize(y, name)
     x = oracle.dequantize(codes, scales, name, N)
-    assert oracle.relerr(H, oracle.correlate(x, oracle.mseq(8), T * L)) <= 1e-5
+    assert perr(H, oracle.correlate(x, oracle.mseq(8), T * L)) <= 1e-5
 
 
 def test_c_client_refine(tmp_path):
@@ -83,4 +83,4 @@ def test_c_client_refine(tmp_path):
     assert p.returncode == 0, p.stderr
     X = np.fromfile(fout, dtype=np.complex64).reshape(B, R, T * L)
     its = oracle.refine(y.astype(np.complex128), oracle.mseq(8), T * L, 3)
-    assert oracle.relerr(X, its[3]) <= 1e-5
+    assert perr(X, its[3]) <= 1e-5

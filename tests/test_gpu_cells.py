@@ -15,7 +15,7 @@ import torch
 
 import oracle
 import synth
-from gpu_helpers import bf16_round, dev, host
+from gpu_helpers import bf16_round, dev, host, perr
 
 pytestmark = pytest.mark.gpu
 
@@ -104,7 +104,7 @@ def test_estimate_parity(shape, prec):
     assert np.array_equal(lag, oracle.lags(N, T, L, "eq8"))
     x = bf16_round(y) if prec == "bf16" else y.astype(np.complex128)
     ref = oracle.correlate(x, s, T * L, lag)
-    err = oracle.relerr(H, ref)
+    err = perr(H, ref)
     print(f"eq8 estimate {prec} N={N} T={T} L={L}: relerr {err:.3e}")
     assert err <= (TOL_F64ACC if prec == "f64acc" else TOL32)
 
@@ -116,7 +116,7 @@ def test_estimate_f64_parity(shape):
     with _plan(N, T, L, R) as p:
         H = host(p.estimate(dev(y, torch.complex128), "f64"))
         ref = oracle.correlate(y, p.sequence(), T * L, oracle.lags(N, T, L, "eq8"))
-    assert oracle.relerr(H, ref) <= TOL64
+    assert perr(H, ref) <= TOL64
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=IDS)
@@ -136,10 +136,10 @@ def test_adjoint_parity(shape, prec):
     g = bf16_round(G) if prec == "bf16" else G.astype(np.complex128)
     ref = oracle.adjoint(g, s, lag)
     tol = TOL_F64ACC if prec == "f64acc" else TOL32
-    err = oracle.relerr(A, ref)
+    err = perr(A, ref)
     print(f"eq8 adjoint {prec} N={N} T={T} L={L}: relerr {err:.3e}")
     assert err <= tol
-    assert oracle.relerr(A2, C.astype(np.complex128) - N * ref) <= tol
+    assert perr(A2, C.astype(np.complex128) - N * ref) <= tol
 
 
 def test_adjoint_f64_and_dot_identity():
@@ -152,7 +152,7 @@ def test_adjoint_f64_and_dot_identity():
         A = host(p.adjoint(dev(G, torch.complex128), "f64"))
         H = host(p.estimate(dev(Y, torch.complex128), "f64"))
         s = p.sequence()
-    assert oracle.relerr(A, oracle.adjoint(G, s, lag)) <= TOL64
+    assert perr(A, oracle.adjoint(G, s, lag)) <= TOL64
     assert abs(np.vdot(G, H) - np.vdot(A, Y)) <= 1e-12 * abs(np.vdot(G, H))
 
 
@@ -168,7 +168,7 @@ def test_estimate_packed_parity(shape, fmt):
         qh, sch = host(q), host(sc)
     x = oracle.dequantize(qh.view(np.uint8 if fmt == "e4m3" else np.uint16), sch, fmt, N)
     ref = oracle.correlate(x, s, T * L, oracle.lags(N, T, L, "eq8"))
-    assert oracle.relerr(H, ref) <= TOL32
+    assert perr(H, ref) <= TOL32
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=IDS)
@@ -186,8 +186,8 @@ def test_estimate_ls_parity(shape, prec):
         Hh = host(H)
     x = bf16_round(y) if prec == "bf16" else y.astype(np.complex128)
     ref = oracle.ls_closed_form(oracle.correlate(x, s, T * L, oracle.lags(N, T, L, "eq8")), N)
-    assert oracle.relerr(X, ref) <= TOL32
-    assert oracle.relerr(Hh, ref) <= TOL32
+    assert perr(X, ref) <= TOL32
+    assert perr(Hh, ref) <= TOL32
 
 
 @pytest.mark.parametrize("shape", [(127, 4, 16, 8, 2), (1023, 16, 32, 16, 2), (255, 3, 50, 8, 1)],
@@ -206,9 +206,9 @@ def test_noiseless_eq8_channels_are_recovered(shape):
         X = host(p.estimate_ls(dev(y.astype(np.complex64)), "f32s"))
         H = host(p.estimate(dev(y.astype(np.complex64)), "f32s"))
     hs = h.reshape(B, R, T * L)
-    assert oracle.relerr(X, hs) <= 1e-5
+    assert perr(X, hs) <= 1e-5
     expect = hs + (hs - hs.sum(axis=-1, keepdims=True)) / N
-    assert oracle.relerr(H, expect) <= 1e-5
+    assert perr(H, expect) <= 1e-5
 
 
 @pytest.mark.parametrize("shape", [(127, 4, 16, 16, 1), (1023, 16, 32, 64, 2), (255, 7, 36, 8, 2)],
@@ -229,7 +229,7 @@ def test_refine_tracks_fp64_iterates(shape):
         for k in range(6):
             X = p.estimate(yd, "f32s")
             p.refine(yd, X, k)
-            err = oracle.relerr(host(X), its[k])
+            err = perr(host(X), its[k])
             print(f"eq8 refine k={k}: relerr vs FP64 iterate {err:.3e}")
             assert err <= TOL32
 
@@ -243,7 +243,7 @@ def test_estimate_cp_parity(prec):
         s = p.sequence()
     y = raw[:, :, cp:]
     x = bf16_round(y) if prec == "bf16" else y.astype(np.complex128)
-    assert oracle.relerr(H, oracle.correlate(x, s, T * L, oracle.lags(N, T, L, "eq8"))) <= TOL32
+    assert perr(H, oracle.correlate(x, s, T * L, oracle.lags(N, T, L, "eq8"))) <= TOL32
 
 
 def test_other_cell_interference_matches_oracle():
@@ -267,8 +267,8 @@ def test_other_cell_interference_matches_oracle():
     with _plan(N, T, L, R) as pa, _plan(N, T, L, R, feedback=mb) as pb:
         Ha = host(pa.estimate(dev(y), "f32s"))
         Hb = host(pb.estimate_ls(dev(y), "f32s"))
-    assert oracle.relerr(Ha, oracle.correlate(y, sa, T * L, lag)) <= TOL32
-    assert oracle.relerr(Hb, h.reshape(B, R, T * L)) <= 1e-5
+    assert perr(Ha, oracle.correlate(y, sa, T * L, lag)) <= TOL32
+    assert perr(Hb, h.reshape(B, R, T * L)) <= 1e-5
 
 
 def test_autograd_follows_eq8_lags():
@@ -285,10 +285,10 @@ def test_autograd_follows_eq8_lags():
         loss = residual_loss(dev(Y), xd, p, "f32s")
         (g,) = torch.autograd.grad(loss, xd)
         s = p.sequence()
-    assert oracle.relerr(host(gY), oracle.adjoint(G, s, lag)) <= TOL32
+    assert perr(host(gY), oracle.adjoint(G, s, lag)) <= TOL32
     ref_loss, ref_g = oracle.loss_grad(Y, s, x, lag)
     assert abs(float(loss.detach()) - ref_loss) <= 1e-5 * ref_loss
-    assert oracle.relerr(host(g), ref_g) <= TOL32
+    assert perr(host(g), ref_g) <= TOL32
 
 
 def test_fp32_baseline_shape_eq8_full_batch_sampled():
@@ -305,6 +305,6 @@ def test_fp32_baseline_shape_eq8_full_batch_sampled():
         Xs = host(p.estimate_ls(yd, "f32s"))
         s = p.sequence()
     pick = [0, 101, 255]
-    assert oracle.relerr(Hb[pick], oracle.correlate(bf16_round(y[pick]), s, T * L, lag)) <= TOL32
+    assert perr(Hb[pick], oracle.correlate(bf16_round(y[pick]), s, T * L, lag)) <= TOL32
     ref = oracle.ls_closed_form(oracle.correlate(y[pick], s, T * L, lag), N)
-    assert oracle.relerr(Xs[pick], ref) <= TOL32
+    assert perr(Xs[pick], ref) <= TOL32

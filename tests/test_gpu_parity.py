@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import synth
-from gpu_helpers import bf16_round, dev, frames, host
+from gpu_helpers import bf16_round, dev, frames, host, perr
 
 pytestmark = pytest.mark.gpu
 
@@ -69,7 +69,7 @@ def test_estimate_parity(shape, prec):
         torch.cuda.synchronize()
     x = bf16_round(y) if prec == "bf16" else y.astype(np.complex128)
     ref = oracle.correlate(x, s, K)
-    err = oracle.relerr(H, ref)
+    err = perr(H, ref)
     print(f"estimate {prec} N={N} K={K} R={R} B={B}: relerr {err:.3e}")
     assert err <= (TOL_F64ACC if prec == "f64acc" else TOL32)
 
@@ -82,7 +82,7 @@ def test_estimate_f64_parity(shape):
     with _plan(N, T, L, R) as p:
         H = host(p.estimate(dev(y, torch.complex128), "f64"))
         ref = oracle.correlate(y, p.sequence(), T * L)
-    assert oracle.relerr(H, ref) <= TOL64
+    assert perr(H, ref) <= TOL64
 
 
 def test_estimate_plain_workload_structured():
@@ -94,10 +94,10 @@ def test_estimate_plain_workload_structured():
         H = host(p.estimate(dev(y), "f32s"))
         y0, _ = oracle.received(s, h, np.zeros_like(y), np.array([300.0]))
         H0 = host(p.estimate(dev(y0.astype(np.complex64)), "f32"))
-    assert oracle.relerr(H, oracle.correlate(y, s, cfg.K)) <= TOL32
+    assert perr(H, oracle.correlate(y, s, cfg.K)) <= TOL32
     hs = h.reshape(1, cfg.R, cfg.K)
     expect = hs + (hs - hs.sum(axis=-1, keepdims=True)) / cfg.N
-    assert oracle.relerr(H0, expect) <= TOL32
+    assert perr(H0, expect) <= TOL32
 
 
 def test_estimate_scales_and_beta():
@@ -110,7 +110,7 @@ def test_estimate_scales_and_beta():
         p.estimate(dev(y), "f32s", out=Hd, scales=torch.from_numpy(sc).cuda(), beta=0.25)
         H = host(Hd)
         ref = sc[:, None, None] * oracle.correlate(y, p.sequence(), T * L) + 0.25 * H0
-    assert oracle.relerr(H, ref) <= TOL32
+    assert perr(H, ref) <= TOL32
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
@@ -126,9 +126,9 @@ def test_adjoint_parity(shape, prec):
         A2 = host(p.adjoint(dev(G), prec, alpha=-1.0, beta=1.0, C=dev(C)))
     ref = oracle.adjoint(G, s)
     tol = TOL_F64ACC if prec == "f64acc" else TOL32
-    assert oracle.relerr(A, ref) <= tol
+    assert perr(A, ref) <= tol
     ref2 = C.astype(np.complex128) - N * ref
-    assert oracle.relerr(A2, ref2) <= tol
+    assert perr(A2, ref2) <= tol
 
 
 def test_adjoint_f64_and_dot_identity():
@@ -138,7 +138,7 @@ def test_adjoint_f64_and_dot_identity():
     with _plan(N, T, L, R) as p:
         A = host(p.adjoint(dev(G, torch.complex128), "f64"))
         H = host(p.estimate(dev(Y, torch.complex128), "f64"))
-        assert oracle.relerr(A, oracle.adjoint(G, p.sequence())) <= TOL64
+        assert perr(A, oracle.adjoint(G, p.sequence())) <= TOL64
     assert abs(np.vdot(G, H) - np.vdot(A, Y)) < 1e-10 * abs(np.vdot(G, H))
 
 
@@ -193,7 +193,7 @@ def test_estimate_packed_parity(shape, fmt):
         qh, sch = host(q), host(sc)
     x = oracle.dequantize(qh.view(np.uint8 if fmt == "e4m3" else np.uint16), sch, fmt, N)
     ref = oracle.correlate(x, s, T * L)
-    assert oracle.relerr(H, ref) <= TOL32
+    assert perr(H, ref) <= TOL32
 
 
 @pytest.mark.parametrize("shape", [(127, 4, 16, 16, 1), (1023, 16, 32, 64, 2), (255, 4, 16, 8, 2)],
@@ -210,7 +210,7 @@ def test_refine_tracks_fp64_iterates(shape):
         for k in range(6):
             X = p.estimate(yd, "f32s")
             p.refine(yd, X, k)
-            err = oracle.relerr(host(X), its[k])
+            err = perr(host(X), its[k])
             print(f"refine k={k}: relerr vs FP64 iterate {err:.3e}")
             assert err <= TOL32
 
@@ -227,10 +227,10 @@ def test_fp32_baseline_full_batch_sampled():
         Hf = host(p.estimate(yd, "f32"))
     pick = [0, 1, 97, 128, 255]
     ref = oracle.correlate(y[pick], s, cfg.K)
-    assert oracle.relerr(Hs[pick], ref) <= TOL32
-    assert oracle.relerr(Hf[pick], ref) <= TOL32
+    assert perr(Hs[pick], ref) <= TOL32
+    assert perr(Hf[pick], ref) <= TOL32
     refb = oracle.correlate(bf16_round(y[pick]), s, cfg.K)
-    assert oracle.relerr(Hb[pick], refb) <= TOL32
+    assert perr(Hb[pick], refb) <= TOL32
 
 
 def test_tile_width_does_not_change_results():
@@ -281,13 +281,13 @@ def test_longest_sequences(d):
         qh, sch = host(q), host(sc)
     ref = oracle.correlate(y, s, K)
     for prec in ("f32", "f32s"):
-        assert oracle.relerr(H[prec], ref) <= TOL32
-    assert oracle.relerr(H["f64acc"], ref) <= TOL_F64ACC
-    assert oracle.relerr(H["bf16"], oracle.correlate(bf16_round(y), s, K)) <= TOL32
-    assert oracle.relerr(X, oracle.ls_closed_form(ref, N)) <= TOL32
-    assert oracle.relerr(A, oracle.adjoint(G, s)) <= TOL32
+        assert perr(H[prec], ref) <= TOL32
+    assert perr(H["f64acc"], ref) <= TOL_F64ACC
+    assert perr(H["bf16"], oracle.correlate(bf16_round(y), s, K)) <= TOL32
+    assert perr(X, oracle.ls_closed_form(ref, N)) <= TOL32
+    assert perr(A, oracle.adjoint(G, s)) <= TOL32
     xe = oracle.dequantize(qh.view(np.uint8), sch, "e4m3", N)
-    assert oracle.relerr(He, oracle.correlate(xe, s, K)) <= TOL32
+    assert perr(He, oracle.correlate(xe, s, K)) <= TOL32
 
 
 def test_longest_sequence_with_lag_alias():
@@ -302,8 +302,8 @@ def test_longest_sequence_with_lag_alias():
         H = host(p.estimate(dev(y), "f32s"))
         A = host(p.adjoint(dev(G), "f32s"))
     assert np.array_equal(H[..., N:], H[..., :T * L - N])
-    assert oracle.relerr(H[..., :4096], oracle.correlate(y, s, 4096)) <= TOL32
-    assert oracle.relerr(A, oracle.adjoint(G, s)) <= TOL32
+    assert perr(H[..., :4096], oracle.correlate(y, s, 4096)) <= TOL32
+    assert perr(A, oracle.adjoint(G, s)) <= TOL32
 
 
 def test_most_antennas():
@@ -313,8 +313,8 @@ def test_most_antennas():
     with _plan(N, T, L, R) as p:
         s = p.sequence()
         H = {prec: host(p.estimate(dev(y), prec)) for prec in ("f32s", "bf16")}
-    assert oracle.relerr(H["f32s"], oracle.correlate(y, s, T * L)) <= TOL32
-    assert oracle.relerr(H["bf16"], oracle.correlate(bf16_round(y), s, T * L)) <= TOL32
+    assert perr(H["f32s"], oracle.correlate(y, s, T * L)) <= TOL32
+    assert perr(H["bf16"], oracle.correlate(bf16_round(y), s, T * L)) <= TOL32
 
 
 def test_graph_replays_match_eager():
@@ -414,11 +414,11 @@ def test_random_shapes(case):
         assert np.array_equal(s, oracle.mseq_mask(oracle.degree_of(N), fb))
     assert np.array_equal(lag, oracle.lags(N, T, L, "eq8" if spacing == "eq8" else "contiguous"))
     ref = oracle.correlate(y, s, K, lag)
-    assert oracle.relerr(Hs, ref) <= TOL32
-    assert oracle.relerr(Hb, oracle.correlate(bf16_round(y), s, K, lag)) <= TOL32
-    assert oracle.relerr(A, oracle.adjoint(G, s, lag)) <= TOL32
+    assert perr(Hs, ref) <= TOL32
+    assert perr(Hb, oracle.correlate(bf16_round(y), s, K, lag)) <= TOL32
+    assert perr(A, oracle.adjoint(G, s, lag)) <= TOL32
     if X is not None:
-        assert oracle.relerr(X, oracle.ls_closed_form(ref, N)) <= TOL32
+        assert perr(X, oracle.ls_closed_form(ref, N)) <= TOL32
 
 
 def test_one_plan_on_two_streams_concurrently():
@@ -457,7 +457,7 @@ def test_lazy_conjugate_views_are_refused():
             p.estimate(y.conj(), "f32s")
         H = host(p.estimate(y.conj().resolve_conj(), "f32s"))
         ref = oracle.correlate(np.conj(host(y)), p.sequence(), T * L)
-    assert oracle.relerr(H, ref) <= TOL32
+    assert perr(H, ref) <= TOL32
 
 
 def test_empty_batch_is_a_no_op():

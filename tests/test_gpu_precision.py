@@ -15,7 +15,7 @@ import torch
 
 import oracle
 import synth
-from gpu_helpers import device_frames, host
+from gpu_helpers import device_frames, host, perr
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +45,7 @@ def test_precision_study_full_workload():
         its = oracle.refine(yr, s, cfg.K, 5)
 
         H32 = p.estimate(y, "f32s")
-        e32 = oracle.relerr(_rows(H32), its[0])
+        e32 = perr(_rows(H32), its[0])
         print(f"f32s correlation relerr {e32:.2e}")
         assert e32 <= 1e-5
 
@@ -60,7 +60,7 @@ def test_precision_study_full_workload():
             for k in range(6):
                 X = X0.clone()
                 p.refine(y, X, k, work=work)
-                errs.append(oracle.relerr(_rows(X), its[k]))
+                errs.append(perr(_rows(X), its[k]))
             report[fmt] = errs
             del q, X0, X
         torch.cuda.synchronize()

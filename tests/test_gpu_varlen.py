@@ -13,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from gpu_helpers import host
+from gpu_helpers import host, perr
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,7 @@ def _oracle_frame(vp, Yq_host, sc_host, H, f):
     x = oracle.dequantize(c, sc_host[f:f + 1], "bf16", N)
     ref = oracle.correlate(x, oracle.mseq(oracle.degree_of(N)), T * L)
     got = host(vp.frame_view(H, f)).reshape(1, R, T * L)
-    return oracle.relerr(got, ref)
+    return perr(got, ref)
 
 
 def test_varlen_edge_shapes():
@@ -74,9 +74,14 @@ def test_varlen_batching_workload():
         torch.cuda.synchronize()
         assert torch.equal(H, He)
         Yh, sh = host(Yq), host(sc)
-        pick = [0, 1, 777, 2048, 4095]
+        # one frame of every (N, T*L) class, plus the batch's first and last
+        first = {}
+        for f, (R, N, T, L) in enumerate(shapes):
+            first.setdefault((N, T * L), f)
+        pick = sorted(set(first.values()) | {0, len(shapes) - 1})
+        print(f"{len(first)} (N, T*L) classes, oracle-checked frames {pick}")
         for f in pick:
-            assert _oracle_frame(vp, Yh, sh, H, f) <= 1e-5
+            assert _oracle_frame(vp, Yh, sh, H, f) <= 1e-5, (f, shapes[f])
 
         # hipGraph: capture the persistent launch, replay with eager work between
         Hg = torch.empty_like(H)
@@ -105,7 +110,46 @@ def test_varlen_batching_workload():
         torch.cuda.synchronize()
         assert torch.equal(H2, He2)
         for f in pick:
-            assert _oracle_frame(vp, Yh, sh, H2, f) <= 1e-5
+            assert _oracle_frame(vp, Yh, sh, H2, f) <= 1e-5, (f, shapes[f])
         st = vp.stats()
         print("tuned:", table, st)
         assert st["tiles"] > 0 and st["workgroups"] > 0
+
+
+def test_graph_captured_before_tuning_replays_new_schedule():
+    """A graph captured before set_tuning keeps valid work-list addresses:
+    after every class is moved to the narrowest column width (the longest
+    work list) and back to the widest, replays equal the per-frame launches
+    of the current schedule and match the oracle."""
+    from paper_2206_05506_amd import VarlenPlan
+    shapes = _shapes(96, seed=7)
+    with VarlenPlan(shapes) as vp:
+        Yq, sc = _inputs(vp, 5)
+        Hg = torch.empty((vp.n_out,), dtype=torch.complex64, device="cuda")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            vp.estimate(Yq, sc, out=Hg)
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            vp.estimate(Yq, sc, out=Hg)
+        torch.cuda.synchronize()
+        start = vp.tuning()
+        tiles0 = vp.stats()["tiles"]
+        Yh, sh = host(Yq), host(sc)
+        for nc in (1, 4, None):
+            table = start if nc is None else [(N, K, nc, us) for N, K, _, us in start]
+            vp.set_tuning(table)
+            if nc == 1:
+                assert vp.stats()["tiles"] > tiles0
+            He = vp.estimate_each(Yq, sc)
+            for _ in range(2):
+                Hg.zero_()
+                torch.cuda.synchronize()
+                graph.replay()
+                torch.cuda.synchronize()
+                assert torch.equal(Hg, He), nc
+            for f in (0, len(shapes) // 2, len(shapes) - 1):
+                assert _oracle_frame(vp, Yh, sh, Hg, f) <= 1e-5, (nc, f, shapes[f])
+        del graph
