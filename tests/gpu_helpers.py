@@ -76,6 +76,14 @@ def perr(x, ref) -> float:
     return float(max(np.max(nw), np.max(ew)))
 
 
+def tol_sum(tol, n_terms):
+    """Parity bound for FP32 sums of n_terms terms: tol up to 4096 terms (every
+    reduction of the workloads: sequences up to 4095, lag stacks up to 4096),
+    scaled by sqrt(n_terms / 4096) beyond, as the rounding error of an FP32
+    sum of random-sign terms grows like the square root of their number."""
+    return tol * max(1.0, (n_terms / 4096.0) ** 0.5)
+
+
 def rows_of(x, rows):
     """Gather (frame, antenna) rows of a [B, R, ...] array into [1, n, ...]."""
     return np.stack([x[b, r] for b, r in rows])[None]

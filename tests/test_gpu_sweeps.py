@@ -1,9 +1,52 @@
-"""The accuracy-sweep tool on a small number of realisations: errors fall
-with SNR, the plain correlator flattens into the -1/M floor at high SNR
-(Section IV) and the least-squares rows remove it."""
+"""The accuracy sweeps of Section IV (Eq. 12 MAE, Figs. 4 and 5).
+
+test_sweep_point_matches_oracle: one Fig. 4 point and one Fig. 5 point on
+frames built by the oracle's receive model from sparse-tap channels; every
+method's MAE from the library equals the MAE of the oracle's estimates of the
+same frames (FP64 correlation of the values each path consumes, then the
+closed-form least-squares rows).
+test_sweep_trends: the sweep tool itself on a small number of realisations:
+errors fall with SNR, the plain correlator flattens into the -1/M floor at
+high SNR and the least-squares rows remove it."""
+import numpy as np
 import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import bf16_round, dev
 
 pytestmark = pytest.mark.gpu
+
+# (M, N_batch, L, L_nz, SNR dB, realisations, seed): Fig. 4 and Fig. 5 points
+POINTS = [(511, 4, 64, 64, 10.0, 3, 31), (2047, 4, 128, 16, 20.0, 2, 32)]
+
+
+@pytest.mark.parametrize("M,nb,L,lnz,snr,iters,seed", POINTS)
+def test_sweep_point_matches_oracle(M, nb, L, lnz, snr, iters, seed):
+    from paper_2206_05506_amd import Plan, sweeps
+    F = iters * (sweeps.N_T // nb)
+    R = sweeps.N_R
+    K = nb * L
+    h = synth.sparse_taps((F, R, nb), L, lnz, sweeps.N_T, seed)
+    w = synth.gaussian((F, R, M), seed + 1)
+    s = oracle.mseq(oracle.degree_of(M))
+    y, _ = oracle.received(s, h, w, np.full(F, snr))
+    y = y.astype(np.complex64)
+    hk = h.reshape(F, R, K)
+    print(f"sweep point M={M} Nb={nb} L={L} Lnz={lnz} SNR={snr} frames={F}", flush=True)
+    with Plan(M, nb, L, R) as plan:
+        assert np.array_equal(plan.sequence(), s)
+        got = sweeps.mae_point(plan, dev(y), torch.from_numpy(hk).cuda())
+    ref = {"fp32": oracle.correlate(y, s, K), "bf16": oracle.correlate(bf16_round(y), s, K)}
+    for fmt in ("f16", "e4m3"):
+        q, sc = oracle.quantize(y, fmt)
+        ref[fmt] = oracle.correlate(oracle.dequantize(q, sc, fmt, M), s, K)
+    ref["fp32_ls"] = oracle.ls_closed_form(ref["fp32"], M)
+    ref["bf16_ls"] = oracle.ls_closed_form(ref["bf16"], M)
+    for m in sweeps.METHODS:
+        want = oracle.mae(ref[m], hk)
+        assert abs(got[m] - want) <= 1e-5 * want, (m, got[m], want)
 
 
 def test_sweep_trends():

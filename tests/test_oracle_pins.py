@@ -362,6 +362,36 @@ def test_synth_is_deterministic_and_normalised():
     assert np.all(shp[:, 2] * shp[:, 3] <= (1 << shp[:, 1]) - 1)
 
 
+
+@pytest.mark.parametrize("L,lnz", [(64, 64), (128, 16), (128, 1), (32, 5)])
+def test_sparse_taps_follow_the_section_ii_model(L, lnz):
+    """Section II's channel: lnz non-zero taps at distinct positions of an
+    L-tap CIR, each CN(0, p), p = 1 / (N_t sqrt(lnz)), positions uniform."""
+    n_tx = 16
+    shape = (40, 16, 4)
+    h = synth.sparse_taps(shape, L, lnz, n_tx, seed=5)
+    assert h.shape == shape + (L,) and h.dtype == np.complex128
+    assert np.array_equal(h, synth.sparse_taps(shape, L, lnz, n_tx, seed=5))
+    nz = h.reshape(-1, L) != 0
+    assert np.all(nz.sum(axis=1) == lnz)          # exactly lnz distinct taps per CIR
+    v = h.reshape(-1, L)[nz]
+    p = 1.0 / (n_tx * np.sqrt(lnz))
+    n = v.size
+    # E|h|^2 = p, E re^2 = E im^2 = p/2, E re*im = 0; |h|^2/p is Exp(1), so
+    # its sample mean has standard deviation 1/sqrt(n): 6 sigma bounds
+    assert abs(np.mean(np.abs(v) ** 2) / p - 1.0) < 6.0 / np.sqrt(n)
+    assert abs(np.mean(v.real ** 2) / (p / 2) - 1.0) < 6.0 * np.sqrt(2.0 / n)
+    assert abs(np.mean(v.imag ** 2) / (p / 2) - 1.0) < 6.0 * np.sqrt(2.0 / n)
+    assert abs(np.mean(v.real * v.imag)) / (p / 2) < 6.0 / np.sqrt(n)
+    # every position is hit with probability lnz / L
+    if lnz < L:
+        cirs = nz.shape[0]
+        hits = nz.sum(axis=0)
+        q = lnz / L
+        sd = np.sqrt(cirs * q * (1 - q))
+        assert np.all(np.abs(hits - cirs * q) < 6.0 * sd)
+
+
 # ------------------------------- per-cell sequences and Eq. 8 lag spacing
 def _totient(n):
     r, m, p = n, n, 2
