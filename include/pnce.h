@@ -224,6 +224,27 @@ pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y,
                         void *X, void *work, int batch, int steps);
 
 /*
+ * pnce_refine for callers that cannot allocate device memory (code under
+ * stream capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and steps, with the residual kept in a fixed array of
+ * PNCE_NOALLOC_SCRATCH_MIB MiB of device memory that the library holds on
+ * each GPU it runs on until the process ends; no memory is allocated or
+ * freed by the call. Frames are refined in groups of
+ * floor(PNCE_NOALLOC_SCRATCH_MIB MiB / (R*N*8)) (each frame's result equals
+ * that of pnce_refine up to FP32 rounding of the kernels' launch shape).
+ * y, X: as for pnce_refine (device memory owned by the caller).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (on different streams, or from several threads) race and give
+ * wrong results; calls on one stream are ordered and safe. The array keeps
+ * the last call's residuals; nothing in it needs to start at zero.
+ * Errors: PNCE_E_UNSUPPORTED when one frame's residual (R*N*8 bytes) exceeds
+ * the array; otherwise as for pnce_refine.
+ */
+#define PNCE_NOALLOC_SCRATCH_MIB 64
+pnce_status pnce_refine_noalloc(const pnce_plan *plan, void *stream, const void *y,
+                                void *X, int batch, int steps);
+
+/*
  * Raw received blocks (Section II-A, Section III-B): each antenna row holds
  * the cyclic prefix of cp samples followed by the N samples of the sequence
  * period; the prefix is removed by addressing alone (rows are cp + N

@@ -36,7 +36,7 @@ PNCE_FMT_E4M3 = 3
 SYMBOLS = ("pnce_create", "pnce_create_ex", "pnce_destroy", "pnce_get_sequence",
            "pnce_get_lags", "pnce_get_feedback", "pnce_get_shape",
            "pnce_estimate", "pnce_pack", "pnce_estimate_packed", "pnce_adjoint",
-           "pnce_refine", "pnce_debias", "pnce_estimate_ls", "pnce_estimate_cp", "pnce_pack_cp",
+           "pnce_refine", "pnce_refine_noalloc", "pnce_debias", "pnce_estimate_ls", "pnce_estimate_cp", "pnce_pack_cp",
            "pnce_varlen_create", "pnce_varlen_destroy", "pnce_varlen_estimate",
            "pnce_varlen_estimate_each", "pnce_varlen_tune", "pnce_varlen_get_tuning",
            "pnce_varlen_set_tuning", "pnce_varlen_stats", "pnce_status_string",
@@ -77,6 +77,7 @@ def _load() -> ctypes.CDLL:
         "pnce_estimate_packed": ([_P, _P, _P, _P, _P, _I, _I, _D], _I),
         "pnce_adjoint": ([_P, _P, _P, _P, _P, _I, _I, _D, _D], _I),
         "pnce_refine": ([_P, _P, _P, _P, _P, _I, _I], _I),
+        "pnce_refine_noalloc": ([_P, _P, _P, _P, _I, _I], _I),
         "pnce_debias": ([_P, _P, _P, _I], _I),
         "pnce_estimate_ls": ([_P, _P, _P, _P, _I, _I, _P], _I),
         "pnce_estimate_cp": ([_P, _P, _P, _I, _P, _I, _I, _P], _I),
@@ -175,6 +176,11 @@ def pnce_adjoint(plan, stream, G, A, C, batch, precision, alpha, beta) -> int:
 
 def pnce_refine(plan, stream, y, X, work, batch, steps) -> int:
     return check(lib.pnce_refine(plan, stream, y, X, work, batch, steps), "pnce_refine")
+
+
+def pnce_refine_noalloc(plan, stream, y, X, batch, steps) -> int:
+    return check(lib.pnce_refine_noalloc(plan, stream, y, X, batch, steps),
+                 "pnce_refine_noalloc")
 
 
 def pnce_debias(plan, stream, H, batch) -> int:

@@ -293,6 +293,15 @@ class Plan:
         _lib.pnce_refine(self.handle, _stream(), _ptr(y), _ptr(X), _ptr(work), B, steps)
         return X
 
+    def refine_noalloc(self, y: torch.Tensor, X: torch.Tensor, steps: int) -> torch.Tensor:
+        """In place, as refine, with the residual in the library's fixed
+        device array (no allocation; calls overlapping on one GPU race)."""
+        B = y.shape[0]
+        _need(y, (B, self.R, self.N), torch.complex64, "y")
+        _need(X, (B, self.R, self.K), torch.complex64, "X")
+        _lib.pnce_refine_noalloc(self.handle, _stream(), _ptr(y), _ptr(X), B, steps)
+        return X
+
 
 class VarlenPlan:
     """Uneven batch: frames with their own (R, N, T, L) in one buffer of

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <string>
@@ -526,6 +527,55 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G, voi
                  alpha, beta);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The refinement loop on `batch` frames with the residual in `work`.
+pnce_status refine_steps(const pnce_plan *plan, hipStream_t s, const void *y, void *X,
+                         void *work, int batch, int steps) {
+  for (int j = 0; j < steps; ++j) {
+    // r = y - P x   (P x = sum_k x[k] s[(n-k) mod N]: adjoint stream, alpha -1)
+    const int prec = (j + 1 < steps) ? PNCE_PREC_F32S : PNCE_PREC_F64ACC;
+    if (pnce_status st = run_adj(plan, s, prec, X, work, y, batch, -1.0, 1.0)) return st;
+    // x = x + P^T r / N
+    if (pnce_status st = run_fwd(plan, s, PNCE_PREC_F32S, pnce::IN_C64, work, plan->N, plan->N,
+                                 X, X, nullptr, batch, 1.0 / plan->N, 1.0))
+      return st;
+  }
+  return PNCE_OK;
+}
+
+// Residual storage of pnce_refine_noalloc: a fixed array in device memory,
+// one copy per GPU, held until the process ends. Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): each device's address comes from hipGetSymbolAddress, resolved
+// once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)PNCE_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // per device ordinal, null until resolved
+
+pnce_status scratch_of_device(int device, void **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0) return fail(PNCE_E_INVALID, "bad device ordinal");
+  if ((size_t)device >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+  if (!g_scratch_ptr[(size_t)device]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(PNCE_E_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+    g_scratch_ptr[(size_t)device] = p;
+  }
+  *out = g_scratch_ptr[(size_t)device];
+  return PNCE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void *X,
                         void *work, int batch, int steps) {
   if (pnce_status st = check_plan(plan)) return st;
@@ -537,14 +587,36 @@ pnce_status pnce_refine(const pnce_plan *plan, void *stream, const void *y, void
   if (pnce_status st = check_align(y, 8, "y")) return st;
   if (pnce_status st = check_align(X, 8, "X")) return st;
   if (pnce_status st = check_align(work, 8, "work")) return st;
-  hipStream_t s = (hipStream_t)stream;
-  for (int j = 0; j < steps; ++j) {
-    // r = y - P x   (P x = sum_k x[k] s[(n-k) mod N]: adjoint stream, alpha -1)
-    const int prec = (j + 1 < steps) ? PNCE_PREC_F32S : PNCE_PREC_F64ACC;
-    if (pnce_status st = run_adj(plan, s, prec, X, work, y, batch, -1.0, 1.0)) return st;
-    // x = x + P^T r / N
-    if (pnce_status st = run_fwd(plan, s, PNCE_PREC_F32S, pnce::IN_C64, work, plan->N, plan->N,
-                                 X, X, nullptr, batch, 1.0 / plan->N, 1.0))
+  return refine_steps(plan, (hipStream_t)stream, y, X, work, batch, steps);
+}
+
+pnce_status pnce_refine_noalloc(const pnce_plan *plan, void *stream, const void *y, void *X,
+                                int batch, int steps) {
+  if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
+  if (steps < 0) return fail(PNCE_E_INVALID, "steps must be >= 0");
+  if (batch == 0) return PNCE_OK;
+  if (!y || !X) return fail(PNCE_E_INVALID, "y and X must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
+  if (pnce_status st = check_align(y, 8, "y")) return st;
+  if (pnce_status st = check_align(X, 8, "X")) return st;
+  const size_t per_frame = (size_t)plan->R * (size_t)plan->N * 8;
+  if (per_frame > kScratchBytes)
+    return fail(PNCE_E_UNSUPPORTED,
+                "one frame's residual (R*N*8 = " + std::to_string(per_frame) +
+                    " bytes) exceeds the " + std::to_string(kScratchBytes >> 20) +
+                    " MiB scratch of pnce_refine_noalloc");
+  if (steps == 0) return PNCE_OK;
+  void *work = nullptr;
+  if (pnce_status st = scratch_of_device(plan->device, &work)) return st;
+  // frames are independent: refine them in groups whose residuals fit
+  const int group = (int)std::min<size_t>((size_t)batch, kScratchBytes / per_frame);
+  const size_t y_frame = (size_t)plan->R * plan->N, x_frame = (size_t)plan->R * plan->K;
+  for (int b0 = 0; b0 < batch; b0 += group) {
+    const int nb = std::min(group, batch - b0);
+    if (pnce_status st = refine_steps(plan, (hipStream_t)stream,
+                                      (const float2 *)y + (size_t)b0 * y_frame,
+                                      (float2 *)X + (size_t)b0 * x_frame, work, nb, steps))
       return st;
   }
   return PNCE_OK;

@@ -94,6 +94,8 @@ def test_null_plan_is_rejected_everywhere(lib):
     assert lib.pnce_adjoint(None, None, None, None, None, 1, 0, 1.0, 0.0) == -1
     lib.pnce_refine.argtypes = [P, P, P, P, P, ctypes.c_int, ctypes.c_int]
     assert lib.pnce_refine(None, None, None, None, None, 1, 1) == -1
+    lib.pnce_refine_noalloc.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int]
+    assert lib.pnce_refine_noalloc(None, None, None, None, 1, 1) == -1
     lib.pnce_pack.argtypes = [P, P, P, P, P, ctypes.c_int, ctypes.c_int]
     assert lib.pnce_pack(None, None, None, None, None, 1, 1) == -1
     lib.pnce_debias.argtypes = [P, P, P, ctypes.c_int]
