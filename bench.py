@@ -50,7 +50,8 @@ ROTATE_COPIES = 5              # frame / CIR buffer copies the FP32-baseline ste
 # HBM bytes per launch of the headline kernel measured with rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
 # for the kernel source with this sha256; any other source reports null.
-TRAFFIC = {"source_sha256": None, "bytes_per_launch": None}
+TRAFFIC = {"source_sha256": "5b2ae679350dc357a5f1bb693846dad60b3ef591700604b91ffecf7ddd638203",
+           "bytes_per_launch": 4295590904}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 / f16 matrix
 FP8_PEAK_TFLOPS = 5033.2       # dense fp8 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix
