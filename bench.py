@@ -24,7 +24,8 @@ T*L = 512, R = 64, 256 frames: the HBM-bound shape), timings of every other
 form of the path (adjoint, refinement, least squares, Eq. 8 lags, the
 4096-frame uneven batch, the front end) and the differentiation workload
 (N = 1023, T*L = 1024, R = 128, 1024 frames: forward + backward through
-autograd).
+autograd), and the frame latencies of Figs. 6 and 7 (copies from and to pinned
+host memory included) beside the pilot airtime of Eq. 11.
 
 Prints one JSON line (rank 0). Usage:
   python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cpu] [--no-rows]
@@ -50,8 +51,8 @@ ROTATE_COPIES = 5              # frame / CIR buffer copies the FP32-baseline ste
 # HBM bytes per launch of the headline kernel measured with rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
 # for the kernel source with this sha256; any other source reports null.
-TRAFFIC = {"source_sha256": "5b2ae679350dc357a5f1bb693846dad60b3ef591700604b91ffecf7ddd638203",
-           "bytes_per_launch": 4295590904}
+TRAFFIC = {"source_sha256": "df680d14f5e742cd80171e0a6bb6e0b093a1773c7ee4d040afb0201390b569a3",
+           "bytes_per_launch": 4295638306}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 / f16 matrix
 FP8_PEAK_TFLOPS = 5033.2       # dense fp8 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix
@@ -192,6 +193,21 @@ def p50_latency_us(fn, iters, torch):
     return statistics.median(ts)
 
 
+def p50_wall_us(fn, iters, torch):
+    """Median host wall-clock time of fn followed by a device synchronize:
+    the latency a host thread sees, enqueue and completion signal included."""
+    for _ in range(10):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(iters):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e6)
+    return statistics.median(ts)
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -314,13 +330,20 @@ def headline(torch, args):
     ms_c64, _ = time_steps(lambda: plan.estimate(y, "bf16", out=H2), few, 2, torch)
     nmse["bf16_from_c64"] = nmse_db(H2, h)
     # the conversion that produces the stored codes (Section III-B)
-    ms_pack, _ = time_steps(lambda: plan.pack(y, "bf16", out=q, scales=sc), few, 1, torch)
+    # (pnce_pack_ws: every frame read from HBM once), and the two-pass
+    # conversion without a workspace (a max pass, then a conversion pass)
+    work = torch.empty((1024 * B + 1,), dtype=torch.int32, device="cuda")
+    ms_pack, _ = time_steps(lambda: plan.pack(y, "bf16", out=q, scales=sc, work=work), few, 1,
+                            torch)
+    ms_pack2, _ = time_steps(lambda: plan.pack_two_pass(y, "bf16", out=q, scales=sc), few, 1,
+                             torch)
     frame_b = B * R * N * 8
     code_b = q.numel() * q.element_size()
     formats = {}
     for fmt, peak in (("f16", BF16_PEAK_TFLOPS), ("e4m3", FP8_PEAK_TFLOPS)):
         qf, sf = plan.pack(y, fmt)
-        ms_p, _ = time_steps(lambda: plan.pack(y, fmt, out=qf, scales=sf), few, 1, torch)
+        ms_p, _ = time_steps(lambda: plan.pack(y, fmt, out=qf, scales=sf, work=work), few, 1,
+                             torch)
         ms_e, _ = time_steps(lambda: plan.estimate_packed(qf, sf, fmt, out=H2), few, 1, torch)
         nmse[fmt] = nmse_db(H2, h)
         cb = qf.numel() * qf.element_size()
@@ -429,6 +452,7 @@ def headline(torch, args):
         "pack_bf16_ms": ms_pack,
         "pack_bf16_GB/s": (frame_b + code_b) / ms_pack / 1e6,
         "pack_bf16_hbm_frac": (frame_b + code_b) / ms_pack / 1e6 / HBM_PEAK_GBS,
+        "pack_bf16_two_pass_ms": ms_pack2,
         "pack_plus_estimate_ms": ms_pack + ms_bf,
         "other_formats": formats,
         "refine_ms": {f"{k}_steps": v for k, v in ref_ms.items()},
@@ -846,6 +870,62 @@ def front_end(plan, cfg, y, torch, lat_h2d_us, args):
                     "airtime per multiplexed block of Eq. 11 at each sample rate"}
 
 
+def latency_sweeps(torch, args):
+    """Frame latency of Section IV-C/IV-D (Figs. 6 and 7) against the pilot
+    airtime of Eq. 11. A frame holds the pilots of all N_t transmitters:
+    N_t / N_batch multiplexed blocks, each C + M samples (C = L, the cyclic
+    prefix) on each of the N_r antennas, i.e. N_t / N_batch estimator frames
+    of the plan (M, T = N_batch, L, R = N_r). Per frame, p50 over
+    `latency_iters` runs (HIP events on one stream): the bf16 estimate of the
+    device-resident blocks (prefix skipped by addressing); the same after
+    the host-to-device copy of the raw blocks from pinned memory; and that
+    plus the copy of the CIRs back to pinned memory. Airtime of Eq. 11:
+    (C + M) / F_s * N_t / N_batch at F_s = 10 MHz. Synthetic complex
+    Gaussian samples: the latency does not depend on the values."""
+    from paper_2206_05506_amd import Plan
+    points = [(16, M, 64, nb) for M in (511, 1023, 2047) for nb in (1, 2, 4, 8)]
+    points += [(n, 2047, 128, nb) for n in (16, 32, 64) for nb in (1, 2, 4, 8)]
+    iters = max(50, args.latency_iters)
+    rows = []
+    for n_ant, M, L, nb in points:
+        blocks = n_ant // nb
+        with Plan(M, nb, L, n_ant) as plan:
+            raw = _randn_c64((blocks, n_ant, L + M), 1000 + M + nb + n_ant, torch)
+            host = torch.empty(raw.shape, dtype=raw.dtype, pin_memory=True)
+            host.copy_(raw.cpu())
+            H = torch.empty((blocks, n_ant, nb * L), dtype=torch.complex64, device="cuda")
+            H_host = torch.empty(H.shape, dtype=H.dtype, pin_memory=True)
+
+            def kernel():
+                plan.estimate_cp(raw, L, "bf16", out=H)
+
+            def h2d():
+                raw.copy_(host, non_blocking=True)
+                kernel()
+
+            def h2d_d2h():
+                h2d()
+                H_host.copy_(H, non_blocking=True)
+
+            rows.append({
+                "array": f"{n_ant}x{n_ant}", "M": M, "L": L, "N_batch": nb, "blocks": blocks,
+                "lag_alias": nb * L > M,
+                "frame_bytes_in": raw.numel() * 8, "cir_bytes_out": H.numel() * 8,
+                "p50_us_estimate": p50_latency_us(kernel, iters, torch),
+                "p50_us_h2d_estimate": p50_latency_us(h2d, iters, torch),
+                "p50_us_h2d_estimate_d2h": p50_latency_us(h2d_d2h, iters, torch),
+                "p50_us_wall_h2d_estimate_d2h": p50_wall_us(h2d_d2h, iters, torch),
+                "airtime_us_10MHz": (L + M) / 10.0 * n_ant / nb,
+            })
+            del raw, host, H, H_host
+    return {"rows": rows,
+            "note": "one frame = pilots of all N_t transmitters (N_t / N_batch blocks of C + M "
+                    "samples, C = L) on N_r = N_t antennas; bf16 estimate; p50 of HIP-event-timed "
+                    "runs on one stream, copies from and to pinned host memory, and p50 of the "
+                    "host wall clock around the whole frame (synchronize included); airtime of Eq. 11 "
+                    "at 10 MHz; lag_alias marks N_batch * L > M (Eq. 7 violated: lags wrap)"}
+
+
 def pmc_probe(torch):
     """Three headline launches and three plain copies of the code buffer,
     nothing timed: the workload of a rocprofv3 --pmc byte-counter run."""
@@ -917,6 +997,8 @@ def main():
     if not args.no_workloads:
         out["fp32_baseline_workload"] = fp32_baseline_workload(torch, args)
         out["differentiation_workload"] = differentiation_workload(torch, args)
+    if not args.no_rows:
+        out["latency_sweeps"] = latency_sweeps(torch, args)
     print(json.dumps(out), flush=True)
 
 

@@ -184,6 +184,31 @@ pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y,
                       void *Yq, float *scales, int batch, int format);
 
 /*
+ * pnce_pack_cp (cp = 0: pnce_pack) with a workspace from the caller, which
+ * lets every frame be read from HBM once: frames above 1 MiB (and batches
+ * under 256 frames) are cut into slices held in registers by consecutive
+ * workgroups until the frame's maximum is gathered, then converted (one
+ * launch after a clear of the workspace); the codes and scales equal
+ * pnce_pack's. Batches of 256+ frames of at most 1 MiB take pnce_pack's
+ * one-launch path and leave work unused.
+ * work: device memory of at least PNCE_PACK_WORK_BYTES(batch) bytes, 4-byte
+ * aligned, owned by the caller, overwritten by the call (no content needed
+ * before it; 4 KiB per frame keeps the frames' synchronisation words on
+ * separate memory channels); concurrent calls need separate workspaces.
+ * After the call has run, the 32-bit word at index 1024 * batch of work
+ * (the last one) is nonzero only if a
+ * slice's wait for the rest of its frame ran past its bound (about a second;
+ * never expected: the launch is sized so that a frame's workgroups run
+ * together); the codes of that call are then not valid.
+ * Errors: as for pnce_pack_cp; work NULL, misaligned or too small ->
+ * PNCE_E_INVALID.
+ */
+#define PNCE_PACK_WORK_BYTES(batch) (4096 * (size_t)(batch) + 4)
+pnce_status pnce_pack_ws(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
+                         void *Yq, float *scales, int batch, int format, void *work,
+                         size_t work_bytes);
+
+/*
  * Correlator on a quantised batch (layout of pnce_pack) with FP32
  * accumulation on bf16 / f16 / fp8 matrix cores; the +-1 operand is exact in
  * every format. H = (scales[b] / N) * (Yq P) + beta * H, H [batch][R][T*L]

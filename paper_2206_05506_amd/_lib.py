@@ -37,6 +37,7 @@ SYMBOLS = ("pnce_create", "pnce_create_ex", "pnce_destroy", "pnce_get_sequence",
            "pnce_get_lags", "pnce_get_feedback", "pnce_get_shape",
            "pnce_estimate", "pnce_pack", "pnce_estimate_packed", "pnce_adjoint",
            "pnce_refine", "pnce_refine_noalloc", "pnce_debias", "pnce_estimate_ls", "pnce_estimate_cp", "pnce_pack_cp",
+           "pnce_pack_ws",
            "pnce_varlen_create", "pnce_varlen_destroy", "pnce_varlen_estimate",
            "pnce_varlen_estimate_each", "pnce_varlen_tune", "pnce_varlen_get_tuning",
            "pnce_varlen_set_tuning", "pnce_varlen_stats", "pnce_status_string",
@@ -82,6 +83,7 @@ def _load() -> ctypes.CDLL:
         "pnce_estimate_ls": ([_P, _P, _P, _P, _I, _I, _P], _I),
         "pnce_estimate_cp": ([_P, _P, _P, _I, _P, _I, _I, _P], _I),
         "pnce_pack_cp": ([_P, _P, _P, _I, _P, _P, _I, _I], _I),
+        "pnce_pack_ws": ([_P, _P, _P, _I, _P, _P, _I, _I, _P, ctypes.c_size_t], _I),
         "pnce_varlen_create": ([ctypes.POINTER(_P), ctypes.POINTER(pnce_frame_desc), _I, _I],
                                _I),
         "pnce_varlen_destroy": ([_P], _I),
@@ -195,6 +197,16 @@ def pnce_estimate_cp(plan, stream, Y_raw, cp, H, batch, precision, scales) -> in
 def pnce_pack_cp(plan, stream, Y_raw, cp, Yq, scales, batch, fmt) -> int:
     return check(lib.pnce_pack_cp(plan, stream, Y_raw, cp, Yq, scales, batch, fmt),
                  "pnce_pack_cp")
+
+
+def pack_work_bytes(batch: int) -> int:
+    """PNCE_PACK_WORK_BYTES(batch) of include/pnce.h."""
+    return 4096 * int(batch) + 4
+
+
+def pnce_pack_ws(plan, stream, Y_raw, cp, Yq, scales, batch, fmt, work, work_bytes) -> int:
+    return check(lib.pnce_pack_ws(plan, stream, Y_raw, cp, Yq, scales, batch, fmt, work,
+                                  work_bytes), "pnce_pack_ws")
 
 
 def pnce_estimate_ls(plan, stream, Y, H, batch, precision, scales) -> int:

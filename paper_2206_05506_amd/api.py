@@ -155,19 +155,29 @@ class Plan:
         return out
 
     # ---------------------------------------------------------------- a3
-    def pack(self, Y: torch.Tensor, fmt: str = "bf16", out=None, scales=None):
-        """Quantise Y [B, R, N] complex64 -> (codes [B, R, 2, N+1], scales [B])."""
+    def pack(self, Y: torch.Tensor, fmt: str = "bf16", out=None, scales=None, work=None):
+        """Quantise Y [B, R, N] complex64 -> (codes [B, R, 2, N+1], scales [B]),
+        every frame read from HBM once (pnce_pack_ws; work: an int32 device
+        tensor of at least 1024 B + 1 words, allocated here when None)."""
+        return self.pack_cp(Y, 0, fmt, out=out, scales=scales, work=work)
+
+    def pack_two_pass(self, Y: torch.Tensor, fmt: str = "bf16", out=None, scales=None):
+        """pnce_pack: the same codes and scales without a workspace (frames
+        above 1 MiB are then read twice: a max pass, a conversion pass)."""
         B = Y.shape[0]
         _need(Y, (B, self.R, self.N), torch.complex64, "Y")
-        if out is None:
-            out = torch.empty((B, self.R, 2, self.N + 1), dtype=_CODE_DTYPE[fmt],
-                              device=Y.device)
-        if scales is None:
-            scales = torch.empty((B,), dtype=torch.float32, device=Y.device)
-        _need(out, (B, self.R, 2, self.N + 1), _CODE_DTYPE[fmt], "Yq")
-        _need(scales, (B,), torch.float32, "scales")
+        out, scales = self._pack_outputs(B, fmt, out, scales, Y.device)
         _lib.pnce_pack(self.handle, _stream(), _ptr(Y), _ptr(out), _ptr(scales), B,
                        FORMATS[fmt])
+        return out, scales
+
+    def _pack_outputs(self, B, fmt, out, scales, device):
+        if out is None:
+            out = torch.empty((B, self.R, 2, self.N + 1), dtype=_CODE_DTYPE[fmt], device=device)
+        if scales is None:
+            scales = torch.empty((B,), dtype=torch.float32, device=device)
+        _need(out, (B, self.R, 2, self.N + 1), _CODE_DTYPE[fmt], "Yq")
+        _need(scales, (B,), torch.float32, "scales")
         return out, scales
 
     # ------------------------------------------------------ front end
@@ -188,18 +198,30 @@ class Plan:
                               _ptr(scales))
         return out
 
-    def pack_cp(self, Y_raw: torch.Tensor, cp: int, fmt: str = "bf16", out=None, scales=None):
+    def pack_cp(self, Y_raw: torch.Tensor, cp: int, fmt: str = "bf16", out=None, scales=None,
+                work=None):
         """Quantise raw blocks Y_raw [B, R, cp + N], dropping the cyclic prefix
-        in the same launch: (codes [B, R, 2, N+1], scales [B])."""
+        in the same launch: (codes [B, R, 2, N+1], scales [B]); every frame is
+        read from HBM once (pnce_pack_ws)."""
         B = Y_raw.shape[0]
         _need(Y_raw, (B, self.R, self.N + cp), torch.complex64, "Y_raw")
-        if out is None:
-            out = torch.empty((B, self.R, 2, self.N + 1), dtype=_CODE_DTYPE[fmt],
-                              device=Y_raw.device)
-        if scales is None:
-            scales = torch.empty((B,), dtype=torch.float32, device=Y_raw.device)
-        _need(out, (B, self.R, 2, self.N + 1), _CODE_DTYPE[fmt], "Yq")
-        _need(scales, (B,), torch.float32, "scales")
+        out, scales = self._pack_outputs(B, fmt, out, scales, Y_raw.device)
+        nbytes = _lib.pack_work_bytes(B)
+        if work is None:
+            work = torch.empty(((nbytes + 3) // 4,), dtype=torch.int32, device=Y_raw.device)
+        _need(work, (work.numel(),), torch.int32, "work")
+        if work.numel() * 4 < nbytes:
+            raise ValueError(f"work holds {work.numel()} words, {(nbytes + 3) // 4} needed")
+        _lib.pnce_pack_ws(self.handle, _stream(), _ptr(Y_raw), int(cp), _ptr(out), _ptr(scales),
+                          B, FORMATS[fmt], _ptr(work), work.numel() * 4)
+        return out, scales
+
+    def pack_cp_two_pass(self, Y_raw: torch.Tensor, cp: int, fmt: str = "bf16", out=None,
+                         scales=None):
+        """pnce_pack_cp: as pack_cp without a workspace."""
+        B = Y_raw.shape[0]
+        _need(Y_raw, (B, self.R, self.N + cp), torch.complex64, "Y_raw")
+        out, scales = self._pack_outputs(B, fmt, out, scales, Y_raw.device)
         _lib.pnce_pack_cp(self.handle, _stream(), _ptr(Y_raw), int(cp), _ptr(out),
                           _ptr(scales), B, FORMATS[fmt])
         return out, scales

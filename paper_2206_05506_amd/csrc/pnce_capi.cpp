@@ -490,6 +490,30 @@ pnce_status pnce_pack_cp(const pnce_plan *plan, void *stream, const void *Y_raw,
   return PNCE_OK;
 }
 
+pnce_status pnce_pack_ws(const pnce_plan *plan, void *stream, const void *Y_raw, int cp,
+                         void *Yq, float *scales, int batch, int format, void *work,
+                         size_t work_bytes) {
+  if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
+  if (!valid_fmt(format)) return fail(PNCE_E_INVALID, "unknown format");
+  if (pnce_status st = check_cp(plan, cp)) return st;
+  if (batch == 0) return PNCE_OK;
+  if (!Y_raw || !Yq || !scales || !work)
+    return fail(PNCE_E_INVALID, "Y_raw, Yq, scales and work must be non-NULL");
+  if (pnce_status st = check_batch(plan, batch)) return st;
+  if (work_bytes < PNCE_PACK_WORK_BYTES(batch))
+    return fail(PNCE_E_INVALID, "work is smaller than PNCE_PACK_WORK_BYTES(batch)");
+  if (pnce_status st = check_align(Y_raw, 8, "Y_raw")) return st;
+  if (pnce_status st = check_align(Yq, code_align(format), "Yq")) return st;
+  if (pnce_status st = check_align(scales, 4, "scales")) return st;
+  if (pnce_status st = check_align(work, 4, "work")) return st;
+  const float *Y = (const float *)Y_raw + (size_t)cp * 2;
+  hipError_t e = pnce::launch_pack_ws(Y, Yq, scales, (uint32_t *)work, batch, plan->R, plan->N,
+                                      plan->N + cp, format, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pack launch");
+  return PNCE_OK;
+}
+
 pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream, const void *Yq,
                                  const float *scales, void *H, int batch, int format,
                                  double beta) {

@@ -122,5 +122,14 @@ constexpr int kPackFrameBatch = 256;
 constexpr long long kPackFrameMaxBytes = 1LL << 20;
 hipError_t launch_pack(const float *y, void *yq, float *scales, int batch,
                        int R, int N, int ld, int fmt, hipStream_t s);
+// Same codes and scales with a workspace of kPackSyncWords * batch + 1
+// words (PNCE_PACK_WORK_BYTES): frames that the one-launch path does not
+// take are read from HBM once, in slices held in registers while the frame
+// maximum is gathered (one launch after a clear of the workspace). Word
+// kPackSyncWords * batch becomes nonzero if a slice's wait for the rest of
+// its frame ran past its bound.
+constexpr int kPackSyncWords = 1024;
+hipError_t launch_pack_ws(const float *y, void *yq, float *scales, uint32_t *work, int batch,
+                          int R, int N, int ld, int fmt, hipStream_t s);
 
 }  // namespace pnce

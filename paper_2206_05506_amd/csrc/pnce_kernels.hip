@@ -1595,282 +1595,4 @@ hipError_t launch_debias(float *H, long rows, int K, int N, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Quantiser.
-// ---------------------------------------------------------------------------
-// Smallest power of two 2^e with m <= target * 2^e (m finite, > 0).
-__device__ float pow2_scale(float m, float target) {
-  int e;
-  (void)frexpf(m / target, &e);
-  while ((double)m > (double)target * ldexp(1.0, e)) ++e;
-  while ((double)m <= (double)target * ldexp(1.0, e - 1)) --e;
-  // at least the smallest normal float, so that the reciprocal is finite
-  // for frames of subnormal samples
-  return ldexpf(1.0f, e < -126 ? -126 : e);
-}
-
-// The frame maximum travels as the bit pattern of |v|: for non-negative
-// floats the unsigned order is the numeric order, and every NaN pattern sits
-// above +inf, so one unsigned max also flags non-finite frames.
-__device__ __forceinline__ float scale_from_maxbits(uint32_t mb, float target) {
-  if (mb == 0u || mb >= 0x7F800000u) return 1.0f;  // zeros, inf or NaN
-  return pow2_scale(__builtin_bit_cast(float, mb), target);
-}
-
-__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p, int n) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
-// Grid (slices, frames): each workgroup reduces one slice of a frame's R*N
-// complex samples and folds it into the frame's word with one atomic max.
-constexpr int kMaxUnroll = 8;
-__global__ __launch_bounds__(256) void frame_max_kernel(const f2a8 *y, uint32_t *maxbits,
-                                                        long per_frame) {
-  const f2a8 *f = y + (size_t)blockIdx.y * per_frame;
-  const long step = (long)gridDim.x * 256;
-  uint32_t m = 0u;
-  for (long i0 = (long)blockIdx.x * 256 + threadIdx.x; i0 < per_frame; i0 += step * kMaxUnroll) {
-    f2a8 v[kMaxUnroll];
-#pragma unroll
-    for (int u = 0; u < kMaxUnroll; ++u) {
-      const long i = i0 + u * step;
-      v[u] = i < per_frame ? f[i] : f2a8{0.0f, 0.0f};
-    }
-#pragma unroll
-    for (int u = 0; u < kMaxUnroll; ++u) {
-      // by-value floats: a bit cast of a vector element lvalue is not safe here
-      const float re = v[u].x, im = v[u].y;
-      m = max(m, __builtin_bit_cast(uint32_t, re) & 0x7FFFFFFFu);
-      m = max(m, __builtin_bit_cast(uint32_t, im) & 0x7FFFFFFFu);
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
-  __shared__ uint32_t sm[4];
-  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    m = max(max(sm[0], sm[1]), max(sm[2], sm[3]));
-    if (m) atomicMax(maxbits + blockIdx.y, m);
-  }
-}
-
-// Rows with a stride (raw blocks whose cyclic prefix is skipped): grid
-// (row slices, frames); a workgroup reduces whole rows r = x, x + slices, ...
-__global__ __launch_bounds__(256) void frame_max_rows_kernel(const f2a8 *y, uint32_t *maxbits,
-                                                             int R, int N, int ld) {
-  uint32_t m = 0u;
-  for (int r = blockIdx.x; r < R; r += gridDim.x) {
-    const f2a8 *row = y + ((size_t)blockIdx.y * R + r) * ld;
-    for (int n = threadIdx.x; n < N; n += 256) {
-      const f2a8 v = row[n];
-      const float re = v.x, im = v.y;
-      m = max(m, __builtin_bit_cast(uint32_t, re) & 0x7FFFFFFFu);
-      m = max(m, __builtin_bit_cast(uint32_t, im) & 0x7FFFFFFFu);
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
-  __shared__ uint32_t sm[4];
-  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    m = max(max(sm[0], sm[1]), max(sm[2], sm[3]));
-    if (m) atomicMax(maxbits + blockIdx.y, m);
-  }
-}
-
-// Max bits -> power-of-two scale, in place, once every pack block has read them.
-__global__ __launch_bounds__(256) void finalize_scale_kernel(float *scales, int batch,
-                                                             float target) {
-  const int b = blockIdx.x * 256 + threadIdx.x;
-  if (b < batch)
-    scales[b] = scale_from_maxbits(__builtin_bit_cast(uint32_t, scales[b]), target);
-}
-
-// float -> OCP e4m3fn code, round to nearest even, saturating at +-448;
-// NaN -> 0x7F with the sign bit.
-__device__ __forceinline__ uint32_t e4m3_code(float x) {
-  const uint32_t u = __builtin_bit_cast(uint32_t, x);
-  const uint32_t sign = (u >> 24) & 0x80u;
-  const float ax = fabsf(x);
-  if (ax != ax) return sign | 0x7Fu;
-  if (ax >= 448.0f) return sign | 0x7Eu;
-  if (ax < 0.015625f) {  // below 2^-6: subnormal grid of step 2^-9
-    return sign | (uint32_t)__builtin_rintf(ax * 512.0f);
-  }
-  int E = (int)((__builtin_bit_cast(uint32_t, ax) >> 23) & 0xFF) - 127;  // -6 .. 8
-  uint32_t q = (uint32_t)__builtin_rintf(ldexpf(ax, 3 - E));              // 8 .. 16
-  if (q == 16u) {
-    q = 8u;
-    ++E;
-  }
-  return sign | ((uint32_t)(E + 7) << 3) | (q - 8u);
-}
-
-// Four consecutive samples of one padded output row per thread. The padded
-// row length N + 1 is a power of two, so each thread's codes form one aligned
-// 8-byte (16-bit codes) or 4-byte (e4m3) store per plane.
-// Four samples n0 .. n0+3 of one row (those at or past N read as zero) to
-// codes n0 .. n0+3 of the row's two planes (real at q_row, imaginary at
-// q_row + Np), each value times inv, rounded to nearest even (e4m3:
-// saturating).
-template <int FMT>
-__device__ __forceinline__ void pack_quad(const f2a8 *y_row, void *yq, size_t q_row, int n0,
-                                          int N, int Np, float inv) {
-  f2a8 v[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) v[u] = n0 + u < N ? y_row[n0 + u] : f2a8{0.0f, 0.0f};
-  const size_t o = q_row + n0;
-  if constexpr (FMT == 3) {
-    uint32_t cr = 0u, ci = 0u;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (n0 + u < N) {
-        cr |= e4m3_code(v[u].x * inv) << (8 * u);
-        ci |= e4m3_code(v[u].y * inv) << (8 * u);
-      }
-    }
-    uint8_t *q = (uint8_t *)yq;
-    *(uint32_t *)(q + o) = cr;
-    *(uint32_t *)(q + o + Np) = ci;
-  } else {
-    uint64_t cr = 0u, ci = 0u;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (n0 + u < N) {
-        uint32_t r, m;
-        if constexpr (FMT == 1) {
-          r = bf16_bits(v[u].x * inv);
-          m = bf16_bits(v[u].y * inv);
-        } else {
-          r = __builtin_bit_cast(uint16_t, (_Float16)(v[u].x * inv));
-          m = __builtin_bit_cast(uint16_t, (_Float16)(v[u].y * inv));
-        }
-        cr |= (uint64_t)r << (16 * u);
-        ci |= (uint64_t)m << (16 * u);
-      }
-    }
-    uint16_t *q = (uint16_t *)yq;
-    *(uint64_t *)(q + o) = cr;
-    *(uint64_t *)(q + o + Np) = ci;
-  }
-}
-
-template <int FMT>
-__global__ __launch_bounds__(256) void pack_kernel(const f2a8 *y, void *yq, const uint32_t *maxbits,
-                                                   int R, int N, int ld, float target,
-                                                   long total) {
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;  // (row, quad)
-  if (i >= total) return;
-  const int Np = N + 1, nq = Np >> 2;
-  const long row = i / nq;  // frame * R + antenna
-  const int n0 = (int)(i - row * nq) * 4;
-  const int b = (int)(row / R);
-  const float inv = 1.0f / scale_from_maxbits(maxbits[b], target);
-  pack_quad<FMT>(y + row * ld, yq, (size_t)row * 2 * Np, n0, N, Np, inv);
-}
-
-// The whole quantiser in one launch when the batch has at least one frame
-// per CU: workgroup b reduces frame b's max-abs word in LDS, then converts
-// the frame (its second read mostly served by the caches) and writes the
-// frame's scale. No atomics and no counters to clear; the codes equal those
-// of the four-launch path (same maximum, same conversions).
-constexpr int kPackFrameThreads = 1024;
-template <int FMT>
-__global__ __launch_bounds__(kPackFrameThreads) void pack_frame_kernel(
-    const f2a8 *y, void *yq, float *scales, int R, int N, int ld, float target) {
-  const int b = blockIdx.x;
-  const int tid = threadIdx.x;
-  const f2a8 *f = y + (size_t)b * R * ld;
-  uint32_t m = 0u;
-  auto fold = [&](f2a8 v) {
-    const float re = v.x, im = v.y;
-    m = max(m, __builtin_bit_cast(uint32_t, re) & 0x7FFFFFFFu);
-    m = max(m, __builtin_bit_cast(uint32_t, im) & 0x7FFFFFFFu);
-  };
-  constexpr int U = 4;
-  if (ld == N) {  // one contiguous run of R*N samples
-    const long per = (long)R * N;
-    for (long i0 = tid; i0 < per; i0 += (long)kPackFrameThreads * U) {
-      f2a8 v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const long i = i0 + (long)u * kPackFrameThreads;
-        v[u] = i < per ? f[i] : f2a8{0.0f, 0.0f};
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) fold(v[u]);
-    }
-  } else {  // rows of N samples at a stride of ld
-    for (int r = 0; r < R; ++r)
-      for (int n = tid; n < N; n += kPackFrameThreads) fold(f[(size_t)r * ld + n]);
-  }
-  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
-  __shared__ uint32_t wmax[kPackFrameThreads / 64];
-  if ((tid & 63) == 0) wmax[tid >> 6] = m;
-  __syncthreads();
-  m = 0u;
-#pragma unroll
-  for (int w = 0; w < kPackFrameThreads / 64; ++w) m = max(m, wmax[w]);
-  const float scale = scale_from_maxbits(m, target);
-  const float inv = 1.0f / scale;
-  const int Np = N + 1, nq = Np >> 2;
-  const long total = (long)R * nq;
-  for (long i = tid; i < total; i += kPackFrameThreads) {
-    const int r = (int)(i / nq);
-    const int n0 = (int)(i - (long)r * nq) * 4;
-    const long row = (long)b * R + r;
-    pack_quad<FMT>(f + (size_t)r * ld, yq, (size_t)row * 2 * Np, n0, N, Np, inv);
-  }
-  if (tid == 0) scales[b] = scale;
-}
-
-// scales doubles as the per-frame max word until the last launch turns it
-// into the scale, so the four launches must stay in this order on one stream.
-hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R, int N,
-                       int ld, int fmt, hipStream_t s) {
-  if (fmt < 1 || fmt > 3) return hipErrorInvalidValue;
-  const float target = (fmt == 3) ? 448.0f : 1.0f;
-  if (batch >= kPackFrameBatch && (long long)R * ld * 8 <= kPackFrameMaxBytes) {
-    const dim3 grid((unsigned)batch), block(kPackFrameThreads);
-    const f2a8 *yc = (const f2a8 *)y;
-    if (fmt == 1)
-      hipLaunchKernelGGL((pack_frame_kernel<1>), grid, block, 0, s, yc, yq, scales, R, N, ld,
-                         target);
-    else if (fmt == 2)
-      hipLaunchKernelGGL((pack_frame_kernel<2>), grid, block, 0, s, yc, yq, scales, R, N, ld,
-                         target);
-    else
-      hipLaunchKernelGGL((pack_frame_kernel<3>), grid, block, 0, s, yc, yq, scales, R, N, ld,
-                         target);
-    return hipGetLastError();
-  }
-  uint32_t *mb = (uint32_t *)scales;
-  const f2a8 *yc = (const f2a8 *)y;
-  hipLaunchKernelGGL(zero_u32_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, mb, batch);
-  if (ld == N) {
-    const long per_frame = (long)R * N;
-    const long slices = std::max(1L, std::min(64L, per_frame / (256L * kMaxUnroll)));
-    hipLaunchKernelGGL(frame_max_kernel, dim3((unsigned)slices, (unsigned)batch), dim3(256), 0,
-                       s, yc, mb, per_frame);
-  } else {
-    hipLaunchKernelGGL(frame_max_rows_kernel, dim3((unsigned)std::min(R, 64), (unsigned)batch),
-                       dim3(256), 0, s, yc, mb, R, N, ld);
-  }
-  const long total = (long)batch * R * ((N + 1) >> 2);
-  const dim3 grid((unsigned)((total + 255) / 256));
-  if (fmt == 1)
-    hipLaunchKernelGGL((pack_kernel<1>), grid, dim3(256), 0, s, yc, yq, mb, R, N, ld, target,
-                       total);
-  else if (fmt == 2)
-    hipLaunchKernelGGL((pack_kernel<2>), grid, dim3(256), 0, s, yc, yq, mb, R, N, ld, target,
-                       total);
-  else
-    hipLaunchKernelGGL((pack_kernel<3>), grid, dim3(256), 0, s, yc, yq, mb, R, N, ld, target,
-                       total);
-  hipLaunchKernelGGL(finalize_scale_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, scales,
-                     batch, target);
-  return hipGetLastError();
-}
-
 }  // namespace pnce

@@ -518,7 +518,7 @@ def test_pack_one_launch_path_bit_exact(fmt, N, R, cp):
     workgroup per frame. Its codes and scales equal the oracle's bit for
     bit, including degenerate frames (all zero, +-inf, NaN, a maximum on a
     power of two, subnormal-size values) and raw rows with a cyclic prefix,
-    and equal the four-launch path's on the first 255 frames."""
+    and equal those of the slice path (255 frames) and of the two-pass path."""
     from paper_2206_05506_amd.api import _CODE_DTYPE
     B = 256
     rng = np.random.default_rng(N + R + cp)
@@ -536,12 +536,110 @@ def test_pack_one_launch_path_bit_exact(fmt, N, R, cp):
         q, sc = (p.pack_cp(yd, cp, fmt) if cp else p.pack(yd, fmt))
         part = yd[:B - 1].contiguous()
         q4, sc4 = (p.pack_cp(part, cp, fmt) if cp else p.pack(part, fmt))
-        q, sc, q4, sc4 = host(q), host(sc), host(q4), host(sc4)
+        q2, sc2 = p.pack_cp_two_pass(yd, cp, fmt)
+        q, sc, q4, sc4, q2, sc2 = (host(q), host(sc), host(q4), host(sc4), host(q2),
+                                   host(sc2))
     ref_q, ref_sc = oracle.quantize(y, fmt)
     assert q.dtype == np.dtype(str(_CODE_DTYPE[fmt]).replace("torch.", ""))
     assert np.array_equal(sc, ref_sc)
     assert np.array_equal(q.view(ref_q.dtype), ref_q)
     assert np.array_equal(sc4, sc[:B - 1]) and np.array_equal(q4, q[:B - 1])
+    assert np.array_equal(sc2, sc) and np.array_equal(q2, q)
+
+
+def _special_frames(y):
+    """Degenerate frames in place (as many as the batch holds): a maximum on
+    a power of two, all zero, +-inf and NaN, subnormal-size values."""
+    B, R, N = y.shape
+    if B > 1:
+        y[1] *= np.float32(0.49) / max(np.abs(y[1].real).max(), np.abs(y[1].imag).max())
+        y[1, R - 1, N - 1] = 0.5
+    if B > 2:
+        y[2] = 0.0
+    if B > 3:
+        y[3, 0, N - 1] = np.inf
+        y[3, R - 1, 0] = np.nan + 1j
+    if B > 4:
+        y[4] = np.float32(1e-39)
+    return y
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "e4m3"])
+@pytest.mark.parametrize("N,R,B,cp", [(4095, 40, 3, 0), (2047, 37, 5, 17), (7, 3, 2, 0),
+                                      (65535, 3, 2, 5), (1023, 300, 4, 0), (255, 2, 5, 3)])
+def test_pack_single_read_path_bit_exact(fmt, N, R, B, cp):
+    """The quantiser with a workspace (pnce_pack_ws) on batches the
+    one-launch path does not take: each frame is cut into slices of 8192
+    samples held in registers while the frame maximum is gathered (full,
+    ragged and single slices). Codes and scales equal the oracle's bit for
+    bit, degenerate frames included, and equal the two-pass path's; the
+    workspace's wait flag stays zero."""
+    from paper_2206_05506_amd import _lib
+    rng = np.random.default_rng(N + R + B + cp)
+    y = (rng.standard_normal((B, R, N)) + 1j * rng.standard_normal((B, R, N))).astype(np.complex64)
+    y *= (10.0 ** rng.uniform(-4, 4, size=(B, 1, 1))).astype(np.float32)
+    y = _special_frames(y)
+    raw = np.concatenate([y[:, :, N - cp:], y], axis=2) if cp else y
+    print(f"pack_ws fmt={fmt} N={N} R={R} B={B} cp={cp}", flush=True)
+    with _plan(N, 1, 1, R) as p:
+        yd = dev(raw)
+        work = torch.full(((_lib.pack_work_bytes(B) + 3) // 4,), -1, dtype=torch.int32,
+                          device="cuda")
+        q, sc = p.pack_cp(yd, cp, fmt, work=work)
+        q2, sc2 = p.pack_cp_two_pass(yd, cp, fmt)
+        q, sc, q2, sc2 = host(q), host(sc), host(q2), host(sc2)
+        flag = int(host(work)[1024 * B])
+    ref_q, ref_sc = oracle.quantize(y, fmt)
+    assert flag == 0
+    assert np.array_equal(sc, ref_sc)
+    assert np.array_equal(q.view(ref_q.dtype), ref_q)
+    assert np.array_equal(sc2, sc) and np.array_equal(q2, q)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "e4m3"])
+def test_pack_single_read_path_precision_frames(fmt):
+    """Eight frames of the precision workload's shape (256 x 4095, 8.4 MB:
+    128 slices each): the single-read codes equal the two-pass codes bit for
+    bit, and the oracle's on the first frame."""
+    N, R, B = 4095, 256, 8
+    g = torch.Generator(device="cuda")
+    g.manual_seed(41)
+    with _plan(N, 32, 64, R) as p:
+        y = torch.complex(torch.randn((B, R, N), generator=g, device="cuda"),
+                          torch.randn((B, R, N), generator=g, device="cuda")).contiguous()
+        y[3] *= 1e-5
+        q, sc = p.pack(y, fmt)
+        q2, sc2 = p.pack_two_pass(y, fmt)
+        assert torch.equal(sc, sc2) and torch.equal(q, q2)
+        y0, q0, s0 = host(y[:1]), host(q[:1]), host(sc[:1])
+    ref_q, ref_sc = oracle.quantize(y0, fmt)
+    assert np.array_equal(s0, ref_sc)
+    assert np.array_equal(q0.view(ref_q.dtype), ref_q)
+
+
+def test_pack_workspace_is_checked():
+    """pnce_pack_ws refuses a missing, misaligned or short workspace before
+    anything is enqueued."""
+    from paper_2206_05506_amd import _lib
+    lib = _lib.lib
+    N, R, B = 127, 3, 4
+    with _plan(N, 1, 1, R) as p:
+        y = dev(_rand_frames(N, R, B, 77))
+        q = torch.zeros((B, R, 2, N + 1), dtype=torch.int16, device="cuda")
+        sc = torch.zeros((B,), dtype=torch.float32, device="cuda")
+        w = torch.zeros((1024 * B + 2,), dtype=torch.int32, device="cuda")
+        need = _lib.pack_work_bytes(B)
+        args = (p.handle, None, y.data_ptr(), 0, q.data_ptr(), sc.data_ptr(), B, 1)
+        assert lib.pnce_pack_ws(*args, None, need) == -1
+        assert lib.pnce_pack_ws(*args, w.data_ptr(), need - 1) == -1
+        assert lib.pnce_pack_ws(*args, w.data_ptr() + 2, need) == -1
+        torch.cuda.synchronize()
+        assert not q.any() and not sc.any()
+        with pytest.raises(ValueError):
+            p.pack(y, "bf16", work=torch.zeros((1024 * B,), dtype=torch.int32, device="cuda"))
+        assert lib.pnce_pack_ws(*args, w.data_ptr(), need) == 0
+        torch.cuda.synchronize()
+        assert sc.all()
 
 
 def test_misaligned_pointers_are_refused():
