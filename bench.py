@@ -76,6 +76,11 @@ def parse():
                          "packed bf16 estimate on all 512 precision-study frames, the e4m3 one, "
                          "the FP32-accurate estimate of the same frames), for rocprofv3 --pmc "
                          "counters of matrix-core activity")
+    ap.add_argument("--adjoint-probe", action="store_true",
+                    help="only 3 launches each of the FP32-accurate adjoint on the FP32-baseline "
+                         "shape (256 frames, T*L=512 -> N=1023) and on the differentiation shape "
+                         "(1024 frames, T*L=1024 -> N=1023), and of the FP32-accurate estimate of "
+                         "the FP32-baseline shape, for rocprofv3 counters")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the adjoint/refinement/uneven-batch/front-end timings")
     ap.add_argument("--no-workloads", action="store_true",
@@ -583,9 +588,21 @@ def _is_primitive(d, mask):
     return False
 
 
+def _varlen_model_cost(N, K, nc):
+    """The uneven batch's default cost model of one (frame, 32-antenna) unit
+    at column width 128 * nc (streaming ~N samples plus matrix work over the
+    padded lag width), used to schedule the fixed-width candidates."""
+    w = 128 * nc
+    groups = (K + w - 1) // w
+    return N * (1.0 + groups * w / 256.0) * 1e-3
+
+
 def uneven_batch(torch, args):
     """4096 frames of uneven (R, N, T, L) (seed 3), bf16 codes: one persistent
-    launch (autotuned) against one launch per frame."""
+    launch, under the autotuned, the default and three fixed-width schedules
+    (timed in interleaved rounds after a clock spin-up, so that clock drift
+    hits every schedule alike), eager against a HIP graph replay (also
+    interleaved), and against one launch per frame."""
     import synth
     from paper_2206_05506_amd import VarlenPlan
     shapes = [(int(R), (1 << int(d)) - 1, int(T), int(L))
@@ -596,25 +613,43 @@ def uneven_batch(torch, args):
     Yq = torch.randn((vp.n_codes,), generator=g, device="cuda").to(torch.bfloat16)
     Yq = Yq.view(torch.int16).contiguous()
     H = torch.empty((vp.n_out,), dtype=torch.complex64, device="cuda")
-    start = vp.tuning()
+
+    def step():
+        vp.estimate(Yq, None, out=H)
+
+    default = vp.tuning()
+    spin_up(step, 0.3, torch)
     vp.tune(Yq, None, out=H, reps=3)
     tuned = vp.tuning()
-    ms_p, _ = time_steps(lambda: vp.estimate(Yq, None, out=H), args.steps, 2, torch)
-    # the default schedule, timed in the same (warm) state for comparison
-    vp.set_tuning(start)
-    ms_u, _ = time_steps(lambda: vp.estimate(Yq, None, out=H), args.steps, 2, torch)
+    schedules = {"tuned": tuned, "default_model": default}
+    for nc in (1, 2, 4):
+        schedules[f"all_width_{128 * nc}"] = [(N, K, nc, _varlen_model_cost(N, K, nc))
+                                              for N, K, _, _ in default]
+    n_t = max(5, args.steps // 2)
+    times = {k: [] for k in schedules}
+    for _ in range(3):
+        for k, sch in schedules.items():
+            vp.set_tuning(sch)
+            times[k].append(time_steps(step, n_t, 2, torch)[0])
+    sched_ms = {k: statistics.median(v) for k, v in times.items()}
     vp.set_tuning(tuned)
+    ms_p = sched_ms["tuned"]
     ms_e, _ = time_steps(lambda: vp.estimate_each(Yq, None, out=H), 3, 1, torch)
-    # the persistent launch captured once in a HIP graph and replayed
+    # the persistent launch captured once in a HIP graph and replayed,
+    # interleaved with eager launches of the same schedule
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        vp.estimate(Yq, None, out=H)
+        step()
     torch.cuda.current_stream().wait_stream(side)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        vp.estimate(Yq, None, out=H)
-    ms_g, _ = time_steps(graph.replay, args.steps, 2, torch)
+        step()
+    spin_up(step, 0.2, torch)
+    eager_t, graph_t = [], []
+    for _ in range(3):
+        eager_t.append(time_steps(step, n_t, 2, torch)[0])
+        graph_t.append(time_steps(graph.replay, n_t, 2, torch)[0])
     del graph
     cirs = sum(R * T for R, N, T, L in shapes)
     byt = vp.n_codes * 2 + vp.n_out * 8
@@ -626,14 +661,21 @@ def uneven_batch(torch, args):
                   for R, N, T, L in shapes)
     st = vp.stats()
     vp.close()
-    return {"frames": len(shapes), "persistent_ms": ms_p, "untuned_ms": ms_u,
-            "graph_replay_ms": ms_g,
+    return {"frames": len(shapes), "persistent_ms": ms_p,
+            "untuned_ms": sched_ms["default_model"],
+            "schedules_ms": sched_ms,
+            "tuned_widths": sorted({(N, K, nc) for N, K, nc, _ in tuned}),
+            "eager_ms_interleaved": statistics.median(eager_t),
+            "graph_replay_ms": statistics.median(graph_t),
             "per_frame_launches_ms": ms_e,
             "speedup": ms_e / ms_p, "CIR/s": cirs / (ms_p * 1e-3),
             "GB/s": byt / ms_p / 1e6, "hbm_frac": byt / ms_p / 1e6 / HBM_PEAK_GBS,
             "mfma_frac": flops / ms_p / 1e9 / BF16_PEAK_TFLOPS,
             "per_frame_roofline_us": roof_us, "per_frame_roofline_frac": roof_us / (ms_p * 1e3),
-            "workgroups": st["workgroups"], "tiles": st["tiles"]}
+            "workgroups": st["workgroups"], "tiles": st["tiles"],
+            "note": "schedules_ms: medians of 3 interleaved rounds; tuned = the schedule "
+                    "pnce_varlen_tune keeps (the fastest of five candidates timed end to end); "
+                    "all_width_W: every class at W lags per tile, scheduled by the cost model"}
 
 
 def _randn_c64(shape, seed, torch):
@@ -971,6 +1013,26 @@ def mfma_probe(torch):
     print(json.dumps({"mfma_probe": True}), flush=True)
 
 
+def adjoint_probe(torch):
+    """Three launches each of the FP32-accurate adjoint (FP32-baseline and
+    differentiation shapes) and of the FP32-accurate estimate on fixed seeded
+    data, nothing timed: the workload of a rocprofv3 run."""
+    import synth
+    from paper_2206_05506_amd import Plan
+    for cfg in (synth.FP32, synth.DIFF):
+        with Plan(cfg.N, cfg.T, cfg.L, cfg.R) as p:
+            G = _randn_c64((cfg.B, cfg.R, cfg.K), 31, torch)
+            A = torch.empty((cfg.B, cfg.R, cfg.N), dtype=torch.complex64, device="cuda")
+            for _ in range(3):
+                p.adjoint(G, "f32s", out=A)
+            if cfg is synth.FP32:
+                for _ in range(3):
+                    p.estimate(A, "f32s", out=G)
+            torch.cuda.synchronize()
+            del G, A
+    print(json.dumps({"adjoint_probe": True}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -986,6 +1048,9 @@ def main():
         return
     if args.pmc_probe:
         pmc_probe(torch)
+        return
+    if args.adjoint_probe:
+        adjoint_probe(torch)
         return
     out, ctx = headline(torch, args)
     if not args.no_cpu:

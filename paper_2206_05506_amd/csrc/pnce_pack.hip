@@ -120,24 +120,21 @@ __global__ __launch_bounds__(256) void finalize_scale_kernel(float *scales, int 
     scales[b] = scale_from_maxbits(__builtin_bit_cast(uint32_t, scales[b]), target);
 }
 
-// float -> OCP e4m3fn code, round to nearest even, saturating at +-448;
-// NaN -> 0x7F with the sign bit.
-__device__ __forceinline__ uint32_t e4m3_code(float x) {
-  const uint32_t u = __builtin_bit_cast(uint32_t, x);
-  const uint32_t sign = (u >> 24) & 0x80u;
-  const float ax = fabsf(x);
-  if (ax != ax) return sign | 0x7Fu;
-  if (ax >= 448.0f) return sign | 0x7Eu;
-  if (ax < 0.015625f) {  // below 2^-6: subnormal grid of step 2^-9
-    return sign | (uint32_t)__builtin_rintf(ax * 512.0f);
-  }
-  int E = (int)((__builtin_bit_cast(uint32_t, ax) >> 23) & 0xFF) - 127;  // -6 .. 8
-  uint32_t q = (uint32_t)__builtin_rintf(ldexpf(ax, 3 - E));              // 8 .. 16
-  if (q == 16u) {
-    q = 8u;
-    ++E;
-  }
-  return sign | ((uint32_t)(E + 7) << 3) | (q - 8u);
+// Two values to OCP e4m3fn codes (a in bits 0-7, b in bits 8-15), round to
+// nearest even, saturating at +-448, NaN to 0x7F with its sign. The
+// hardware conversion (v_cvt_pk_fp8_f32) rounds every finite value of
+// magnitude up to 448 exactly so (subnormals included; checked against the
+// e4m3fn grid on the whole bf16 range and at every rounding midpoint) but
+// does not saturate, so values beyond +-448 (and infinities) are clamped
+// first and NaN lanes are patched after.
+__device__ __forceinline__ uint32_t e4m3_pair(float a, float b) {
+  const float ca = __builtin_fminf(__builtin_fmaxf(a, -448.0f), 448.0f);
+  const float cb = __builtin_fminf(__builtin_fmaxf(b, -448.0f), 448.0f);
+  uint32_t r = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(ca, cb, 0, false) & 0xFFFFu;
+  if (a != a) r = (r & 0xFF00u) | 0x7Fu | ((__builtin_bit_cast(uint32_t, a) >> 24) & 0x80u);
+  if (b != b)
+    r = (r & 0x00FFu) | ((0x7Fu | ((__builtin_bit_cast(uint32_t, b) >> 24) & 0x80u)) << 8);
+  return r;
 }
 
 // Four consecutive samples n0 .. n0+3 of one padded output row (those at
@@ -150,14 +147,12 @@ template <int FMT>
 __device__ __forceinline__ void store_quad(const f2a8 (&v)[4], void *yq, size_t o, int valid,
                                            int Np, float inv) {
   if constexpr (FMT == 3) {
-    uint32_t cr = 0u, ci = 0u;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (u < valid) {
-        cr |= e4m3_code(v[u].x * inv) << (8 * u);
-        ci |= e4m3_code(v[u].y * inv) << (8 * u);
-      }
-    }
+    // samples at or past `valid` are zero and encode as 0
+    (void)valid;
+    const uint32_t cr = e4m3_pair(v[0].x * inv, v[1].x * inv) |
+                        (e4m3_pair(v[2].x * inv, v[3].x * inv) << 16);
+    const uint32_t ci = e4m3_pair(v[0].y * inv, v[1].y * inv) |
+                        (e4m3_pair(v[2].y * inv, v[3].y * inv) << 16);
     uint8_t *q = (uint8_t *)yq;
     *(uint32_t *)(q + o) = cr;
     *(uint32_t *)(q + o + Np) = ci;
