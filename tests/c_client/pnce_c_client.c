@@ -8,8 +8,11 @@
  *        adjoint        in: G [batch][R][T*L], out: A = G P^T / N [batch][R][N]
  *        packed:FMT     pnce_pack to format FMT (1 bf16, 2 f16, 3 e4m3), then
  *                       pnce_estimate_packed; in: Y, out: H
+ *        packedws:FMT   the same with pnce_pack_ws and a workspace of
+ *                       PNCE_PACK_WORK_BYTES(batch) bytes
  *        refine:STEPS   FP32-accurate estimate, then STEPS refinement steps;
  *                       in: Y, out: the refined H
+ *        refinena:STEPS the same with pnce_refine_noalloc (no workspace)
  * Exit status: 0 on success; 2 for usage or I/O errors; 3 for a HIP error;
  * otherwise 10 - (the failing pnce status).
  */
@@ -42,8 +45,12 @@ int main(int argc, char **argv)
     const unsigned feedback = (unsigned)strtoul(argv[7], NULL, 0);
     const char *op = argc == 12 ? argv[11] : "estimate";
     const int adjoint = strcmp(op, "adjoint") == 0;
-    const int fmt = strncmp(op, "packed:", 7) == 0 ? atoi(op + 7) : 0;
-    const int steps = strncmp(op, "refine:", 7) == 0 ? atoi(op + 7) : -1;
+    const int ws = strncmp(op, "packedws:", 9) == 0;
+    const int fmt = strncmp(op, "packed:", 7) == 0 ? atoi(op + 7) : (ws ? atoi(op + 9) : 0);
+    const int noalloc = strncmp(op, "refinena:", 9) == 0;
+    const int steps = strncmp(op, "refine:", 7) == 0 ? atoi(op + 7)
+                      : noalloc                        ? atoi(op + 9)
+                                                       : -1;
     if (!adjoint && !fmt && steps < 0 && strcmp(op, "estimate") != 0) {
         fprintf(stderr, "unknown op %s\n", op);
         return 2;
@@ -71,13 +78,17 @@ int main(int argc, char **argv)
         hipMalloc(&dout, nout) != hipSuccess ||
         (fmt && (hipMalloc(&dq, nq) != hipSuccess ||
                  hipMalloc((void **)&dscale, (size_t)B * sizeof(float)) != hipSuccess)) ||
-        (steps > 0 && hipMalloc(&dwork, ny) != hipSuccess) ||
+        (steps > 0 && !noalloc && hipMalloc(&dwork, ny) != hipSuccess) ||
+        (ws && hipMalloc(&dwork, PNCE_PACK_WORK_BYTES(B)) != hipSuccess) ||
         hipMemcpyAsync(din, hin, nin, hipMemcpyHostToDevice, s) != hipSuccess)
         return 3;
     if (adjoint) {
         rc = check(pnce_adjoint(plan, s, din, dout, NULL, B, prec, 1.0 / N, 0.0), "pnce_adjoint");
     } else if (fmt) {
-        rc = check(pnce_pack(plan, s, din, dq, dscale, B, fmt), "pnce_pack");
+        rc = ws ? check(pnce_pack_ws(plan, s, din, 0, dq, dscale, B, fmt, dwork,
+                                     PNCE_PACK_WORK_BYTES(B)),
+                        "pnce_pack_ws")
+                : check(pnce_pack(plan, s, din, dq, dscale, B, fmt), "pnce_pack");
         if (!rc)
             rc = check(pnce_estimate_packed(plan, s, dq, dscale, dout, B, fmt, 0.0),
                        "pnce_estimate_packed");
@@ -85,7 +96,9 @@ int main(int argc, char **argv)
         rc = check(pnce_estimate(plan, s, din, dout, B, PNCE_PREC_F32S, 1.0 / N, NULL, 0.0),
                    "pnce_estimate");
         if (!rc)
-            rc = check(pnce_refine(plan, s, din, dout, dwork, B, steps), "pnce_refine");
+            rc = noalloc ? check(pnce_refine_noalloc(plan, s, din, dout, B, steps),
+                                 "pnce_refine_noalloc")
+                         : check(pnce_refine(plan, s, din, dout, dwork, B, steps), "pnce_refine");
     } else {
         rc = check(pnce_estimate(plan, s, din, dout, B, prec, 1.0 / N, NULL, 0.0),
                    "pnce_estimate");

@@ -1,6 +1,7 @@
 """The C ABI from a plain C program (tests/c_client): plan, device buffers
-and one operation (correlator, adjoint, quantise + packed correlator, or
-refinement) with no Python in the process; its output checked against the
+and one operation (correlator, adjoint, quantise with or without a
+workspace + packed correlator, or refinement with a workspace or with the
+library's fixed array) with no Python in the process; its output checked against the
 FP64 oracle, and its error statuses."""
 import os
 import subprocess
@@ -64,11 +65,12 @@ def test_c_client_adjoint(tmp_path):
     assert perr(A, oracle.adjoint(G, oracle.mseq(8))) <= 1e-5
 
 
+@pytest.mark.parametrize("op", ["packed", "packedws"])
 @pytest.mark.parametrize("fmt,name", [(1, "bf16"), (2, "f16"), (3, "e4m3")])
-def test_c_client_pack_and_packed_estimate(tmp_path, fmt, name):
+def test_c_client_pack_and_packed_estimate(tmp_path, fmt, name, op):
     N, T, L, R, B = SMALL
     y = (synth.gaussian((B, R, N), 43) * 3.0).astype(np.complex64)
-    p, fout = _run([N, T, L, R, B, 1, 0, 0], tmp_path, y, f"packed:{fmt}")
+    p, fout = _run([N, T, L, R, B, 1, 0, 0], tmp_path, y, f"{op}:{fmt}")
     assert p.returncode == 0, p.stderr
     H = np.fromfile(fout, dtype=np.complex64).reshape(B, R, T * L)
     codes, scales = oracle.quantize(y, name)
@@ -76,10 +78,11 @@ def test_c_client_pack_and_packed_estimate(tmp_path, fmt, name):
     assert perr(H, oracle.correlate(x, oracle.mseq(8), T * L)) <= 1e-5
 
 
-def test_c_client_refine(tmp_path):
+@pytest.mark.parametrize("op", ["refine", "refinena"])
+def test_c_client_refine(tmp_path, op):
     N, T, L, R, B = SMALL
     y = synth.gaussian((B, R, N), 44).astype(np.complex64)
-    p, fout = _run([N, T, L, R, B, 1, 0, 0], tmp_path, y, "refine:3")
+    p, fout = _run([N, T, L, R, B, 1, 0, 0], tmp_path, y, f"{op}:3")
     assert p.returncode == 0, p.stderr
     X = np.fromfile(fout, dtype=np.complex64).reshape(B, R, T * L)
     its = oracle.refine(y.astype(np.complex128), oracle.mseq(8), T * L, 3)

@@ -617,6 +617,28 @@ def test_pack_single_read_path_precision_frames(fmt):
     assert np.array_equal(q0.view(ref_q.dtype), ref_q)
 
 
+def test_pack_frames_too_large_for_slices_fall_back():
+    """A frame of 2048 x 4095 samples (67 MB, 512 slices: more than half of
+    what the chip holds at once) cannot be gathered in registers; the call
+    with a workspace then takes the two-pass path and still writes the
+    oracle's codes and scale."""
+    from paper_2206_05506_amd import _lib
+    N, R, B = 4095, 2048, 1
+    g = torch.Generator(device="cuda")
+    g.manual_seed(43)
+    with _plan(N, 1, 1, R) as p:
+        y = torch.complex(torch.randn((B, R, N), generator=g, device="cuda"),
+                          torch.randn((B, R, N), generator=g, device="cuda")).contiguous()
+        y *= 3.0e-3
+        work = torch.full(((_lib.pack_work_bytes(B) + 3) // 4,), 7, dtype=torch.int32,
+                          device="cuda")
+        q, sc = p.pack(y, "bf16", work=work)
+        yh, qh, sh = host(y), host(q), host(sc)
+    ref_q, ref_sc = oracle.quantize(yh, "bf16")
+    assert np.array_equal(sh, ref_sc)
+    assert np.array_equal(qh.view(ref_q.dtype), ref_q)
+
+
 def test_pack_workspace_is_checked():
     """pnce_pack_ws refuses a missing, misaligned or short workspace before
     anything is enqueued."""
