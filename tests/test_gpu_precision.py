@@ -4,8 +4,11 @@ correlated with FP32 accumulation, then FP32 least-squares refinement.
 
 Checked against the FP64 oracle on sampled (frame, antenna) rows: the oracle
 iterate with the same step count k, started from the FP64 correlation of the
-original complex64 frame. Bars: FP32-accurate correlation <= 1e-5; bf16 and
-f16 + refinement <= 1e-5 after 5 steps; every format's error shrinks
+original complex64 frame. The quantiser's codes and scales of the first and
+last frames are bit-exact, and the packed estimates of their sampled rows
+match the oracle's correlation of the same dequantised codes (<= 1e-5).
+Bars: FP32-accurate correlation <= 1e-5; bf16 and f16 + refinement <= 1e-5
+after 5 steps; every format's error shrinks
 monotonically for the first steps. NMSE of the bf16 estimate (no refinement)
 against the true channels within 0.05 dB of the FP32-accurate estimate.
 """
@@ -56,6 +59,19 @@ def test_precision_study_full_workload():
             q, sc = p.pack(y, fmt)
             X0 = p.estimate_packed(q, sc, fmt)
             nmse[fmt] = _nmse_db(X0, h)
+            # the launches the benchmark times, at full size: codes and
+            # scales of the first and last frames bit-exact, and the packed
+            # correlation of their sampled rows against the oracle's
+            # correlation of the same dequantised codes
+            for b in (0, cfg.B - 1):
+                ref_q, ref_s = oracle.quantize(host(y[b:b + 1]), fmt)
+                assert np.array_equal(host(sc[b:b + 1]), ref_s), (fmt, b)
+                assert np.array_equal(host(q[b:b + 1]).view(ref_q.dtype), ref_q), (fmt, b)
+                x = oracle.dequantize(ref_q, ref_s, fmt, cfg.N)
+                for bb, r in ROWS:
+                    if bb == b:
+                        got = host(X0[b, r])[None, None]
+                        assert perr(got, oracle.correlate(x[:, r:r + 1], s, cfg.K)) <= 1e-5
             errs = []
             for k in range(6):
                 X = X0.clone()
