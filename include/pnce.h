@@ -196,7 +196,7 @@ pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y,
  * before it; 4 KiB per frame keeps the frames' synchronisation words on
  * separate memory channels); concurrent calls need separate workspaces.
  * After the call has run, the 32-bit word at index 1024 * batch of work
- * (the last one) is nonzero only if a
+ * (the last one; every launch plan writes it) is nonzero only if a
  * slice's wait for the rest of its frame ran past its bound (about a second;
  * never expected: the launch is sized so that a frame's workgroups run
  * together); the codes of that call are then not valid.

@@ -120,8 +120,10 @@ hipError_t launch_tg_frame(int in_fmt, int nc, const TgArgs &a, hipStream_t s);
 // launches. Both give the same codes and scales.
 constexpr int kPackFrameBatch = 256;
 constexpr long long kPackFrameMaxBytes = 1LL << 20;
+// flag (may be null): a word set to 0 by the launch (the wait flag of the
+// workspace path, which these launches do not wait on).
 hipError_t launch_pack(const float *y, void *yq, float *scales, int batch,
-                       int R, int N, int ld, int fmt, hipStream_t s);
+                       int R, int N, int ld, int fmt, hipStream_t s, uint32_t *flag = nullptr);
 // Same codes and scales with a workspace of kPackSyncWords * batch + 1
 // words (PNCE_PACK_WORK_BYTES): frames that the one-launch path does not
 // take are read from HBM once, in slices held in registers while the frame

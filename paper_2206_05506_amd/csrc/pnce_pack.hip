@@ -114,10 +114,11 @@ __global__ __launch_bounds__(256) void frame_max_rows_kernel(const f2a8 *y, uint
 
 // Max bits -> power-of-two scale, in place, once every pack block has read them.
 __global__ __launch_bounds__(256) void finalize_scale_kernel(float *scales, int batch,
-                                                             float target) {
+                                                             float target, uint32_t *flag) {
   const int b = blockIdx.x * 256 + threadIdx.x;
   if (b < batch)
     scales[b] = scale_from_maxbits(__builtin_bit_cast(uint32_t, scales[b]), target);
+  if (flag && b == 0) *flag = 0u;  // nothing waited (see pack_slices_kernel)
 }
 
 // Two values to OCP e4m3fn codes (a in bits 0-7, b in bits 8-15), round to
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const f2a8 *y, void *yq, cons
 constexpr int kPackFrameThreads = 1024;
 template <int FMT>
 __global__ __launch_bounds__(kPackFrameThreads) void pack_frame_kernel(
-    const f2a8 *y, void *yq, float *scales, int R, int N, int ld, float target) {
+    const f2a8 *y, void *yq, float *scales, int R, int N, int ld, float target, uint32_t *flag) {
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
   const f2a8 *f = y + (size_t)b * R * ld;
@@ -260,12 +261,13 @@ __global__ __launch_bounds__(kPackFrameThreads) void pack_frame_kernel(
     pack_quad<FMT>(f + (size_t)r * ld, yq, (size_t)row * 2 * Np, n0, N, Np, inv);
   }
   if (tid == 0) scales[b] = scale;
+  if (flag && b == 0 && tid == 0) *flag = 0u;  // nothing waited (see pack_slices_kernel)
 }
 
 // scales doubles as the per-frame max word until the last launch turns it
 // into the scale, so the four launches must stay in this order on one stream.
 hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R, int N,
-                       int ld, int fmt, hipStream_t s) {
+                       int ld, int fmt, hipStream_t s, uint32_t *flag) {
   if (fmt < 1 || fmt > 3) return hipErrorInvalidValue;
   const float target = (fmt == 3) ? 448.0f : 1.0f;
   if (batch >= kPackFrameBatch && (long long)R * ld * 8 <= kPackFrameMaxBytes) {
@@ -273,13 +275,13 @@ hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R
     const f2a8 *yc = (const f2a8 *)y;
     if (fmt == 1)
       hipLaunchKernelGGL((pack_frame_kernel<1>), grid, block, 0, s, yc, yq, scales, R, N, ld,
-                         target);
+                         target, flag);
     else if (fmt == 2)
       hipLaunchKernelGGL((pack_frame_kernel<2>), grid, block, 0, s, yc, yq, scales, R, N, ld,
-                         target);
+                         target, flag);
     else
       hipLaunchKernelGGL((pack_frame_kernel<3>), grid, block, 0, s, yc, yq, scales, R, N, ld,
-                         target);
+                         target, flag);
     return hipGetLastError();
   }
   uint32_t *mb = (uint32_t *)scales;
@@ -306,7 +308,7 @@ hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R
     hipLaunchKernelGGL((pack_kernel<3>), grid, dim3(256), 0, s, yc, yq, mb, R, N, ld, target,
                        total);
   hipLaunchKernelGGL(finalize_scale_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, scales,
-                     batch, target);
+                     batch, target, flag);
   return hipGetLastError();
 }
 
@@ -478,20 +480,20 @@ hipError_t launch_pack_ws(const float *y, void *yq, float *scales, uint32_t *wor
                           int R, int N, int ld, int fmt, hipStream_t s) {
   if (fmt < 1 || fmt > 3) return hipErrorInvalidValue;
   const bool small_frames = (long long)R * ld * 8 <= kPackFrameMaxBytes;
+  uint32_t *err = work + (size_t)kPackSyncWords * batch;
   if (batch >= kPackFrameBatch && small_frames)
-    return launch_pack(y, yq, scales, batch, R, N, ld, fmt, s);
+    return launch_pack(y, yq, scales, batch, R, N, ld, fmt, s, err);
   const int slices = pack_slices_per_frame(R, N);
   const int cap = slice_capacity(fmt);
   if (cap <= 0 || slices > cap / 2 || slices > kPackSyncWords ||
       (long long)slices * batch > 0x7FFFFFFFLL)
-    return launch_pack(y, yq, scales, batch, R, N, ld, fmt, s);
+    return launch_pack(y, yq, scales, batch, R, N, ld, fmt, s, err);
   const float target = (fmt == 3) ? 448.0f : 1.0f;
   const long zero_n = (long)batch * slices + 1;
   hipLaunchKernelGGL(zero_sync_kernel, dim3((unsigned)((zero_n + 255) / 256)), dim3(256), 0, s,
                      work, batch, slices);
   const dim3 grid((unsigned)(slices * batch)), block(kSliceThreads);
   const f2a8 *yc = (const f2a8 *)y;
-  uint32_t *err = work + (size_t)kPackSyncWords * batch;
   if (fmt == 1)
     hipLaunchKernelGGL((pack_slices_kernel<1, kSliceQuads, kSliceThreads>), grid, block, 0, s,
                        yc, yq, scales, work, err, R, N, ld, target, slices, kSpinLimit);

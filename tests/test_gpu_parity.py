@@ -533,7 +533,9 @@ def test_pack_one_launch_path_bit_exact(fmt, N, R, cp):
     raw = np.concatenate([y[:, :, N - cp:], y], axis=2) if cp else y
     with _plan(N, 1, 1, R) as p:
         yd = dev(raw)
-        q, sc = (p.pack_cp(yd, cp, fmt) if cp else p.pack(yd, fmt))
+        work = torch.full((1024 * B + 1,), 5, dtype=torch.int32, device="cuda")
+        q, sc = p.pack_cp(yd, cp, fmt, work=work)
+        assert int(host(work)[1024 * B]) == 0   # written by every launch plan
         part = yd[:B - 1].contiguous()
         q4, sc4 = (p.pack_cp(part, cp, fmt) if cp else p.pack(part, fmt))
         q2, sc2 = p.pack_cp_two_pass(yd, cp, fmt)
@@ -634,6 +636,8 @@ def test_pack_frames_too_large_for_slices_fall_back():
                           device="cuda")
         q, sc = p.pack(y, "bf16", work=work)
         yh, qh, sh = host(y), host(q), host(sc)
+        flag = int(host(work)[1024 * B])
+    assert flag == 0   # written by every launch plan
     ref_q, ref_sc = oracle.quantize(yh, "bf16")
     assert np.array_equal(sh, ref_sc)
     assert np.array_equal(qh.view(ref_q.dtype), ref_q)
