@@ -185,12 +185,15 @@ pnce_status pnce_pack(const pnce_plan *plan, void *stream, const void *Y,
 
 /*
  * pnce_pack_cp (cp = 0: pnce_pack) with a workspace from the caller, which
- * lets every frame be read from HBM once: frames above 1 MiB (and batches
- * under 256 frames) are cut into slices held in registers by consecutive
- * workgroups until the frame's maximum is gathered, then converted (one
- * launch after a clear of the workspace); the codes and scales equal
- * pnce_pack's. Batches of 256+ frames of at most 1 MiB take pnce_pack's
- * one-launch path and leave work unused.
+ * lets every frame be read from HBM once (the conversion to half precision
+ * ahead of the correlation, Section III-B): frames above 1 MiB (and batches
+ * under 256 frames) are cut into slices of 16,384 samples held in registers
+ * by consecutive workgroups until the frame's maximum is gathered, then
+ * converted (one launch after a clear of the workspace); the codes and
+ * scales equal pnce_pack's. Batches of 256+ frames of at most 1 MiB take
+ * pnce_pack's one-launch path, and frames of more than half as many slices
+ * as the GPU holds workgroups at once (about 4 million samples on MI355X)
+ * its two-pass path; both leave work unused but for the flag below.
  * work: device memory of at least PNCE_PACK_WORK_BYTES(batch) bytes, 4-byte
  * aligned, owned by the caller, overwritten by the call (no content needed
  * before it; 4 KiB per frame keeps the frames' synchronisation words on

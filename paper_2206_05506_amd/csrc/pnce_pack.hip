@@ -11,10 +11,12 @@
 //  - one workgroup per frame (batches of 256+ frames of at most 1 MiB): the
 //    frame is read, reduced in LDS, and read again for the conversion, the
 //    second read served by the Infinity Cache;
-//  - slices of a frame at consecutive workgroups (frames above 1 MiB, given
-//    a workspace): one HBM read, the slice held in registers until the
+//  - slices of a frame at consecutive workgroups (every other batch, when the
+//    caller gives a workspace and a frame's slices fit half of what the chip
+//    holds at once): one HBM read, the slice held in registers until the
 //    frame's maximum is known (pack_slices_kernel);
-//  - a per-frame max pass then a conversion pass (everything else).
+//  - a per-frame max pass then a conversion pass (no workspace, or frames too
+//    large for the slices).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
