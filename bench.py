@@ -81,6 +81,9 @@ def parse():
                          "shape (256 frames, T*L=512 -> N=1023) and on the differentiation shape "
                          "(1024 frames, T*L=1024 -> N=1023), and of the FP32-accurate estimate of "
                          "the FP32-baseline shape, for rocprofv3 counters")
+    ap.add_argument("--varlen-probe", action="store_true",
+                    help="only 3 persistent launches of the 4096-frame uneven batch (default "
+                         "schedule) and 3 plain copies of its code buffer, for rocprofv3 counters")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the adjoint/refinement/uneven-batch/front-end timings")
     ap.add_argument("--no-workloads", action="store_true",
@@ -1033,6 +1036,30 @@ def adjoint_probe(torch):
     print(json.dumps({"adjoint_probe": True}), flush=True)
 
 
+def varlen_probe(torch):
+    """Three persistent launches of the uneven batch and three plain copies
+    of its code buffer (the counters' calibration), nothing timed."""
+    import synth
+    from paper_2206_05506_amd import VarlenPlan
+    shapes = [(int(R), (1 << int(d)) - 1, int(T), int(L))
+              for R, d, T, L in synth.varlen_shapes(4096, 3)]
+    vp = VarlenPlan(shapes)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    Yq = torch.randn((vp.n_codes,), generator=g, device="cuda").to(torch.bfloat16)
+    Yq = Yq.view(torch.int16).contiguous()
+    H = torch.empty((vp.n_out,), dtype=torch.complex64, device="cuda")
+    for _ in range(3):
+        vp.estimate(Yq, None, out=H)
+    Y2 = torch.empty_like(Yq)
+    for _ in range(3):
+        Y2.copy_(Yq)
+    torch.cuda.synchronize()
+    print(json.dumps({"varlen_probe": True, "code_bytes": vp.n_codes * 2,
+                      "cir_bytes": vp.n_out * 8}), flush=True)
+    vp.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1051,6 +1078,9 @@ def main():
         return
     if args.adjoint_probe:
         adjoint_probe(torch)
+        return
+    if args.varlen_probe:
+        varlen_probe(torch)
         return
     out, ctx = headline(torch, args)
     if not args.no_cpu:
