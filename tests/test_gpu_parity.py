@@ -643,6 +643,44 @@ def test_pack_frames_too_large_for_slices_fall_back():
     assert np.array_equal(qh.view(ref_q.dtype), ref_q)
 
 
+def test_pack_workspace_path_under_graph_capture():
+    """pnce_pack_ws (slices gathered through the workspace, cleared by a fill
+    kernel, no memset) captured in a HIP graph and replayed three times on new
+    frames, with eager work between the replays: every replay's codes and
+    scales equal the eager call's."""
+    N, T, L, R, B = 4095, 32, 64, 40, 3
+    g = torch.Generator(device="cuda")
+    g.manual_seed(47)
+
+    def frames(k):
+        return (torch.complex(torch.randn((B, R, N), generator=g, device="cuda"),
+                              torch.randn((B, R, N), generator=g, device="cuda"))
+                * (10.0 ** (k - 1))).contiguous()
+
+    with _plan(N, T, L, R) as p:
+        y = frames(0)
+        q, sc = p.pack(y, "bf16")
+        work = torch.empty((1024 * B + 1,), dtype=torch.int32, device="cuda")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            p.pack(y, "bf16", out=q, scales=sc, work=work)
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            p.pack(y, "bf16", out=q, scales=sc, work=work)
+        for k in range(3):
+            y.copy_(frames(k))
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            q2, sc2 = p.pack_two_pass(y, "bf16")
+            torch.cuda.synchronize()
+            assert torch.equal(q, q2) and torch.equal(sc, sc2), k
+            assert int(host(work)[1024 * B]) == 0
+        del graph
+
+
 def test_pack_workspace_is_checked():
     """pnce_pack_ws refuses a missing, misaligned or short workspace before
     anything is enqueued."""

@@ -73,3 +73,38 @@ def test_noalloc_refine_edge_cases():
             p.refine_noalloc(y, X, 1)
         assert e.value.status == PNCE_E_UNSUPPORTED
         assert torch.all(X == 3.0)
+
+
+def test_noalloc_refine_under_graph_capture():
+    """The callers this entry point is for: a HIP graph captured around it
+    (no allocation happens inside), replayed three times on new frames with
+    eager work and synchronisations between the replays; every replay equals
+    the eager pnce_refine of the same frames."""
+    from paper_2206_05506_amd import Plan
+    print("no-alloc refine under graph capture: N=1023 T=16 L=32 R=64 B=4 steps=2", flush=True)
+    with Plan(1023, 16, 32, 64) as p:
+        y = _frames(4, 64, 1023, 21)
+        X = p.estimate(y, "bf16")
+        p.refine_noalloc(y, X.clone(), 2)          # the scratch address is resolved eagerly
+        torch.cuda.synchronize()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            p.refine_noalloc(y, X.clone(), 2)
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            p.estimate(y, "bf16", out=X)
+            p.refine_noalloc(y, X, 2)
+        for k in range(3):
+            fresh = _frames(4, 64, 1023, 30 + k)
+            y.copy_(fresh)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            got = host(X)
+            ref = p.estimate(fresh, "bf16")
+            p.refine(fresh, ref, 2, work=torch.empty_like(fresh))
+            torch.cuda.synchronize()
+            assert perr(got, host(ref)) <= TOL, k
+        del graph
