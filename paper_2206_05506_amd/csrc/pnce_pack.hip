@@ -339,8 +339,9 @@ hipError_t launch_pack(const float *y, void *yq, float *scales, int batch, int R
 // such launch running beside it); the launch therefore takes this path only
 // when slices <= half of what the chip holds. The wait is still bounded
 // (spin_limit polls, one to two seconds): a workgroup that reaches the bound
-// sets *err and goes on with the slots it has seen, so a broken residency
-// assumption shows as a flag, not as a hang.
+// sets *err and goes on with the slots it has seen, and every other waiting
+// workgroup sees *err within 64 polls and goes on too, so a broken residency
+// assumption shows as a flag and a delay of one bound, not as a hang.
 // work: per frame a line of kPackSyncWords words whose first `slices` are
 // the slots (a line per frame also spreads the polls of the frames in
 // flight over memory channels), zeroed before the launch; err: one word,
@@ -416,6 +417,11 @@ __global__ __launch_bounds__(TH) void pack_slices_kernel(const f2a8 *y, void *yq
         if (tid == 0) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
+      // once any workgroup of the launch has given up, stop waiting too, so
+      // a launch is delayed by one bound at most, not one per frame
+      if ((polls & 63u) == 0u &&
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+        break;
       __builtin_amdgcn_s_sleep(16);
     }
     if (tid == 0) s_frame = fm;
