@@ -681,6 +681,47 @@ def test_pack_workspace_path_under_graph_capture():
         del graph
 
 
+def test_pack_workspace_path_random_shapes():
+    """120 seeded (N, R, batch, cyclic prefix, format) cases through the
+    quantiser with a workspace, spread over its three launch plans (slices
+    for most, one workgroup per frame and two passes for some): codes and
+    scales bit-exact against the two-pass path, the wait flag 0, and one
+    frame per case bit-exact against the oracle."""
+    import random
+    from paper_2206_05506_amd import _lib
+    rnd = random.Random(2206)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2206)
+    for case in range(120):
+        d = rnd.choice([2, 3, 5, 7, 8, 9, 10, 11, 12, 13])
+        N = (1 << d) - 1
+        R = rnd.choice([1, 2, 3, 31, 32, 33, 64, 100, 255])
+        B = rnd.choice([1, 2, 3, 5, 17])
+        if rnd.random() < 0.05:
+            B, R, N = 256, 4, 127             # the one-workgroup-per-frame plan
+        cp = rnd.choice([0, 0, 1, 7, 32])
+        fmt = rnd.choice(["bf16", "f16", "e4m3"])
+        scale = 10.0 ** rnd.uniform(-8, 8)
+        raw = (torch.complex(torch.randn((B, R, cp + N), generator=g, device="cuda"),
+                             torch.randn((B, R, cp + N), generator=g, device="cuda"))
+               * scale).contiguous()
+        with _plan(N, 1, 1, R) as p:
+            work = torch.full(((_lib.pack_work_bytes(B) + 3) // 4,), -1, dtype=torch.int32,
+                              device="cuda")
+            q, sc = p.pack_cp(raw, cp, fmt, work=work)
+            q2, sc2 = p.pack_cp_two_pass(raw, cp, fmt)
+            torch.cuda.synchronize()
+            where = (case, N, R, B, cp, fmt)
+            assert torch.equal(sc, sc2) and torch.equal(q, q2), where
+            assert int(host(work)[1024 * B]) == 0, where
+            f = rnd.randrange(B)
+            y = host(raw[f:f + 1, :, cp:].contiguous())
+            qh, sh = host(q[f:f + 1]), host(sc[f:f + 1])
+        ref_q, ref_sc = oracle.quantize(y, fmt)
+        assert np.array_equal(sh, ref_sc), where
+        assert np.array_equal(qh.view(ref_q.dtype), ref_q), where
+
+
 def test_pack_workspace_is_checked():
     """pnce_pack_ws refuses a missing, misaligned or short workspace before
     anything is enqueued."""
