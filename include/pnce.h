@@ -289,6 +289,38 @@ pnce_status pnce_pack_cp(const pnce_plan *plan, void *stream, const void *Y_raw,
                          void *Yq, float *scales, int batch, int format);
 
 /*
+ * pnce_estimate_cp on raw blocks that sit in host memory, with their copies
+ * to the device overlapped with the estimates (the host-to-device transfer
+ * that the frame latency of Section IV-C includes). Frames are taken in
+ * chunks of `chunk`: chunk i is copied on copy_stream into half (i & 1) of
+ * the staging buffer while chunk i - 1 is estimated on `stream`; events
+ * order each copy after the estimate that last read its half and each
+ * estimate after its copy. Every copy waits for the work already queued on
+ * `stream` when the call is made, and `stream` waits for every copy, so once
+ * `stream` reaches the end of this call's work, H is complete and staging and
+ * Y_host are free again. Results equal pnce_estimate_cp on the same frames
+ * bit for bit.
+ * Y_host: [frames][R][cp + N] complex64 (complex128 for PNCE_PREC_F64) in
+ *   host memory; page-locked (hipHostMalloc) for the copies to overlap, else
+ *   the runtime stages them and they do not. Must not change until `stream`
+ *   has finished this call's work.
+ * H: [frames][R][T*L] complex64 (complex128 for PNCE_PREC_F64), device.
+ * staging: device memory owned by the caller, 16-byte aligned, of at least
+ *   PNCE_HOST_STAGING_BYTES(R, N, cp, min(chunk, frames), precision) bytes;
+ *   its contents on return are unspecified.
+ * copy_stream may equal stream (the copies then do not overlap).
+ * Errors: PNCE_E_INVALID for chunk < 1, a NULL pointer with frames > 0 or a
+ * staging buffer that is too small; otherwise as for pnce_estimate_cp. An
+ * error after the first chunk was queued leaves H partly written.
+ */
+#define PNCE_HOST_STAGING_BYTES(R, N, cp, chunk, precision)                         \
+  (2 * (size_t)(chunk) * (size_t)(R) * ((size_t)(N) + (size_t)(cp)) *             \
+   ((precision) == PNCE_PREC_F64 ? 16 : 8))
+pnce_status pnce_estimate_host(const pnce_plan *plan, void *stream, void *copy_stream,
+                               const void *Y_host, int cp, void *H, int frames, int chunk,
+                               int precision, void *staging, size_t staging_bytes);
+
+/*
  * Least-squares CIRs in closed form. The two-level autocorrelation of the
  * sequence (Eq. 1) gives P^T P = (N+1) I - J (J all-ones, K = T*L <= N), so
  * (P^T P)^-1 = (I + J / (N+1-K)) / (N+1), and from correlator outputs

@@ -37,7 +37,7 @@ SYMBOLS = ("pnce_create", "pnce_create_ex", "pnce_destroy", "pnce_get_sequence",
            "pnce_get_lags", "pnce_get_feedback", "pnce_get_shape",
            "pnce_estimate", "pnce_pack", "pnce_estimate_packed", "pnce_adjoint",
            "pnce_refine", "pnce_refine_noalloc", "pnce_debias", "pnce_estimate_ls", "pnce_estimate_cp", "pnce_pack_cp",
-           "pnce_pack_ws",
+           "pnce_pack_ws", "pnce_estimate_host",
            "pnce_varlen_create", "pnce_varlen_destroy", "pnce_varlen_estimate",
            "pnce_varlen_estimate_each", "pnce_varlen_tune", "pnce_varlen_get_tuning",
            "pnce_varlen_set_tuning", "pnce_varlen_stats", "pnce_status_string",
@@ -84,6 +84,7 @@ def _load() -> ctypes.CDLL:
         "pnce_estimate_cp": ([_P, _P, _P, _I, _P, _I, _I, _P], _I),
         "pnce_pack_cp": ([_P, _P, _P, _I, _P, _P, _I, _I], _I),
         "pnce_pack_ws": ([_P, _P, _P, _I, _P, _P, _I, _I, _P, ctypes.c_size_t], _I),
+        "pnce_estimate_host": ([_P, _P, _P, _P, _I, _P, _I, _I, _I, _P, ctypes.c_size_t], _I),
         "pnce_varlen_create": ([ctypes.POINTER(_P), ctypes.POINTER(pnce_frame_desc), _I, _I],
                                _I),
         "pnce_varlen_destroy": ([_P], _I),
@@ -207,6 +208,18 @@ def pack_work_bytes(batch: int) -> int:
 def pnce_pack_ws(plan, stream, Y_raw, cp, Yq, scales, batch, fmt, work, work_bytes) -> int:
     return check(lib.pnce_pack_ws(plan, stream, Y_raw, cp, Yq, scales, batch, fmt, work,
                                   work_bytes), "pnce_pack_ws")
+
+
+def host_staging_bytes(R: int, N: int, cp: int, chunk: int, precision: int) -> int:
+    """PNCE_HOST_STAGING_BYTES(R, N, cp, chunk, precision) of include/pnce.h."""
+    return 2 * int(chunk) * int(R) * (int(N) + int(cp)) * (16 if precision == 3 else 8)
+
+
+def pnce_estimate_host(plan, stream, copy_stream, Y_host, cp, H, frames, chunk, precision,
+                       staging, staging_bytes) -> int:
+    return check(lib.pnce_estimate_host(plan, stream, copy_stream, Y_host, cp, H, frames, chunk,
+                                        precision, staging, staging_bytes),
+                 "pnce_estimate_host")
 
 
 def pnce_estimate_ls(plan, stream, Y, H, batch, precision, scales) -> int:

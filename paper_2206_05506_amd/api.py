@@ -28,6 +28,17 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
+_COPY_STREAMS = {}
+
+
+def _copy_stream(dev: torch.device):
+    """One copy stream per device for host-to-device staging (default
+    priority)."""
+    if dev.index not in _COPY_STREAMS:
+        _COPY_STREAMS[dev.index] = torch.cuda.Stream(device=dev)
+    return _COPY_STREAMS[dev.index]
+
+
 def _need_host(t: torch.Tensor, shape, dtype, name):
     if not isinstance(t, torch.Tensor) or t.is_cuda:
         raise ValueError(f"{name} must be a host tensor")
@@ -227,47 +238,42 @@ class Plan:
         return out, scales
 
     def stream_from_host(self, Y_host: torch.Tensor, cp: int, chunk: int,
-                         precision: str = "bf16", out=None) -> torch.Tensor:
-        """Estimate raw blocks that sit in pinned host memory
-        (Y_host [F, R, cp + N] complex64): chunks of `chunk` frames are copied
-        to the device on a copy stream while the previous chunk is estimated
-        on the current stream (two device buffers, events between them).
-        Returns H [F, R, T*L] on the device; the current stream carries the
-        last estimate."""
-        if not Y_host.is_pinned():
-            raise ValueError("Y_host must be in pinned host memory")
+                         precision: str = "bf16", out=None, copy_stream=None,
+                         staging=None) -> torch.Tensor:
+        """pnce_estimate_host: raw blocks in pinned host memory
+        (Y_host [F, R, cp + N] complex64, complex128 for "f64") are copied to
+        the device in chunks of `chunk` frames on copy_stream (default: one
+        library-held stream per device) while the previous chunk is estimated
+        on the current stream. Returns H [F, R, T*L] on the device; the
+        current stream carries the last estimate, and Y_host must stay
+        unchanged until it has run."""
         if int(chunk) < 1:
             raise ValueError("chunk must be >= 1")
+        prec = PRECISIONS[precision]
+        cdt = torch.complex128 if prec == PNCE_PREC_F64 else torch.complex64
         F = Y_host.shape[0]
-        _need_host(Y_host, (F, self.R, self.N + cp), torch.complex64, "Y_host")
+        _need_host(Y_host, (F, self.R, self.N + cp), cdt, "Y_host")
+        if F > 0 and not Y_host.is_pinned():   # (an empty tensor cannot be pinned)
+            raise ValueError("Y_host must be in pinned host memory")
         dev = torch.device("cuda", torch.cuda.current_device())
         if out is None:
-            out = torch.empty((F, self.R, self.K), dtype=torch.complex64, device=dev)
-        _need(out, (F, self.R, self.K), torch.complex64, "H")
-        compute = torch.cuda.current_stream()
-        copy = torch.cuda.Stream()
-        bufs = [torch.empty((chunk, self.R, self.N + cp), dtype=torch.complex64, device=dev)
-                for _ in range(2)]
-        # The staging buffers come from the compute stream's pool: a block
-        # freed there may still be read by kernels queued on it, so the first
-        # copies wait for everything already enqueued on the compute stream.
-        copy.wait_stream(compute)
-        copied = [torch.cuda.Event() for _ in range(2)]
-        used = [torch.cuda.Event() for _ in range(2)]
-        starts = list(range(0, F, chunk))
-        for i, f0 in enumerate(starts):
-            n = min(chunk, F - f0)
-            k = i & 1
-            with torch.cuda.stream(copy):
-                if i >= 2:
-                    copy.wait_event(used[k])  # the estimate that read buffer k is done
-                bufs[k][:n].copy_(Y_host[f0:f0 + n], non_blocking=True)
-                copied[k].record(copy)
-            compute.wait_event(copied[k])
-            self.estimate_cp(bufs[k][:n], cp, precision, out=out[f0:f0 + n])
-            used[k].record(compute)
-        for b in bufs:
-            b.record_stream(copy)  # written there; keep them until its work is done
+            out = torch.empty((F, self.R, self.K), dtype=cdt, device=dev)
+        _need(out, (F, self.R, self.K), cdt, "H")
+        per = max(1, min(int(chunk), F))
+        nbytes = _lib.host_staging_bytes(self.R, self.N, cp, per, prec)
+        if staging is None:
+            # Taken from the current stream's pool: the library orders every
+            # copy after the work already queued on this stream and this
+            # stream after every copy, so the block is free for this stream
+            # again once the call's estimates have run.
+            staging = torch.empty((nbytes,), dtype=torch.uint8, device=dev)
+        if staging.device != dev or staging.numel() * staging.element_size() < nbytes:
+            raise ValueError(f"staging must hold {nbytes} bytes on {dev}")
+        if copy_stream is None:
+            copy_stream = _copy_stream(dev)
+        _lib.pnce_estimate_host(self.handle, _stream(), copy_stream.cuda_stream, _ptr(Y_host),
+                                int(cp), _ptr(out), F, int(chunk), prec, _ptr(staging),
+                                staging.numel() * staging.element_size())
         return out
 
     def estimate_packed(self, Yq: torch.Tensor, scales, fmt: str = "bf16", out=None,

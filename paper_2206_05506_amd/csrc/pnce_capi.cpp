@@ -514,6 +514,77 @@ pnce_status pnce_pack_ws(const pnce_plan *plan, void *stream, const void *Y_raw,
   return PNCE_OK;
 }
 
+// Events of one pnce_estimate_host call: start (on the compute stream), and
+// per staging half "copied" (on the copy stream) and "read" (on the compute
+// stream). Destroyed when the call returns; the runtime keeps recorded events
+// alive until they complete.
+namespace {
+struct HostEvents {
+  hipEvent_t start = nullptr, copied[2] = {}, read[2] = {};
+  hipError_t create() {
+    hipEvent_t *all[5] = {&start, &copied[0], &copied[1], &read[0], &read[1]};
+    for (hipEvent_t *e : all)
+      if (hipError_t r = hipEventCreateWithFlags(e, hipEventDisableTiming)) return r;
+    return hipSuccess;
+  }
+  ~HostEvents() {
+    for (hipEvent_t e : {start, copied[0], copied[1], read[0], read[1]})
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+}  // namespace
+
+pnce_status pnce_estimate_host(const pnce_plan *plan, void *stream, void *copy_stream,
+                               const void *Y_host, int cp, void *H, int frames, int chunk,
+                               int precision, void *staging, size_t staging_bytes) {
+  if (pnce_status st = check_plan(plan)) return st;
+  if (pnce_status st = check_device(plan->device)) return st;
+  if (!valid_prec(precision)) return fail(PNCE_E_INVALID, "unknown precision");
+  if (pnce_status st = check_cp(plan, cp)) return st;
+  if (chunk < 1) return fail(PNCE_E_INVALID, "chunk must be >= 1");
+  if (frames == 0) return PNCE_OK;
+  if (!Y_host || !H || !staging)
+    return fail(PNCE_E_INVALID, "Y_host, H and staging must be non-NULL");
+  if (pnce_status st = check_batch(plan, frames)) return st;
+  if (pnce_status st = check_batch(plan, chunk)) return st;
+  const size_t esz = c_bytes(precision);
+  const size_t fbytes = (size_t)plan->R * (size_t)(plan->N + cp) * esz;
+  const int per = chunk < frames ? chunk : frames;  // frames per staging half
+  if (staging_bytes / 2 / fbytes < (size_t)per)
+    return fail(PNCE_E_INVALID, "staging is smaller than 2 * min(chunk, frames) raw frames");
+  if (pnce_status st = check_align(staging, 16, "staging")) return st;
+  if (pnce_status st = check_align(H, esz, "H")) return st;
+  hipStream_t s = (hipStream_t)stream, cs = (hipStream_t)copy_stream;
+  HostEvents ev;
+  if (hipError_t e = ev.create()) return hip_fail(e, "hipEventCreateWithFlags");
+  // The copies may overwrite staging only after the work already queued on
+  // the compute stream (an earlier call's estimates may still read it).
+  if (hipError_t e = hipEventRecord(ev.start, s)) return hip_fail(e, "hipEventRecord");
+  if (hipError_t e = hipStreamWaitEvent(cs, ev.start, 0)) return hip_fail(e, "hipStreamWaitEvent");
+  const size_t obytes = (size_t)plan->R * plan->K * esz;
+  for (int i = 0, f0 = 0; f0 < frames; ++i, f0 += per) {
+    const int n = per < frames - f0 ? per : frames - f0;
+    const int k = i & 1;
+    char *buf = (char *)staging + (size_t)k * per * fbytes;
+    if (i >= 2) {  // half k was last read by the estimate of chunk i - 2
+      if (hipError_t e = hipStreamWaitEvent(cs, ev.read[k], 0))
+        return hip_fail(e, "hipStreamWaitEvent");
+    }
+    if (hipError_t e = hipMemcpyAsync(buf, (const char *)Y_host + (size_t)f0 * fbytes,
+                                      (size_t)n * fbytes, hipMemcpyHostToDevice, cs))
+      return hip_fail(e, "hipMemcpyAsync");
+    if (hipError_t e = hipEventRecord(ev.copied[k], cs)) return hip_fail(e, "hipEventRecord");
+    if (hipError_t e = hipStreamWaitEvent(s, ev.copied[k], 0))
+      return hip_fail(e, "hipStreamWaitEvent");
+    if (pnce_status st = run_fwd(plan, s, precision, pnce::IN_C64, buf + (size_t)cp * esz,
+                                 plan->N, plan->N + cp, (char *)H + (size_t)f0 * obytes,
+                                 nullptr, nullptr, n, 1.0 / plan->N, 0.0))
+      return st;
+    if (hipError_t e = hipEventRecord(ev.read[k], s)) return hip_fail(e, "hipEventRecord");
+  }
+  return PNCE_OK;
+}
+
 pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream, const void *Yq,
                                  const float *scales, void *H, int batch, int format,
                                  double beta) {

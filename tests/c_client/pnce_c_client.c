@@ -13,6 +13,9 @@
  *        refine:STEPS   FP32-accurate estimate, then STEPS refinement steps;
  *                       in: Y, out: the refined H
  *        refinena:STEPS the same with pnce_refine_noalloc (no workspace)
+ *        host:CHUNK:CP  pnce_estimate_host from page-locked host memory in
+ *                       chunks of CHUNK frames on a second stream; in: raw
+ *                       blocks [batch][R][CP + N], out: H
  * Exit status: 0 on success; 2 for usage or I/O errors; 3 for a HIP error;
  * otherwise 10 - (the failing pnce status).
  */
@@ -51,13 +54,25 @@ int main(int argc, char **argv)
     const int steps = strncmp(op, "refine:", 7) == 0 ? atoi(op + 7)
                       : noalloc                        ? atoi(op + 9)
                                                        : -1;
-    if (!adjoint && !fmt && steps < 0 && strcmp(op, "estimate") != 0) {
+    int chunk = 0, cp = 0;
+    const int from_host = strncmp(op, "host:", 5) == 0;
+    if (from_host && (sscanf(op + 5, "%d:%d", &chunk, &cp) != 2 || cp < 0)) {
+        fprintf(stderr, "bad op %s\n", op);
+        return 2;
+    }
+    if (!adjoint && !fmt && steps < 0 && !from_host && strcmp(op, "estimate") != 0) {
         fprintf(stderr, "unknown op %s\n", op);
         return 2;
     }
-    const size_t ny = (size_t)B * R * N * 8, nh = (size_t)B * R * T * L * 8;
+    const size_t ny = (size_t)B * R * (N + cp) * 8, nh = (size_t)B * R * T * L * 8;
     const size_t nin = adjoint ? nh : ny, nout = adjoint ? ny : nh;
-    void *hin = malloc(nin), *hout = malloc(nout);
+    void *hin = NULL, *hout = malloc(nout);
+    if (from_host) {
+        if (hipHostMalloc(&hin, nin, hipHostMallocDefault) != hipSuccess)
+            return 3;
+    } else {
+        hin = malloc(nin);
+    }
     FILE *f = fopen(argv[9], "rb");
     if (!hin || !hout || !f || fread(hin, 1, nin, f) != nin) {
         fprintf(stderr, "cannot read %s\n", argv[9]);
@@ -73,16 +88,22 @@ int main(int argc, char **argv)
     const size_t nq = (size_t)B * R * 2 * (N + 1) * (fmt == 3 ? 1 : 2);
     void *din = NULL, *dout = NULL, *dq = NULL, *dwork = NULL;
     float *dscale = NULL;
-    hipStream_t s;
-    if (hipStreamCreate(&s) != hipSuccess || hipMalloc(&din, nin) != hipSuccess ||
+    hipStream_t s, cs = NULL;
+    const int per = chunk < B ? chunk : B;
+    const size_t nstage = from_host ? PNCE_HOST_STAGING_BYTES(R, N, cp, per, prec) : 0;
+    if (hipStreamCreate(&s) != hipSuccess || hipMalloc(&din, from_host ? nstage : nin) != hipSuccess ||
+        (from_host && hipStreamCreate(&cs) != hipSuccess) ||
         hipMalloc(&dout, nout) != hipSuccess ||
         (fmt && (hipMalloc(&dq, nq) != hipSuccess ||
                  hipMalloc((void **)&dscale, (size_t)B * sizeof(float)) != hipSuccess)) ||
         (steps > 0 && !noalloc && hipMalloc(&dwork, ny) != hipSuccess) ||
         (ws && hipMalloc(&dwork, PNCE_PACK_WORK_BYTES(B)) != hipSuccess) ||
-        hipMemcpyAsync(din, hin, nin, hipMemcpyHostToDevice, s) != hipSuccess)
+        (!from_host && hipMemcpyAsync(din, hin, nin, hipMemcpyHostToDevice, s) != hipSuccess))
         return 3;
-    if (adjoint) {
+    if (from_host) {
+        rc = check(pnce_estimate_host(plan, s, cs, hin, cp, dout, B, chunk, prec, din, nstage),
+                   "pnce_estimate_host");
+    } else if (adjoint) {
         rc = check(pnce_adjoint(plan, s, din, dout, NULL, B, prec, 1.0 / N, 0.0), "pnce_adjoint");
     } else if (fmt) {
         rc = ws ? check(pnce_pack_ws(plan, s, din, 0, dq, dscale, B, fmt, dwork,
@@ -121,7 +142,12 @@ int main(int argc, char **argv)
     (void)hipFree(dscale);
     (void)hipFree(dwork);
     (void)hipStreamDestroy(s);
-    free(hin);
+    if (cs)
+        (void)hipStreamDestroy(cs);
+    if (from_host)
+        (void)hipHostFree(hin);
+    else
+        free(hin);
     free(hout);
     return rc;
 }

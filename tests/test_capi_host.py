@@ -101,6 +101,9 @@ def test_null_plan_is_rejected_everywhere(lib):
     lib.pnce_pack_ws.argtypes = [P, P, P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P,
                                  ctypes.c_size_t]
     assert lib.pnce_pack_ws(None, None, None, 0, None, None, 1, 1, None, 0) == -1
+    lib.pnce_estimate_host.argtypes = [P, P, P, P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, P, ctypes.c_size_t]
+    assert lib.pnce_estimate_host(None, None, None, None, 0, None, 1, 1, 1, None, 0) == -1
     lib.pnce_debias.argtypes = [P, P, P, ctypes.c_int]
     assert lib.pnce_debias(None, None, None, 1) == -1
     lib.pnce_estimate_ls.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, P]

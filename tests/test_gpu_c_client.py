@@ -87,3 +87,16 @@ def test_c_client_refine(tmp_path, op):
     X = np.fromfile(fout, dtype=np.complex64).reshape(B, R, T * L)
     its = oracle.refine(y.astype(np.complex128), oracle.mseq(8), T * L, 3)
     assert perr(X, its[3]) <= 1e-5
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 8])
+def test_c_client_estimate_from_host(tmp_path, chunk):
+    """pnce_estimate_host from page-locked memory on a second stream, raw
+    blocks with a 16-sample prefix, 5 frames in chunks (the last ragged)."""
+    N, T, L, R, B, cp = 255, 4, 16, 40, 5, 16
+    yr = synth.gaussian((B, R, cp + N), 44).astype(np.complex64)
+    p, fout = _run([N, T, L, R, B, 1, 0, 0], tmp_path, yr, f"host:{chunk}:{cp}")
+    assert p.returncode == 0, p.stderr
+    H = np.fromfile(fout, dtype=np.complex64).reshape(B, R, T * L)
+    assert perr(H, oracle.correlate(yr[..., cp:].astype(np.complex128), oracle.mseq(8),
+                                    T * L)) <= 1e-5

@@ -63,13 +63,45 @@ def test_pack_cp_bit_exact(shape, fmt):
     assert np.array_equal(q.view(ref_q.dtype), ref_q)
 
 
-def test_stream_from_host_equals_device_estimate():
-    N, T, L, R, F, cp, chunk = 1023, 16, 32, 64, 40, 32, 16   # 3 chunks, the last ragged
-    y = synth.gaussian((F, R, N), 9).astype(np.complex64)
-    yr = _raw(y, cp, 5)
+@pytest.mark.parametrize("prec", ["bf16", "f32s", "f64"])
+@pytest.mark.parametrize("chunk", [16, 1, 64])   # ragged last chunk; one frame; one chunk
+def test_stream_from_host_equals_device_estimate(prec, chunk):
+    N, T, L, R, F, cp = 1023, 16, 32, 64, 40, 32
+    cdt = np.complex128 if prec == "f64" else np.complex64
+    y = synth.gaussian((F, R, N), 9).astype(cdt)
+    yr = _raw(y, cp, 5).astype(cdt)
     with _plan(N, T, L, R) as p:
         yh = torch.from_numpy(yr).pin_memory()
-        H = p.stream_from_host(yh, cp, chunk, "bf16")
-        Hd = p.estimate(dev(y), "bf16")
+        H = p.stream_from_host(yh, cp, chunk, prec)
+        Hd = p.estimate_cp(dev(yr, yh.dtype), cp, prec)
         torch.cuda.synchronize()
         assert torch.equal(H, Hd)
+        s = p.sequence()
+        Hh = host(H[::13])
+    x = bf16_round(y[::13]) if prec == "bf16" else y[::13].astype(np.complex128)
+    assert perr(Hh, oracle.correlate(x, s, T * L)) <= 1e-5
+
+
+def test_stream_from_host_back_to_back_reuses_staging():
+    """Two calls sharing one staging buffer and one copy stream, the second
+    with other frames and the copy stream equal to the compute stream: the
+    second call's copies must wait for the first call's estimates."""
+    N, T, L, R, cp, chunk = 255, 4, 32, 40, 8, 3
+    ya = synth.gaussian((7, R, N + cp), 11).astype(np.complex64)
+    yb = synth.gaussian((5, R, N + cp), 12).astype(np.complex64)
+    with _plan(N, T, L, R) as p:
+        staging = torch.empty((2 * chunk * R * (N + cp) * 8,), dtype=torch.uint8, device="cuda")
+        ha = torch.from_numpy(ya).pin_memory()
+        hb = torch.from_numpy(yb).pin_memory()
+        Ha = p.stream_from_host(ha, cp, chunk, "f32s", staging=staging)
+        Hb = p.stream_from_host(hb, cp, chunk, "f32s", staging=staging,
+                                copy_stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        assert torch.equal(Ha, p.estimate_cp(dev(ya), cp, "f32s"))
+        assert torch.equal(Hb, p.estimate_cp(dev(yb), cp, "f32s"))
+        with pytest.raises(ValueError):
+            p.stream_from_host(ha, cp, chunk, "f32s", staging=staging[:-1])
+        with pytest.raises(ValueError):
+            p.stream_from_host(ha, cp, 0, "f32s")
+        empty = torch.empty((0, R, N + cp), dtype=torch.complex64).pin_memory()
+        assert p.stream_from_host(empty, cp, chunk, "bf16").shape == (0, R, T * L)
