@@ -86,6 +86,18 @@ typedef int pnce_status;
                           /* checks; not a throughput path)                   */
 #define PNCE_PREC_F64ACC 4 /* c64 buffers, FP64 sums on FP64 matrix cores    */
                            /* (v_mfma_f64_16x16x4_f64), one rounding to FP32  */
+#define PNCE_PREC_EXACT 5  /* c64 buffers, exact sums: each input row in      */
+                           /* fixed point (62 bits below a power of two above */
+                           /* the row's largest |re| or |im|) cut into eight  */
+                           /* 8-bit digits, each digit's sum exact in int32   */
+                           /* on int8 matrix cores (v_mfma_i32_32x32x32_i8),  */
+                           /* combined and scaled in FP64; alpha and beta in  */
+                           /* FP64, one rounding to FP32. Exact for elements  */
+                           /* within 2^38 of their row's largest magnitude,   */
+                           /* smaller ones rounded at 2^-62 of the row bound; */
+                           /* at most 65535 terms per output (else            */
+                           /* PNCE_E_UNSUPPORTED); a row holding inf or NaN   */
+                           /* gives NaN outputs.                              */
 
 /* Reduced-precision storage formats of Y (the half-precision conversion
  * before correlation, Section III-B). */
@@ -160,7 +172,8 @@ pnce_status pnce_get_shape(const pnce_plan *plan, int *N, int *T, int *L, int *R
  * Y: [batch][R][N] c64 (c128 when precision == PNCE_PREC_F64);
  * H: [batch][R][T*L] c64 (c128 for PNCE_PREC_F64), read only if beta != 0;
  * scales: NULL or `batch` device floats. Y and H must not overlap.
- * precision: PNCE_PREC_F32, _F32S, _BF16, _F64 or _F64ACC.
+ * precision: PNCE_PREC_F32, _F32S, _BF16, _F64, _F64ACC or _EXACT (alpha and
+ * beta then in FP64).
  * Errors: null Y/H, batch < 0, unknown precision -> PNCE_E_INVALID.
  */
 pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y,
@@ -232,7 +245,8 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream,
  * the residual y - P h of the receive model of Eq. 9.
  * G: [batch][R][T*L]; A, C: [batch][R][N]; c64, or c128 for
  * PNCE_PREC_F64. C may equal A, or be NULL when beta == 0. G must not
- * overlap A. precision: PNCE_PREC_F32, _F32S, _BF16, _F64 or _F64ACC.
+ * overlap A. precision: PNCE_PREC_F32, _F32S, _BF16, _F64, _F64ACC or
+ * _EXACT (alpha and beta then in FP64).
  */
 pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
                          void *A, const void *C, int batch, int precision,
@@ -242,8 +256,10 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
  * Least-squares refinement of a CIR estimate (the correlator's bias floor
  * comes from the -1/M term of Eq. 1; each step removes part of it):
  *   repeat `steps` times:  r = y - P x;  x = x + P^T r / N.
- * Both contractions are FP32-accurate (PNCE_PREC_F32S); the residual of the
- * last step is accumulated in FP64 (PNCE_PREC_F64ACC).
+ * Both contractions are FP32-accurate (PNCE_PREC_F32S), except the residual
+ * of the last step, whose sums are exact (PNCE_PREC_EXACT: r is y - P x
+ * rounded once to FP32), or accumulated in FP64 (PNCE_PREC_F64ACC) when
+ * they have more than 65535 terms.
  * y: [batch][R][N] c64 (the original, unquantised frames);
  * X: [batch][R][T*L] c64, in: the starting estimate, out: refined;
  * work: device scratch of batch*R*N*8 bytes (the residual). steps >= 0.

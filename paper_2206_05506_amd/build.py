@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libpnce.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = [os.path.join(CSRC, "pnce_kernels.hip"), os.path.join(CSRC, "pnce_pack.hip"),
-           os.path.join(CSRC, "pnce_capi.cpp")]
+           os.path.join(CSRC, "pnce_exact.hip"), os.path.join(CSRC, "pnce_capi.cpp")]
 
 # Packed FP32 instructions are disabled for all device code.
 FLAGS = [

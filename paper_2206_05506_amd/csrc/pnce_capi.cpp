@@ -103,7 +103,7 @@ std::vector<uint32_t> bit_stream(const std::vector<signed char> &s, int len_word
 
 bool valid_prec(int p) {
   return p == PNCE_PREC_F32 || p == PNCE_PREC_F32S || p == PNCE_PREC_BF16 ||
-         p == PNCE_PREC_F64 || p == PNCE_PREC_F64ACC;
+         p == PNCE_PREC_F64 || p == PNCE_PREC_F64ACC || p == PNCE_PREC_EXACT;
 }
 
 bool valid_fmt(int f) {
@@ -185,6 +185,32 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.rseg_len = sg.rlen;
     a.rseg_lag = sg.rlag;
     e = pnce::launch_tg64(a, s);
+  } else if (precision == PNCE_PREC_EXACT) {
+    if (positions > 65535)
+      return fail(PNCE_E_UNSUPPORTED, "PNCE_PREC_EXACT sums at most 65535 terms per output");
+    pnce::ExArgs a{};
+    a.in = (const float *)in;
+    a.out = (float *)out;
+    a.cin = (const float *)cin;
+    a.bits = bits;
+    a.scales = scales;
+    a.R = p->R;
+    a.batch = batch;
+    a.t_len = positions;
+    a.ld_in = ld_in;
+    a.c_len = c_len;
+    a.ld_out = c_len;
+    a.N = p->N;
+    a.nbw = p->nbw;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.seg_len = sg.len;
+    a.seg_lag = sg.lag;
+    a.poff = sg.poff;
+    a.rseg_len = sg.rlen;
+    a.rseg_lag = sg.rlag;
+    a.rseg_n = sg.rn;
+    e = pnce::launch_exact(a, s);
   } else {
     pnce::TgArgs a{};
     a.in = in;
@@ -629,9 +655,13 @@ namespace {
 // The refinement loop on `batch` frames with the residual in `work`.
 pnce_status refine_steps(const pnce_plan *plan, hipStream_t s, const void *y, void *X,
                          void *work, int batch, int steps) {
+  // The last residual is summed exactly (int8 digits) when its sums have at
+  // most 65535 terms, else in FP64 on the FP64 matrix cores.
+  const long terms = plan->D != plan->L ? (long)(plan->T - 1) * plan->D + plan->L : plan->K;
+  const int last_prec = terms <= 65535 ? PNCE_PREC_EXACT : PNCE_PREC_F64ACC;
   for (int j = 0; j < steps; ++j) {
     // r = y - P x   (P x = sum_k x[k] s[(n-k) mod N]: adjoint stream, alpha -1)
-    const int prec = (j + 1 < steps) ? PNCE_PREC_F32S : PNCE_PREC_F64ACC;
+    const int prec = (j + 1 < steps) ? PNCE_PREC_F32S : last_prec;
     if (pnce_status st = run_adj(plan, s, prec, X, work, y, batch, -1.0, 1.0)) return st;
     // x = x + P^T r / N
     if (pnce_status st = run_fwd(plan, s, PNCE_PREC_F32S, pnce::IN_C64, work, plan->N, plan->N,

@@ -1,0 +1,416 @@
+// pnce_exact.hip -- the Toeplitz +-1 contraction of Eq. 3 / Eq. 10 (and its
+// adjoint) with exact sums, on int8 matrix cores (v_mfma_i32_32x32x32_i8).
+//
+//   out[r][c] = alpha * sum_t in[r][t] * s'[(t - c) mod N] + beta * cin[r][c]
+//
+// Every FP32 input row is written in fixed point relative to the row's
+// largest magnitude, X = round(x * 2^(62 - e)) with |X| < 2^62, and X is cut
+// into eight balanced 8-bit digits (the splitting of the Ozaki scheme for
+// error-free matrix products, here one-sided: the other operand is +-1 and
+// exact in int8). Each digit's contraction is summed exactly in int32
+// (|digit| <= 128, at most 65535 terms, so |sum| < 2^23); the eight sums are
+// combined in FP64 (two exact partial sums of four digits, one rounding when
+// they are added), scaled back by 2^(e - 62), and the output is rounded once
+// to FP32 after alpha and beta are applied in FP64. Row elements within 2^38
+// of the row's largest magnitude are represented exactly; smaller ones are
+// rounded at 2^(e - 63), far below FP32 resolution of the row.
+//
+// Tile: 4 antennas x 8 digits = the 32 rows of the matrix-core A operand, by
+// 4 waves x 32*NB output columns. A workgroup takes one block of 4 antennas
+// of one frame and a share of its column groups (all of them unless the
+// launch would be too small to fill the chip). It first finds each row's
+// exponent (wave w scans antenna w), then, per column group, streams the
+// rows through LDS in 256-sample stages, converting every sample into its
+// digits on the way (two stages in flight in registers, one barrier per
+// stage). The +-1 operand is expanded from the sequence bit stream in LDS;
+// without column segments, block c's fragment at k-step i is block 0's at
+// k-step i - c (a block of 32 columns is one k-step of 32 terms), so a wave
+// expands one fragment per k-step and rotates 2*NB of them.
+#include <algorithm>
+
+#include "pnce_device.h"
+
+namespace pnce {
+
+namespace {
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kExWaves = 4;
+constexpr int kExThreads = 64 * kExWaves;
+constexpr int kExAnts = 4;                 // antennas per tile (8 digit rows each)
+constexpr int kExCh = 256;                 // samples per LDS stage: 8 k-steps of 32
+constexpr int kExRow = kExCh + 16;         // bytes per digit row in LDS (16 B pad)
+constexpr int kExPlane = 32 * kExRow;      // one plane (re or im) of a stage
+constexpr int kExStage = 2 * kExPlane;
+constexpr uint64_t kDigitBias = 0x8080808080808080ull;
+
+// x (FP32) in fixed point relative to the row's exponent field E (the
+// largest |re| or |im| of the row has biased exponent E; E >= 1):
+// X = round(x * 2^(188 - E)), half away from zero, |X| < 2^62. Returned as
+// (X + bias) ^ bias, bias = 0x80 in every byte: its bytes, read as signed,
+// are balanced base-256 digits of X (X = sum_j digit_j * 256^j, each in
+// [-128, 127]), since every byte of X + bias lies in [0, 255] and
+// byte - 128 == byte ^ 0x80 as a signed byte.
+__device__ __forceinline__ uint64_t fixed_digits(float x, int E) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, x);
+  int ex = (int)((u >> 23) & 0xFFu);
+  uint32_t m = u & 0x7FFFFFu;
+  if (ex) {
+    m |= 0x800000u;
+  } else {
+    ex = 1;  // subnormal: m * 2^(1 - 150)
+  }
+  const int sh = ex - E + 38;  // x = m * 2^(ex - 150), X = m * 2^sh; sh <= 38
+  uint64_t mag;
+  if (sh >= 0)
+    mag = (uint64_t)m << sh;
+  else if (sh > -25)
+    mag = (uint64_t)((m + (1u << (-sh - 1))) >> (-sh));
+  else
+    mag = 0;
+  const uint64_t X = (u >> 31) ? (uint64_t)0 - mag : mag;
+  return (X + kDigitBias) ^ kDigitBias;
+}
+
+// Digit rows of 4 consecutive samples: row d (d = 0..7) receives byte d of
+// w[0..3] as one dword (sample s in byte s). Two 4x4 byte transposes.
+__device__ __forceinline__ void store_digits(uint8_t *row0, const uint64_t (&w)[4]) {
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const uint32_t a = (uint32_t)(w[0] >> (32 * half)), b = (uint32_t)(w[1] >> (32 * half));
+    const uint32_t c = (uint32_t)(w[2] >> (32 * half)), d = (uint32_t)(w[3] >> (32 * half));
+    // v_perm_b32(S0, S1, sel): selector bytes 0-3 pick S1's bytes, 4-7 S0's
+    const uint32_t ab01 = __builtin_amdgcn_perm(b, a, 0x05010400u);  // a0 b0 a1 b1
+    const uint32_t ab23 = __builtin_amdgcn_perm(b, a, 0x07030602u);  // a2 b2 a3 b3
+    const uint32_t cd01 = __builtin_amdgcn_perm(d, c, 0x05010400u);  // c0 d0 c1 d1
+    const uint32_t cd23 = __builtin_amdgcn_perm(d, c, 0x07030602u);  // c2 d2 c3 d3
+    const uint32_t t[4] = {__builtin_amdgcn_perm(cd01, ab01, 0x05040100u),   // a0 b0 c0 d0
+                           __builtin_amdgcn_perm(cd01, ab01, 0x07060302u),   // a1 b1 c1 d1
+                           __builtin_amdgcn_perm(cd23, ab23, 0x05040100u),   // a2 b2 c2 d2
+                           __builtin_amdgcn_perm(cd23, ab23, 0x07060302u)};  // a3 b3 c3 d3
+#pragma unroll
+    for (int j = 0; j < 4; ++j) *(uint32_t *)(row0 + (4 * half + j) * kExRow) = t[j];
+  }
+}
+
+// 16 sequence bits -> 16 int8 values of +-1 (bit 1 -> -1 = 0xFF, bit 0 ->
+// +1 = 0x01), bit e in byte e. A nibble's bits are spread to the low bit of
+// each byte by one multiply (bit j moves by 7j to bit 8j).
+__device__ __forceinline__ i32x4 pm1_bytes(uint32_t w16) {
+  i32x4 r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t spread = (((w16 >> (4 * q)) & 0xFu) * 0x00204081u) & 0x01010101u;
+    r[q] = (int)(0x01010101u | (spread * 0xFEu));
+  }
+  return r;
+}
+
+__device__ __forceinline__ i32x4 frag_at(const uint32_t *sbits, int p) {
+  return pm1_bytes(window32(sbits, p) & 0xFFFFu);
+}
+
+// One thread's share of a stage: samples n0 + 4 lane .. + 3 of antenna
+// a0 + wave, as two complex pairs.
+struct RawEx {
+  f32x4 v[2];
+};
+
+template <int NB, bool SB, bool GA>
+__global__ __launch_bounds__(kExThreads, 2) void exact_kernel(ExArgs a, int rblocks, int splits,
+                                                              int ngroups, int nbw_pad) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+  constexpr int NW = 2 * NB;  // fragment slots (NW divides the 8 k-steps of a stage)
+  uint32_t *sbits = smem;
+  int *e_tab = (int *)(smem + nbw_pad);
+  uint8_t *stage = (uint8_t *)(smem + nbw_pad + 4);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m = lane & 31;
+  const int kh = lane >> 5;
+  const int split = blockIdx.x % splits;
+  const int rest = blockIdx.x / splits;
+  const int rb = rest % rblocks;
+  const int b = rest / rblocks;
+  const int a0 = rb * kExAnts;
+  const float *fin = a.in + (size_t)b * a.R * a.ld_in * 2;
+  const int row_terms = GA ? a.rseg_n * a.rseg_len : a.t_len;
+
+  // Exponent field of each row's largest |re| or |im| (255: a non-finite
+  // value; the row's outputs are then NaN). Wave w scans antenna a0 + w.
+  {
+    uint32_t mx = 0u;
+    const int ant = a0 + wave;
+    if (ant < a.R) {
+      const uint2 *row = (const uint2 *)(fin + (size_t)ant * a.ld_in * 2);
+      int n = lane;
+      for (; n + 192 < row_terms; n += 256) {
+        const uint2 v0 = row[n], v1 = row[n + 64], v2 = row[n + 128], v3 = row[n + 192];
+        mx = max(mx, max(v0.x & 0x7FFFFFFFu, v0.y & 0x7FFFFFFFu));
+        mx = max(mx, max(v1.x & 0x7FFFFFFFu, v1.y & 0x7FFFFFFFu));
+        mx = max(mx, max(v2.x & 0x7FFFFFFFu, v2.y & 0x7FFFFFFFu));
+        mx = max(mx, max(v3.x & 0x7FFFFFFFu, v3.y & 0x7FFFFFFFu));
+      }
+      for (; n < row_terms; n += 64) {
+        const uint2 v = row[n];
+        mx = max(mx, max(v.x & 0x7FFFFFFFu, v.y & 0x7FFFFFFFu));
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+    if (lane == 0) e_tab[wave] = max((int)(mx >> 23), 1);
+  }
+  for (int i = tid; i < a.nbw; i += kExThreads) sbits[i] = a.bits[i];
+  __syncthreads();
+  const int e_own = e_tab[wave];                              // the row this thread converts
+  const int e_fin[2] = {e_tab[2 * kh], e_tab[2 * kh + 1]};  // the rows this lane finishes
+
+  const __amdgpu_buffer_rsrc_t rsrc =
+      frame_rsrc(fin, ((long long)(a.R - 1) * a.ld_in + row_terms) * 8);
+  const uint32_t rowoff = (uint32_t)(a0 + wave) * (uint32_t)a.ld_in * 8u;
+  const int nchunks = (a.t_len + kExCh - 1) / kExCh;
+  const int last = nchunks - 1;
+
+  // chunk -> registers (past the end: the last chunk again). Pairs cut by
+  // the end of the row are read one sample early so that no 16-byte load
+  // straddles the end of the frame (t_len >= 2); land() shifts them back.
+  auto fetch = [&](RawEx &r, int chunk) {
+    const int n = (chunk < last ? chunk : last) * kExCh + 4 * lane;
+    if constexpr (GA) {
+      // rows of lag blocks: position u holds term j*len + l when
+      // u = j*step + l, l < len, j < n; other positions read past any frame
+      f32x2 x[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int u = n + e;
+        const int j = u / a.rseg_lag;
+        const int l = u - j * a.rseg_lag;
+        const uint32_t off = (rowoff + 8u * (uint32_t)(j * a.rseg_len + l)) |
+                             ((j < a.rseg_n && l < a.rseg_len) ? 0u : 0x80000000u);
+        x[e] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0));
+      }
+      r.v[0] = f32x4{x[0].x, x[0].y, x[1].x, x[1].y};
+      r.v[1] = f32x4{x[2].x, x[2].y, x[3].x, x[3].y};
+    } else {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int np = n + 2 * p;
+        const uint32_t off = rowoff + 8u * (uint32_t)np - (np + 1 == a.t_len ? 8u : 0u);
+        r.v[p] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
+      }
+    }
+  };
+  // registers -> digit planes of LDS stage st
+  auto land = [&](uint8_t *st, const RawEx &r, int chunk) {
+    f32x4 v[2] = {r.v[0], r.v[1]};
+    if constexpr (!GA) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int np = chunk * kExCh + 4 * lane + 2 * p;
+        if (np >= a.t_len)
+          v[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+        else if (np + 1 == a.t_len)
+          v[p] = f32x4{v[p].z, v[p].w, 0.f, 0.f};
+      }
+    }
+    const uint64_t wre[4] = {fixed_digits(v[0].x, e_own), fixed_digits(v[0].z, e_own),
+                             fixed_digits(v[1].x, e_own), fixed_digits(v[1].z, e_own)};
+    const uint64_t wim[4] = {fixed_digits(v[0].y, e_own), fixed_digits(v[0].w, e_own),
+                             fixed_digits(v[1].y, e_own), fixed_digits(v[1].w, e_own)};
+    uint8_t *row0 = st + (8 * wave) * kExRow + 4 * lane;
+    store_digits(row0, wre);
+    store_digits(row0 + kExPlane, wim);
+  };
+
+  const int gw = kExWaves * 32 * NB;
+  for (int g = split; g < ngroups; g += splits) {
+    // this wave's 32*NB columns: lags sp.lag0 + j, stored at sp.ocol0 + j
+    // for j < sp.n_out (SB: block c's 32 columns from sb[c] likewise)
+    const int v0 = g * gw + wave * 32 * NB;
+    const SegPos sp = seg_pos(v0, seg_pad(a.seg_len, a.seg_lag, SB ? 32 : 32 * NB), a.seg_len,
+                              a.seg_lag, a.c_len);
+    [[maybe_unused]] SegPos sb[SB ? NB : 1];
+    if constexpr (SB) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        sb[c] = seg_pos(v0 + 32 * c, seg_pad(a.seg_len, a.seg_lag, 32), a.seg_len, a.seg_lag,
+                        a.c_len);
+    }
+    auto ocol = [&](int c) { return SB ? sb[c].ocol0 : sp.ocol0 + 32 * c; };
+    auto nout = [&](int c) { return SB ? sb[c].n_out : sp.n_out - 32 * c; };
+
+    RawEx raw[2];
+    fetch(raw[0], 0);
+    fetch(raw[1], 1);
+    land(stage, raw[0], 0);
+    fetch(raw[0], 2);
+
+    // B fragment of lane (m, kh) at k-step i: terms t = 32i + 16kh + e
+    // (e < 16) against column lag0 + m: bits p_base + 32i + e with
+    // p_base = 16kh - m - lag0 + poff (mod N); positions stay below
+    // N + t_len + 96 bits, inside the doubled stream.
+    [[maybe_unused]] i32x4 win[SB ? 1 : NW];
+    [[maybe_unused]] i32x4 wb[SB ? NB : 1][2];
+    [[maybe_unused]] int pb[SB ? NB : 1];
+    int p_base = 0;
+    if constexpr (SB) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        pb[c] = pos_mod(16 * kh - m - sb[c].lag0 + a.poff, a.N);
+        wb[c][0] = frag_at(sbits, pb[c]);
+      }
+    } else {
+      p_base = pos_mod(16 * kh - m - sp.lag0 + a.poff, a.N);
+      win[0] = frag_at(sbits, p_base);
+#pragma unroll
+      for (int j = 1; j < NB; ++j) win[NW - j] = frag_at(sbits, pos_mod(p_base - 32 * j, a.N));
+    }
+
+    i32x16 acc_re[NB], acc_im[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc_re[c][v] = 0;
+        acc_im[c][v] = 0;
+      }
+    }
+    __syncthreads();
+
+    // 8 k-steps on one stage; the fragments of k-step i + 1 are built
+    // during k-step i (their slot held step i + 1 - 2NB, which no block
+    // reads at step i).
+    auto do_chunk = [&](const uint8_t *st, int chunk) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = 8 * chunk + u;
+        const i32x4 are = *(const i32x4 *)(st + m * kExRow + 32 * u + 16 * kh);
+        const i32x4 aim = *(const i32x4 *)(st + kExPlane + m * kExRow + 32 * u + 16 * kh);
+        if constexpr (SB) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) wb[c][(u + 1) & 1] = frag_at(sbits, pb[c] + 32 * (i + 1));
+        } else {
+          win[(u + 1) % NW] = frag_at(sbits, p_base + 32 * (i + 1));
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const i32x4 bw = SB ? wb[c][u & 1] : win[(u - c + NW) % NW];
+          acc_re[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(are, bw, acc_re[c], 0, 0, 0);
+          acc_im[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aim, bw, acc_im[c], 0, 0, 0);
+        }
+      }
+    };
+
+    for (int chunk0 = 0; chunk0 < nchunks; chunk0 += 2) {
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const int chunk = chunk0 + cc;
+        if (chunk < nchunks) {
+          do_chunk(stage + cc * kExStage, chunk);
+          if (chunk + 1 < nchunks) land(stage + (1 - cc) * kExStage, raw[(cc + 1) & 1], chunk + 1);
+          fetch(raw[(cc + 1) & 1], chunk + 3);
+          __syncthreads();
+        }
+      }
+    }
+
+    // Epilogue. Lane (m, kh) holds, for block c, column ocol(c) + m and
+    // accumulator rows 8(v/4) + 4kh + (v%4): antenna v/4, digit 4kh + v%4.
+    // Q = sum of its four digit sums times 256^(digit - 4kh) is exact in
+    // FP64 (< 2^48); the lanes kh = 0 and 1 swap halves so that lane kh
+    // finishes antennas 2kh and 2kh + 1: total = Q_low + 2^32 Q_high.
+    const double alpha = a.alpha * (a.scales ? (double)a.scales[b] : 1.0);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      double tot[2][2];  // [antenna 2kh + jj][re, im]
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri) {
+        const i32x16 &acc = ri ? acc_im[c] : acc_re[c];
+        double q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          q[j] = (double)acc[4 * j] + 256.0 * (double)acc[4 * j + 1] +
+                 65536.0 * (double)acc[4 * j + 2] + 16777216.0 * (double)acc[4 * j + 3];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const double send = kh ? q[jj] : q[2 + jj];
+          const double recv = __shfl_xor(send, 32);
+          const double lo = kh ? recv : q[jj];
+          const double hi = kh ? q[2 + jj] : recv;
+          tot[jj][ri] = lo + 4294967296.0 * hi;
+        }
+      }
+      const int col = ocol(c) + m;
+      if (m < nout(c)) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int j = 2 * kh + jj;
+          const int ant = a0 + j;
+          if (ant < a.R) {
+            const int e = e_fin[jj];
+            // 2^(e - 188): X carried 188 - e fractional bits
+            const double sc = __builtin_bit_cast(double, (uint64_t)(e - 188 + 1023) << 52);
+            double re = alpha * (tot[jj][0] * sc), im = alpha * (tot[jj][1] * sc);
+            if (e == 255) re = im = __builtin_nan("");
+            const size_t o = ((size_t)(b * a.R + ant) * a.ld_out + col) * 2;
+            if (a.beta != 0.0) {
+              const f2a8 old = *(const f2a8 *)(a.cin + o);
+              re += a.beta * (double)old.x;
+              im += a.beta * (double)old.y;
+            }
+            __builtin_nontemporal_store(f2a8{(float)re, (float)im}, (f2a8 *)(a.out + o));
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int NB>
+hipError_t launch_exact_nb(const ExArgs &a, int rblocks, int splits, int ngroups, int nbw_pad,
+                           size_t lds, long nt, hipStream_t s) {
+  auto go = [&](auto kern) -> hipError_t {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)nt), dim3(kExThreads), lds, s, a, rblocks, splits,
+                       ngroups, nbw_pad);
+    return hipGetLastError();
+  };
+  if (a.seg_lag && a.rseg_lag) return hipErrorInvalidValue;  // never both (one direction each)
+  if (a.seg_lag) return go(exact_kernel<NB, true, false>);
+  if (a.rseg_lag) return go(exact_kernel<NB, false, true>);
+  return go(exact_kernel<NB, false, false>);
+}
+
+}  // namespace
+
+hipError_t launch_exact(const ExArgs &a, hipStream_t s) {
+  if (a.t_len < 2 || a.t_len > 65535 || a.c_len < 1 || a.R < 1 || a.batch < 1)
+    return hipErrorInvalidValue;
+  const int vcols = virtual_cols(a.c_len, a.seg_len, a.seg_lag, 32);
+  const int nb = vcols > 256 ? 4 : (vcols > 128 ? 2 : 1);
+  const int gw = kExWaves * 32 * nb;
+  const int ngroups = (vcols + gw - 1) / gw;
+  const int rblocks = (a.R + kExAnts - 1) / kExAnts;
+  const long units = (long)a.batch * rblocks;
+  // Small launches spread one block's column groups over several
+  // workgroups (each finds the rows' exponents itself).
+  constexpr long kFill = 2048;  // 8 workgroups per compute unit
+  const int splits = units >= kFill ? 1 : (int)std::min<long>(ngroups, (kFill + units - 1) / units);
+  const long nt = units * splits;
+  if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
+  const int nbw_pad = (a.nbw + 3) & ~3;
+  const size_t lds = (size_t)(nbw_pad + 4) * 4 + 2 * (size_t)kExStage;
+  if (nb == 4) return launch_exact_nb<4>(a, rblocks, splits, ngroups, nbw_pad, lds, nt, s);
+  if (nb == 2) return launch_exact_nb<2>(a, rblocks, splits, ngroups, nbw_pad, lds, nt, s);
+  return launch_exact_nb<1>(a, rblocks, splits, ngroups, nbw_pad, lds, nt, s);
+}
+
+}  // namespace pnce

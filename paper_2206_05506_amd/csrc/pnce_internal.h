@@ -54,6 +54,26 @@ inline int virtual_cols(int c_len, int seg_len, int seg_lag, int gran) {
 
 hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s);
 
+// Contraction with exact sums (pnce_exact.hip): complex64 rows, int8 matrix
+// cores on eight 8-bit fixed-point digits per value, alpha and beta in FP64.
+// Same geometry fields as TgArgs; t_len in [2, 65535].
+struct ExArgs {
+  const float *in;
+  float *out;
+  const float *cin;
+  const uint32_t *bits;
+  const float *scales;
+  int R, batch;
+  int t_len, ld_in;
+  int c_len, ld_out;
+  int N, nbw;
+  double alpha, beta;
+  int seg_len, seg_lag;
+  int poff;
+  int rseg_len, rseg_lag, rseg_n;
+};
+hipError_t launch_exact(const ExArgs &a, hipStream_t s);
+
 // LDS one workgroup needs, at most over the kernels, for a bit stream of
 // nbw words, and what a gfx950 workgroup may have.
 size_t max_lds_bytes(int nbw);

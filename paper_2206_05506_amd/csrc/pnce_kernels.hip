@@ -22,18 +22,13 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "pnce_internal.h"
+#include "pnce_device.h"
 
 namespace pnce {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
-typedef float f2a8 __attribute__((ext_vector_type(2), aligned(8)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kRows = 32;      // antennas per tile
 constexpr int kWaves = 4;
@@ -116,27 +111,10 @@ template <int CH> struct RawPacked {
   u32x4 v[CH / 32];
 };
 
-// Complex64 rows come through a raw buffer resource bounded by the frame:
-// reads at or past its end (antennas at or beyond R, the tail of the last
-// row) return zeros, so every load is unconditional and the compiler can
-// count them exactly (a load in a divergent branch forces it to wait for all
-// outstanding loads). The whole byte offset goes in the per-lane offset,
-// which the hardware checks against the frame size (the scalar offset is not
-// checked), so no load ever touches memory past the frame. Thread t reads
-// sample pairs q = t + 256 i of a stage (row q / (CH/2), samples
-// 2 (q % (CH/2)) and +1); a wave instruction reads 64 consecutive pairs.
-constexpr int kRsrcFlags = 0x00020000;  // raw buffer, 32-bit dwords
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t frame_rsrc(const void *base, long long bytes) {
-  // The descriptor lives in scalar registers: make its parts provably uniform.
-  const uint64_t b = (uint64_t)base;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
-  const int n = __builtin_amdgcn_readfirstlane((int)bytes);
-  return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0, n,
-                                           kRsrcFlags);
-}
-
+// Complex64 stages come through the frame-bounded buffer resource
+// (frame_rsrc): thread t reads sample pairs q = t + 256 i of a stage (row
+// q / (CH/2), samples 2 (q % (CH/2)) and +1); a wave instruction reads 64
+// consecutive pairs.
 // Byte offset of this thread's pair i of a stage at sample 0.
 template <int CH>
 __device__ __forceinline__ uint32_t pair_voff(int i, int a0, int ld_in, int tid) {
@@ -313,20 +291,6 @@ __device__ __forceinline__ void store_stage(uint32_t *st, const RawPacked<CH> &r
   }
 }
 
-// 8 bits of the periodic stream starting at bit p (p + 63 < 32 * nbw).
-__device__ __forceinline__ uint32_t window8(const uint32_t *sbits, int p) {
-  const uint32_t w0 = sbits[p >> 5];
-  const uint32_t w1 = sbits[(p >> 5) + 1];
-  return __builtin_amdgcn_alignbit(w1, w0, (uint32_t)(p & 31)) & 0xFFu;
-}
-
-// 32 bits of the periodic stream starting at bit p.
-__device__ __forceinline__ uint32_t window32(const uint32_t *sbits, int p) {
-  const uint32_t w0 = sbits[p >> 5];
-  const uint32_t w1 = sbits[(p >> 5) + 1];
-  return __builtin_amdgcn_alignbit(w1, w0, (uint32_t)(p & 31));
-}
-
 // Expand 8 bits into 8 16-bit +-1 values (bit 1 -> sign set). ONE is the
 // 16-bit pattern of +1 in both halves: 0x3F803F80 (bf16), 0x3C003C00 (f16).
 template <uint32_t ONE>
@@ -362,24 +326,6 @@ __device__ __forceinline__ void fill_lut(uint32_t *lut) {
   const u32x4 v = (IN == IN_F16) ? expand16<0x3C003C00u>((uint32_t)e)
                                  : expand16<0x3F803F80u>((uint32_t)e);
   *(u32x4 *)(lut + 4 * e) = v;
-}
-
-__device__ __forceinline__ int pos_mod(int a, int n) {
-  int r = a % n;
-  return r < 0 ? r + n : r;
-}
-
-// Where a run of columns starting at dealt-out column v0 sits: its first lag,
-// its first stored column, and how many of its columns are stored (<= 0:
-// none). The run must not cross a segment (see seg_pad).
-struct SegPos {
-  int lag0, ocol0, n_out;
-};
-__device__ __forceinline__ SegPos seg_pos(int v0, int pad, int seg_len, int seg_lag, int c_len) {
-  if (!seg_lag) return {v0, v0, c_len - v0};
-  const int j = v0 / pad;
-  const int l0 = v0 - j * pad;
-  return {j * seg_lag + l0, j * seg_len + l0, min(seg_len, c_len - j * seg_len) - l0};
 }
 
 // ---------------------------------------------------------------------------

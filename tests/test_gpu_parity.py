@@ -58,7 +58,7 @@ TOL_F64ACC = 2e-7   # FP64 sums, one rounding of each output to FP32
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
-@pytest.mark.parametrize("prec", ["f32", "f32s", "bf16", "f64acc"])
+@pytest.mark.parametrize("prec", ["f32", "f32s", "bf16", "f64acc", "exact"])
 def test_estimate_parity(shape, prec):
     N, T, L, R, B = shape
     K = T * L
@@ -71,7 +71,7 @@ def test_estimate_parity(shape, prec):
     ref = oracle.correlate(x, s, K)
     err = perr(H, ref)
     print(f"estimate {prec} N={N} K={K} R={R} B={B}: relerr {err:.3e}")
-    assert err <= (TOL_F64ACC if prec == "f64acc" else TOL32)
+    assert err <= (TOL_F64ACC if prec in ("f64acc", "exact") else TOL32)
 
 
 @pytest.mark.parametrize("shape", [SHAPES[2], SHAPES[4], SHAPES[6]],
@@ -114,7 +114,7 @@ def test_estimate_scales_and_beta():
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
-@pytest.mark.parametrize("prec", ["f32", "f32s", "f64acc"])
+@pytest.mark.parametrize("prec", ["f32", "f32s", "f64acc", "exact"])
 def test_adjoint_parity(shape, prec):
     N, T, L, R, B = shape
     K = T * L
@@ -125,7 +125,7 @@ def test_adjoint_parity(shape, prec):
         A = host(p.adjoint(dev(G), prec))
         A2 = host(p.adjoint(dev(G), prec, alpha=-1.0, beta=1.0, C=dev(C)))
     ref = oracle.adjoint(G, s)
-    tol = TOL_F64ACC if prec == "f64acc" else TOL32
+    tol = TOL_F64ACC if prec in ("f64acc", "exact") else TOL32
     assert perr(A, ref) <= tol
     ref2 = C.astype(np.complex128) - N * ref
     assert perr(A2, ref2) <= tol
