@@ -27,6 +27,7 @@
 // k-step i - c (a block of 32 columns is one k-step of 32 terms), so a wave
 // expands one fragment per k-step and rotates 2*NB of them.
 #include <algorithm>
+#include <type_traits>
 
 #include "pnce_device.h"
 
@@ -37,13 +38,7 @@ namespace {
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kExWaves = 4;
-constexpr int kExThreads = 64 * kExWaves;
-constexpr int kExAnts = 4;                 // antennas per tile (8 digit rows each)
-constexpr int kExCh = 256;                 // samples per LDS stage: 8 k-steps of 32
-constexpr int kExRow = kExCh + 16;         // bytes per digit row in LDS (16 B pad)
-constexpr int kExPlane = 32 * kExRow;      // one plane (re or im) of a stage
-constexpr int kExStage = 2 * kExPlane;
+constexpr int kExAnts = 4;  // antennas per tile (8 digit rows each)
 constexpr uint64_t kDigitBias = 0x8080808080808080ull;
 
 // x (FP32) in fixed point relative to the row's exponent field E (the
@@ -55,27 +50,24 @@ constexpr uint64_t kDigitBias = 0x8080808080808080ull;
 // byte - 128 == byte ^ 0x80 as a signed byte.
 __device__ __forceinline__ uint64_t fixed_digits(float x, int E) {
   const uint32_t u = __builtin_bit_cast(uint32_t, x);
-  int ex = (int)((u >> 23) & 0xFFu);
-  uint32_t m = u & 0x7FFFFFu;
-  if (ex) {
-    m |= 0x800000u;
-  } else {
-    ex = 1;  // subnormal: m * 2^(1 - 150)
-  }
+  const uint32_t ex_raw = (u >> 23) & 0xFFu;
+  const uint32_t m = (u & 0x7FFFFFu) | (ex_raw ? 0x800000u : 0u);
+  const int ex = ex_raw ? (int)ex_raw : 1;  // subnormal: m * 2^(1 - 150)
   const int sh = ex - E + 38;  // x = m * 2^(ex - 150), X = m * 2^sh; sh <= 38
-  uint64_t mag;
-  if (sh >= 0)
-    mag = (uint64_t)m << sh;
-  else if (sh > -25)
-    mag = (uint64_t)((m + (1u << (-sh - 1))) >> (-sh));
-  else
-    mag = 0;
-  const uint64_t X = (u >> 31) ? (uint64_t)0 - mag : mag;
+  // both shifts, then a select (no branch): left for sh >= 0, right
+  // (rounded, clamped to 31 so that tiny values give 0) for sh < 0
+  const uint64_t left = (uint64_t)m << (sh > 0 ? sh : 0);
+  const int rs = sh < -1 ? (-sh < 31 ? -sh : 31) : 1;
+  const uint32_t right = (m + (1u << (rs - 1))) >> rs;
+  const uint64_t mag = sh >= 0 ? left : (uint64_t)right;
+  const uint64_t neg = (uint64_t)(int64_t)((int32_t)u >> 31);  // 0 or all ones
+  const uint64_t X = (mag ^ neg) - neg;
   return (X + kDigitBias) ^ kDigitBias;
 }
 
 // Digit rows of 4 consecutive samples: row d (d = 0..7) receives byte d of
 // w[0..3] as one dword (sample s in byte s). Two 4x4 byte transposes.
+template <int ROW>
 __device__ __forceinline__ void store_digits(uint8_t *row0, const uint64_t (&w)[4]) {
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
@@ -91,47 +83,78 @@ __device__ __forceinline__ void store_digits(uint8_t *row0, const uint64_t (&w)[
                            __builtin_amdgcn_perm(cd23, ab23, 0x05040100u),   // a2 b2 c2 d2
                            __builtin_amdgcn_perm(cd23, ab23, 0x07060302u)};  // a3 b3 c3 d3
 #pragma unroll
-    for (int j = 0; j < 4; ++j) *(uint32_t *)(row0 + (4 * half + j) * kExRow) = t[j];
+    for (int j = 0; j < 4; ++j) *(uint32_t *)(row0 + (4 * half + j) * ROW) = t[j];
   }
 }
 
-// 16 sequence bits -> 16 int8 values of +-1 (bit 1 -> -1 = 0xFF, bit 0 ->
-// +1 = 0x01), bit e in byte e. A nibble's bits are spread to the low bit of
-// each byte by one multiply (bit j moves by 7j to bit 8j).
-__device__ __forceinline__ i32x4 pm1_bytes(uint32_t w16) {
-  i32x4 r;
+// +-1 fragments: 16 sequence bits -> 16 int8 values (bit 1 -> -1 = 0xFF,
+// bit 0 -> +1 = 0x01), bit e in byte e, read nibble by nibble from a
+// 16-entry table at the start of LDS (16 consecutive dwords: lanes reading
+// different entries hit different banks).
+__device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib) {
+  uint32_t r = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t spread = (((w16 >> (4 * q)) & 0xFu) * 0x00204081u) & 0x01010101u;
-    r[q] = (int)(0x01010101u | (spread * 0xFEu));
-  }
+  for (int e = 0; e < 4; ++e) r |= (((nib >> e) & 1u) ? 0xFFu : 0x01u) << (8 * e);
   return r;
 }
 
-__device__ __forceinline__ i32x4 frag_at(const uint32_t *sbits, int p) {
-  return pm1_bytes(window32(sbits, p) & 0xFFFFu);
+__device__ __forceinline__ i32x4 frag_at(const uint32_t *sbits, const uint32_t *lut, int p) {
+  const uint32_t w = window32(sbits, p);
+  return i32x4{(int)lut[w & 0xFu], (int)lut[(w >> 4) & 0xFu], (int)lut[(w >> 8) & 0xFu],
+               (int)lut[(w >> 12) & 0xFu]};
 }
 
-// One thread's share of a stage: samples n0 + 4 lane .. + 3 of antenna
-// a0 + wave, as two complex pairs.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// One thread's share of a stage: 4 consecutive samples of one antenna, as
+// two complex pairs.
 struct RawEx {
   f32x4 v[2];
 };
 
-template <int NB, bool SB, bool GA>
-__global__ __launch_bounds__(kExThreads, 2) void exact_kernel(ExArgs a, int rblocks, int splits,
-                                                              int ngroups, int nbw_pad) {
+// NWV waves per workgroup (4, or 8 for outputs wider than 512 columns, so
+// that each converted stage feeds twice the matrix work). WPA = NWV/4 waves
+// share an antenna: wave w loads and converts antenna w / WPA, samples
+// 256 (w % WPA) + 4 lane .. + 3 of every stage of CH = 256 WPA samples
+// (KS = CH/32 k-steps per barrier).
+template <int NWV> struct ExGeom {
+  static constexpr int threads = 64 * NWV;
+  static constexpr int wpa = NWV / 4;
+  static constexpr int ch = 256 * wpa;
+  static constexpr int ks = ch / 32;
+  static constexpr int row = ch + 16;  // bytes per digit row in LDS (16 B pad)
+  static constexpr int plane = 32 * row;
+  static constexpr int stage = 2 * plane;  // re and im planes
+};
+constexpr int kLutDw = 16;  // LDS: nibble table, sequence bits, per-wave maxima, stages
+constexpr int kMaxDw = 8;
+
+template <int NB, int NWV, bool SB, bool GA>
+__global__ __launch_bounds__(64 * NWV, 8 / NWV) void exact_kernel(ExArgs a, int rblocks,
+                                                                  int splits, int ngroups,
+                                                                  int nbw_pad) {
+  using G = ExGeom<NWV>;
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
-  constexpr int NW = 2 * NB;  // fragment slots (NW divides the 8 k-steps of a stage)
-  uint32_t *sbits = smem;
-  int *e_tab = (int *)(smem + nbw_pad);
-  uint8_t *stage = (uint8_t *)(smem + nbw_pad + 4);
+  constexpr int NW = 2 * NB;  // fragment slots (NW divides the KS k-steps of a stage)
+  static_assert(G::ks % NW == 0, "slots must repeat within a stage");
+  uint32_t *lut = smem;
+  uint32_t *sbits = smem + kLutDw;
+  uint32_t *mx_tab = smem + kLutDw + nbw_pad;
+  uint8_t *stage = (uint8_t *)(smem + kLutDw + nbw_pad + kMaxDw);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int m = lane & 31;
   const int kh = lane >> 5;
+  const int my_ant = wave / G::wpa;  // the antenna this wave loads and converts
+  const int my_part = wave % G::wpa;
   const int split = blockIdx.x % splits;
   const int rest = blockIdx.x / splits;
   const int rb = rest % rblocks;
@@ -140,46 +163,18 @@ __global__ __launch_bounds__(kExThreads, 2) void exact_kernel(ExArgs a, int rblo
   const float *fin = a.in + (size_t)b * a.R * a.ld_in * 2;
   const int row_terms = GA ? a.rseg_n * a.rseg_len : a.t_len;
 
-  // Exponent field of each row's largest |re| or |im| (255: a non-finite
-  // value; the row's outputs are then NaN). Wave w scans antenna a0 + w.
-  {
-    uint32_t mx = 0u;
-    const int ant = a0 + wave;
-    if (ant < a.R) {
-      const uint2 *row = (const uint2 *)(fin + (size_t)ant * a.ld_in * 2);
-      int n = lane;
-      for (; n + 192 < row_terms; n += 256) {
-        const uint2 v0 = row[n], v1 = row[n + 64], v2 = row[n + 128], v3 = row[n + 192];
-        mx = max(mx, max(v0.x & 0x7FFFFFFFu, v0.y & 0x7FFFFFFFu));
-        mx = max(mx, max(v1.x & 0x7FFFFFFFu, v1.y & 0x7FFFFFFFu));
-        mx = max(mx, max(v2.x & 0x7FFFFFFFu, v2.y & 0x7FFFFFFFu));
-        mx = max(mx, max(v3.x & 0x7FFFFFFFu, v3.y & 0x7FFFFFFFu));
-      }
-      for (; n < row_terms; n += 64) {
-        const uint2 v = row[n];
-        mx = max(mx, max(v.x & 0x7FFFFFFFu, v.y & 0x7FFFFFFFu));
-      }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
-    if (lane == 0) e_tab[wave] = max((int)(mx >> 23), 1);
-  }
-  for (int i = tid; i < a.nbw; i += kExThreads) sbits[i] = a.bits[i];
-  __syncthreads();
-  const int e_own = e_tab[wave];                              // the row this thread converts
-  const int e_fin[2] = {e_tab[2 * kh], e_tab[2 * kh + 1]};  // the rows this lane finishes
-
   const __amdgpu_buffer_rsrc_t rsrc =
       frame_rsrc(fin, ((long long)(a.R - 1) * a.ld_in + row_terms) * 8);
-  const uint32_t rowoff = (uint32_t)(a0 + wave) * (uint32_t)a.ld_in * 8u;
-  const int nchunks = (a.t_len + kExCh - 1) / kExCh;
+  const uint32_t rowoff = (uint32_t)(a0 + my_ant) * (uint32_t)a.ld_in * 8u;
+  const int nchunks = (a.t_len + G::ch - 1) / G::ch;
   const int last = nchunks - 1;
+  const int my_n = 256 * my_part + 4 * lane;  // this thread's first sample in a stage
 
   // chunk -> registers (past the end: the last chunk again). Pairs cut by
   // the end of the row are read one sample early so that no 16-byte load
   // straddles the end of the frame (t_len >= 2); land() shifts them back.
   auto fetch = [&](RawEx &r, int chunk) {
-    const int n = (chunk < last ? chunk : last) * kExCh + 4 * lane;
+    const int n = (chunk < last ? chunk : last) * G::ch + my_n;
     if constexpr (GA) {
       // rows of lag blocks: position u holds term j*len + l when
       // u = j*step + l, l < len, j < n; other positions read past any frame
@@ -204,73 +199,138 @@ __global__ __launch_bounds__(kExThreads, 2) void exact_kernel(ExArgs a, int rblo
       }
     }
   };
-  // registers -> digit planes of LDS stage st
-  auto land = [&](uint8_t *st, const RawEx &r, int chunk) {
-    f32x4 v[2] = {r.v[0], r.v[1]};
-    if constexpr (!GA) {
-#pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const int np = chunk * kExCh + 4 * lane + 2 * p;
-        if (np >= a.t_len)
-          v[p] = f32x4{0.f, 0.f, 0.f, 0.f};
-        else if (np + 1 == a.t_len)
-          v[p] = f32x4{v[p].z, v[p].w, 0.f, 0.f};
+  // The first two stages' loads go out before the rows' exponents are
+  // found (they do not depend on them), so their latency overlaps the scan.
+  RawEx raw[2];
+  fetch(raw[0], 0);
+  fetch(raw[1], 1 % nchunks);
+
+  // Largest |re| or |im| bits of each row; wave w scans part w % WPA of
+  // antenna w / WPA (exponent field 255: a non-finite value, the row's
+  // outputs are then NaN).
+  {
+    uint32_t mx = 0u;
+    const int ant = a0 + my_ant;
+    if (ant < a.R) {
+      const uint2 *row = (const uint2 *)(fin + (size_t)ant * a.ld_in * 2);
+      constexpr int step = 64 * G::wpa;
+      int n = lane + 64 * my_part;
+      for (; n + 3 * step < row_terms; n += 4 * step) {
+        const uint2 v0 = row[n], v1 = row[n + step], v2 = row[n + 2 * step],
+                    v3 = row[n + 3 * step];
+        mx = max(mx, max(v0.x & 0x7FFFFFFFu, v0.y & 0x7FFFFFFFu));
+        mx = max(mx, max(v1.x & 0x7FFFFFFFu, v1.y & 0x7FFFFFFFu));
+        mx = max(mx, max(v2.x & 0x7FFFFFFFu, v2.y & 0x7FFFFFFFu));
+        mx = max(mx, max(v3.x & 0x7FFFFFFFu, v3.y & 0x7FFFFFFFu));
+      }
+      for (; n < row_terms; n += step) {
+        const uint2 v = row[n];
+        mx = max(mx, max(v.x & 0x7FFFFFFFu, v.y & 0x7FFFFFFFu));
       }
     }
-    const uint64_t wre[4] = {fixed_digits(v[0].x, e_own), fixed_digits(v[0].z, e_own),
-                             fixed_digits(v[1].x, e_own), fixed_digits(v[1].z, e_own)};
-    const uint64_t wim[4] = {fixed_digits(v[0].y, e_own), fixed_digits(v[0].w, e_own),
-                             fixed_digits(v[1].y, e_own), fixed_digits(v[1].w, e_own)};
-    uint8_t *row0 = st + (8 * wave) * kExRow + 4 * lane;
-    store_digits(row0, wre);
-    store_digits(row0 + kExPlane, wim);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+    if (lane == 0) mx_tab[wave] = mx;
+  }
+  if (tid < kLutDw) lut[tid] = nibble_bytes((uint32_t)tid);
+  for (int i = tid; i < a.nbw; i += G::threads) sbits[i] = a.bits[i];
+  __syncthreads();
+  // exponent field E of antenna j of the tile (E >= 1)
+  auto e_of = [&](int j) {
+    uint32_t mx = mx_tab[j * G::wpa];
+#pragma unroll
+    for (int q = 1; q < G::wpa; ++q) mx = max(mx, mx_tab[j * G::wpa + q]);
+    return max((int)(mx >> 23), 1);
+  };
+  const int e_own = e_of(my_ant);                     // the row this wave converts
+  const int e_fin[2] = {e_of(2 * kh), e_of(2 * kh + 1)};  // the rows this lane finishes
+
+  // registers -> digit planes of LDS stage st, in ten pieces so that they
+  // can be spread over the k-steps of the previous stage: piece 0 masks the
+  // samples past the row end and converts re of sample 0, pieces 1-3 re of
+  // samples 1-3, piece 4 stores the re digits, pieces 5-9 the same for im.
+  struct Conv {
+    f32x4 v[2];
+    uint64_t w[4];
+  };
+  auto conv_piece = [&](auto kp, Conv &cv, uint8_t *st, const RawEx &r, int chunk) {
+    constexpr int K = decltype(kp)::value;
+    uint8_t *row0 = st + (8 * my_ant) * G::row + my_n;
+    if constexpr (K == 0) {
+      cv.v[0] = r.v[0];
+      cv.v[1] = r.v[1];
+      if constexpr (!GA) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const int np = chunk * G::ch + my_n + 2 * p;
+          const f32x4 x = cv.v[p];
+          cv.v[p] = np >= a.t_len       ? f32x4{0.f, 0.f, 0.f, 0.f}
+                    : np + 1 == a.t_len ? f32x4{x.z, x.w, 0.f, 0.f}
+                                        : x;
+        }
+      }
+    }
+    if constexpr (K < 4) {
+      const f32x4 x = cv.v[K >> 1];
+      cv.w[K] = fixed_digits((K & 1) ? x.z : x.x, e_own);
+    } else if constexpr (K == 4) {
+      store_digits<G::row>(row0, cv.w);
+    } else if constexpr (K < 9) {
+      const f32x4 x = cv.v[(K - 5) >> 1];
+      cv.w[K - 5] = fixed_digits(((K - 5) & 1) ? x.w : x.y, e_own);
+    } else {
+      store_digits<G::row>(row0 + G::plane, cv.w);
+    }
+  };
+  auto land = [&](uint8_t *st, const RawEx &r, int chunk) {
+    Conv cv;
+    static_for<0, 10>([&](auto kp) { conv_piece(kp, cv, st, r, chunk); });
   };
 
-  const int gw = kExWaves * 32 * NB;
-  for (int g = split; g < ngroups; g += splits) {
-    // this wave's 32*NB columns: lags sp.lag0 + j, stored at sp.ocol0 + j
-    // for j < sp.n_out (SB: block c's 32 columns from sb[c] likewise)
-    const int v0 = g * gw + wave * 32 * NB;
-    const SegPos sp = seg_pos(v0, seg_pad(a.seg_len, a.seg_lag, SB ? 32 : 32 * NB), a.seg_len,
-                              a.seg_lag, a.c_len);
-    [[maybe_unused]] SegPos sb[SB ? NB : 1];
-    if constexpr (SB) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        sb[c] = seg_pos(v0 + 32 * c, seg_pad(a.seg_len, a.seg_lag, 32), a.seg_len, a.seg_lag,
-                        a.c_len);
-    }
-    auto ocol = [&](int c) { return SB ? sb[c].ocol0 : sp.ocol0 + 32 * c; };
-    auto nout = [&](int c) { return SB ? sb[c].n_out : sp.n_out - 32 * c; };
+  // The workgroup's column groups g = split, split + splits, ... all stream
+  // the same rows, so the stage pipeline runs straight through them: step s
+  // is chunk s % nchunks of group s / nchunks, and the next group's first
+  // stage is staged while the last stage of the current one is used.
+  const int gw = NWV * 32 * NB;
+  const int my_groups = (ngroups - split + splits - 1) / splits;
+  const int total = my_groups * nchunks;
 
-    RawEx raw[2];
-    fetch(raw[0], 0);
-    fetch(raw[1], 1);
-    land(stage, raw[0], 0);
-    fetch(raw[0], 2);
+  SegPos sp{};
+  [[maybe_unused]] SegPos sb[SB ? NB : 1];
+  [[maybe_unused]] i32x4 win[SB ? 1 : NW];
+  [[maybe_unused]] i32x4 wb[SB ? NB : 1][2];
+  [[maybe_unused]] int pb[SB ? NB : 1];
+  int p_base = 0;
+  i32x16 acc_re[NB], acc_im[NB];
+  auto ocol = [&](int c) { return SB ? sb[c].ocol0 : sp.ocol0 + 32 * c; };
+  auto nout = [&](int c) { return SB ? sb[c].n_out : sp.n_out - 32 * c; };
 
-    // B fragment of lane (m, kh) at k-step i: terms t = 32i + 16kh + e
-    // (e < 16) against column lag0 + m: bits p_base + 32i + e with
-    // p_base = 16kh - m - lag0 + poff (mod N); positions stay below
-    // N + t_len + 96 bits, inside the doubled stream.
-    [[maybe_unused]] i32x4 win[SB ? 1 : NW];
-    [[maybe_unused]] i32x4 wb[SB ? NB : 1][2];
-    [[maybe_unused]] int pb[SB ? NB : 1];
-    int p_base = 0;
+  // Group k: this wave's 32*NB columns (lags sp.lag0 + j, stored at
+  // sp.ocol0 + j for j < sp.n_out; SB: block c's 32 columns from sb[c]
+  // likewise), the B fragments of k-steps -(NB-1) .. 0, zero accumulators.
+  // B fragment of lane (m, kh) at k-step i: terms t = 32i + 16kh + e
+  // (e < 16) against column lag0 + m: bits p_base + 32i + e with
+  // p_base = 16kh - m - lag0 + poff (mod N); positions stay below
+  // N + t_len + 600 bits, inside the doubled stream.
+  auto start_group = [&](int k) {
+    const int v0 = (split + k * splits) * gw + wave * 32 * NB;
+    sp = seg_pos(v0, seg_pad(a.seg_len, a.seg_lag, SB ? 32 : 32 * NB), a.seg_len, a.seg_lag,
+                 a.c_len);
     if constexpr (SB) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
+        sb[c] = seg_pos(v0 + 32 * c, seg_pad(a.seg_len, a.seg_lag, 32), a.seg_len, a.seg_lag,
+                        a.c_len);
         pb[c] = pos_mod(16 * kh - m - sb[c].lag0 + a.poff, a.N);
-        wb[c][0] = frag_at(sbits, pb[c]);
+        wb[c][0] = frag_at(sbits, lut, pb[c]);
       }
     } else {
       p_base = pos_mod(16 * kh - m - sp.lag0 + a.poff, a.N);
-      win[0] = frag_at(sbits, p_base);
+      win[0] = frag_at(sbits, lut, p_base);
 #pragma unroll
-      for (int j = 1; j < NB; ++j) win[NW - j] = frag_at(sbits, pos_mod(p_base - 32 * j, a.N));
+      for (int j = 1; j < NB; ++j)
+        win[NW - j] = frag_at(sbits, lut, pos_mod(p_base - 32 * j, a.N));
     }
-
-    i32x16 acc_re[NB], acc_im[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
 #pragma unroll
@@ -279,51 +339,67 @@ __global__ __launch_bounds__(kExThreads, 2) void exact_kernel(ExArgs a, int rblo
         acc_im[c][v] = 0;
       }
     }
-    __syncthreads();
+  };
 
-    // 8 k-steps on one stage; the fragments of k-step i + 1 are built
-    // during k-step i (their slot held step i + 1 - 2NB, which no block
-    // reads at step i).
-    auto do_chunk = [&](const uint8_t *st, int chunk) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = 8 * chunk + u;
-        const i32x4 are = *(const i32x4 *)(st + m * kExRow + 32 * u + 16 * kh);
-        const i32x4 aim = *(const i32x4 *)(st + kExPlane + m * kExRow + 32 * u + 16 * kh);
-        if constexpr (SB) {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) wb[c][(u + 1) & 1] = frag_at(sbits, pb[c] + 32 * (i + 1));
-        } else {
-          win[(u + 1) % NW] = frag_at(sbits, p_base + 32 * (i + 1));
-        }
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          const i32x4 bw = SB ? wb[c][u & 1] : win[(u - c + NW) % NW];
-          acc_re[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(are, bw, acc_re[c], 0, 0, 0);
-          acc_im[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aim, bw, acc_im[c], 0, 0, 0);
-        }
+  // KS k-steps on one stage; the fragments of k-step i + 1 are built
+  // during k-step i (their slot held step i + 1 - 2NB, which no block
+  // reads at step i), and so are its A operands. The next stage (registers
+  // nr, chunk nchunk) is converted into LDS stage nst in pieces between the
+  // k-steps: no wave reads nst until the barrier after this stage.
+  constexpr int kPieces = 10;
+  constexpr int kPerStep = (kPieces + G::ks - 1) / G::ks;
+  auto do_chunk = [&](const uint8_t *st, int chunk, uint8_t *nst, const RawEx &nr, int nchunk) {
+    Conv cv;
+    i32x4 are[2], aim[2];
+    are[0] = *(const i32x4 *)(st + m * G::row + 16 * kh);
+    aim[0] = *(const i32x4 *)(st + G::plane + m * G::row + 16 * kh);
+    static_for<0, G::ks>([&](auto iu) {
+      constexpr int u = decltype(iu)::value;
+      const int i = G::ks * chunk + u;
+      if constexpr (u + 1 < G::ks) {
+        are[(u + 1) & 1] = *(const i32x4 *)(st + m * G::row + 32 * (u + 1) + 16 * kh);
+        aim[(u + 1) & 1] = *(const i32x4 *)(st + G::plane + m * G::row + 32 * (u + 1) + 16 * kh);
       }
-    };
-
-    for (int chunk0 = 0; chunk0 < nchunks; chunk0 += 2) {
+      if constexpr (SB) {
 #pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
-        const int chunk = chunk0 + cc;
-        if (chunk < nchunks) {
-          do_chunk(stage + cc * kExStage, chunk);
-          if (chunk + 1 < nchunks) land(stage + (1 - cc) * kExStage, raw[(cc + 1) & 1], chunk + 1);
-          fetch(raw[(cc + 1) & 1], chunk + 3);
-          __syncthreads();
-        }
+        for (int c = 0; c < NB; ++c)
+          wb[c][(u + 1) & 1] = frag_at(sbits, lut, pb[c] + 32 * (i + 1));
+      } else {
+        win[(u + 1) % NW] = frag_at(sbits, lut, p_base + 32 * (i + 1));
+      }
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const i32x4 bw = SB ? wb[c][u & 1] : win[(u - c + NW) % NW];
+        acc_re[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(are[u & 1], bw, acc_re[c], 0, 0, 0);
+        acc_im[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aim[u & 1], bw, acc_im[c], 0, 0, 0);
+      }
+      static_for<u * kPerStep, (u + 1) * kPerStep>([&](auto kp) {
+        if constexpr (decltype(kp)::value < kPieces) conv_piece(kp, cv, nst, nr, nchunk);
+      });
+    });
+  };
+
+  // Epilogue. Lane (m, kh) holds, for block c, column ocol(c) + m and
+  // accumulator rows 8(v/4) + 4kh + (v%4): antenna v/4, digit 4kh + v%4.
+  // Q = sum of its four digit sums times 256^(digit - 4kh) is exact in
+  // FP64 (< 2^48); the lanes kh = 0 and 1 swap halves so that lane kh
+  // finishes antennas 2kh and 2kh + 1: total = Q_low + 2^32 Q_high.
+  const double alpha = a.alpha * (a.scales ? (double)a.scales[b] : 1.0);
+  // cin of the group's outputs, loaded during its last stage
+  f2a8 cpre[NB][2];
+  auto load_cin = [&]() {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int ant = a0 + 2 * kh + jj;
+        const size_t o = ((size_t)(b * a.R + ant) * a.ld_out + ocol(c) + m) * 2;
+        cpre[c][jj] = (a.beta != 0.0 && m < nout(c) && ant < a.R) ? *(const f2a8 *)(a.cin + o)
+                                                                   : f2a8{0.f, 0.f};
       }
     }
-
-    // Epilogue. Lane (m, kh) holds, for block c, column ocol(c) + m and
-    // accumulator rows 8(v/4) + 4kh + (v%4): antenna v/4, digit 4kh + v%4.
-    // Q = sum of its four digit sums times 256^(digit - 4kh) is exact in
-    // FP64 (< 2^48); the lanes kh = 0 and 1 swap halves so that lane kh
-    // finishes antennas 2kh and 2kh + 1: total = Q_low + 2^32 Q_high.
-    const double alpha = a.alpha * (a.scales ? (double)a.scales[b] : 1.0);
+  };
+  auto finish_group = [&]() {
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       double tot[2][2];  // [antenna 2kh + jj][re, im]
@@ -348,8 +424,7 @@ __global__ __launch_bounds__(kExThreads, 2) void exact_kernel(ExArgs a, int rblo
       if (m < nout(c)) {
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
-          const int j = 2 * kh + jj;
-          const int ant = a0 + j;
+          const int ant = a0 + 2 * kh + jj;
           if (ant < a.R) {
             const int e = e_fin[jj];
             // 2^(e - 188): X carried 188 - e fractional bits
@@ -358,35 +433,59 @@ __global__ __launch_bounds__(kExThreads, 2) void exact_kernel(ExArgs a, int rblo
             if (e == 255) re = im = __builtin_nan("");
             const size_t o = ((size_t)(b * a.R + ant) * a.ld_out + col) * 2;
             if (a.beta != 0.0) {
-              const f2a8 old = *(const f2a8 *)(a.cin + o);
-              re += a.beta * (double)old.x;
-              im += a.beta * (double)old.y;
+              re += a.beta * (double)cpre[c][jj].x;
+              im += a.beta * (double)cpre[c][jj].y;
             }
             __builtin_nontemporal_store(f2a8{(float)re, (float)im}, (f2a8 *)(a.out + o));
           }
         }
       }
     }
+  };
+
+  land(stage, raw[0], 0);
+  fetch(raw[0], 2 % nchunks);
+  start_group(0);
+  __syncthreads();
+  for (int s0 = 0; s0 < total; s0 += 2) {
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const int st = s0 + cc;
+      if (st < total) {
+        const int chunk = st % nchunks;
+        if (chunk == last) load_cin();
+        // (after the last step the conversion fills a stage nobody reads)
+        do_chunk(stage + cc * G::stage, chunk, stage + (1 - cc) * G::stage, raw[(cc + 1) & 1],
+                 (st + 1) % nchunks);
+        fetch(raw[(cc + 1) & 1], (st + 3) % nchunks);
+        __syncthreads();
+        if (chunk == last) {
+          finish_group();
+          if (st + 1 < total) start_group(st / nchunks + 1);
+        }
+      }
+    }
   }
 }
 
-template <int NB>
+template <int NB, int NWV>
 hipError_t launch_exact_nb(const ExArgs &a, int rblocks, int splits, int ngroups, int nbw_pad,
-                           size_t lds, long nt, hipStream_t s) {
+                           long nt, hipStream_t s) {
+  const size_t lds = (size_t)(kLutDw + nbw_pad + kMaxDw) * 4 + 2 * (size_t)ExGeom<NWV>::stage;
   auto go = [&](auto kern) -> hipError_t {
     if (lds > 64 * 1024) {
       hipError_t e = hipFuncSetAttribute((const void *)kern,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)nt), dim3(kExThreads), lds, s, a, rblocks, splits,
-                       ngroups, nbw_pad);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nt), dim3(ExGeom<NWV>::threads), lds, s, a, rblocks,
+                       splits, ngroups, nbw_pad);
     return hipGetLastError();
   };
   if (a.seg_lag && a.rseg_lag) return hipErrorInvalidValue;  // never both (one direction each)
-  if (a.seg_lag) return go(exact_kernel<NB, true, false>);
-  if (a.rseg_lag) return go(exact_kernel<NB, false, true>);
-  return go(exact_kernel<NB, false, false>);
+  if (a.seg_lag) return go(exact_kernel<NB, NWV, true, false>);
+  if (a.rseg_lag) return go(exact_kernel<NB, NWV, false, true>);
+  return go(exact_kernel<NB, NWV, false, false>);
 }
 
 }  // namespace
@@ -396,21 +495,22 @@ hipError_t launch_exact(const ExArgs &a, hipStream_t s) {
     return hipErrorInvalidValue;
   const int vcols = virtual_cols(a.c_len, a.seg_len, a.seg_lag, 32);
   const int nb = vcols > 256 ? 4 : (vcols > 128 ? 2 : 1);
-  const int gw = kExWaves * 32 * nb;
+  const int nwv = (nb == 4 && vcols > 512) ? 8 : 4;
+  const int gw = nwv * 32 * nb;
   const int ngroups = (vcols + gw - 1) / gw;
   const int rblocks = (a.R + kExAnts - 1) / kExAnts;
   const long units = (long)a.batch * rblocks;
   // Small launches spread one block's column groups over several
   // workgroups (each finds the rows' exponents itself).
-  constexpr long kFill = 2048;  // 8 workgroups per compute unit
+  constexpr long kFill = 2048;
   const int splits = units >= kFill ? 1 : (int)std::min<long>(ngroups, (kFill + units - 1) / units);
   const long nt = units * splits;
   if (nt <= 0 || nt > 0x7FFFFFFFL) return hipErrorInvalidValue;
   const int nbw_pad = (a.nbw + 3) & ~3;
-  const size_t lds = (size_t)(nbw_pad + 4) * 4 + 2 * (size_t)kExStage;
-  if (nb == 4) return launch_exact_nb<4>(a, rblocks, splits, ngroups, nbw_pad, lds, nt, s);
-  if (nb == 2) return launch_exact_nb<2>(a, rblocks, splits, ngroups, nbw_pad, lds, nt, s);
-  return launch_exact_nb<1>(a, rblocks, splits, ngroups, nbw_pad, lds, nt, s);
+  if (nwv == 8) return launch_exact_nb<4, 8>(a, rblocks, splits, ngroups, nbw_pad, nt, s);
+  if (nb == 4) return launch_exact_nb<4, 4>(a, rblocks, splits, ngroups, nbw_pad, nt, s);
+  if (nb == 2) return launch_exact_nb<2, 4>(a, rblocks, splits, ngroups, nbw_pad, nt, s);
+  return launch_exact_nb<1, 4>(a, rblocks, splits, ngroups, nbw_pad, nt, s);
 }
 
 }  // namespace pnce
