@@ -51,12 +51,13 @@ ROTATE_COPIES = 5              # frame / CIR buffer copies the FP32-baseline ste
 # HBM bytes per launch of the headline kernel measured with rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size), valid only
 # for the kernel source with this sha256; any other source reports null.
-TRAFFIC = {"source_sha256": "df680d14f5e742cd80171e0a6bb6e0b093a1773c7ee4d040afb0201390b569a3",
-           "bytes_per_launch": 4295638306}
+TRAFFIC = {"source_sha256": "f0338a9c6819640b641b336567326292ecd7793258f3482507f49e88f7b7bbfe",
+           "bytes_per_launch": 4295642035}
 BF16_PEAK_TFLOPS = 2516.6      # dense bf16 / f16 matrix
 FP8_PEAK_TFLOPS = 5033.2       # dense fp8 matrix
 FP32_PEAK_TFLOPS = 157.3       # dense fp32 matrix
 FP64_PEAK_TFLOPS = 78.6        # dense fp64 matrix
+INT8_PEAK_TOPS = 5033.2         # dense int8 matrix
 
 
 def parse():
@@ -81,6 +82,10 @@ def parse():
                          "shape (256 frames, T*L=512 -> N=1023) and on the differentiation shape "
                          "(1024 frames, T*L=1024 -> N=1023), and of the FP32-accurate estimate of "
                          "the FP32-baseline shape, for rocprofv3 counters")
+    ap.add_argument("--exact-probe", action="store_true",
+                    help="only 3 launches each of the last refinement residual r = y - P x on "
+                         "the 512 precision-study frames with exact sums (int8 digits) and with "
+                         "FP64 sums (FP64 matrix cores), for rocprofv3 counters")
     ap.add_argument("--varlen-probe", action="store_true",
                     help="only 3 persistent launches of the 4096-frame uneven batch (default "
                          "schedule) and 3 plain copies of its code buffer, for rocprofv3 counters")
@@ -371,6 +376,12 @@ def headline(torch, args):
     ref_ms = {}
     for k in (1, 2, 5):
         ref_ms[k], _ = time_steps(lambda: plan.refine(y, X, k, work=work), 2, 1, torch)
+    # its last residual r = y - P x both ways: exact sums on int8 digits (the
+    # one refinement runs) and FP64 sums on the FP64 matrix cores
+    resid = {}
+    for prec in ("exact", "f64acc"):
+        resid[prec], _ = time_steps(
+            lambda: plan.adjoint(X, prec, alpha=-1.0, beta=1.0, C=y, out=work), 2, 1, torch)
     del X, work, H2
     torch.cuda.empty_cache()
 
@@ -464,9 +475,17 @@ def headline(torch, args):
         "pack_plus_estimate_ms": ms_pack + ms_bf,
         "other_formats": formats,
         "refine_ms": {f"{k}_steps": v for k, v in ref_ms.items()},
+        "final_residual_ms": {
+            "exact_int8_digits": resid["exact"], "fp64_matrix_cores": resid["f64acc"],
+            "speedup": resid["f64acc"] / resid["exact"],
+            "int8_frac": 8.0 * flops / resid["exact"] / 1e9 / INT8_PEAK_TOPS,
+            "fp64_frac": flops / resid["f64acc"] / 1e9 / FP64_PEAK_TFLOPS,
+            "note": "r = y - P x over all frames; exact: every value in 62-bit fixed point "
+                    "cut into eight int8 digits, exact int32 sums on v_mfma_i32_32x32x32_i8 "
+                    "(8x the contraction's operations), result correctly rounded to FP32"},
         "bf16_plus_2_refine_steps": {
             "ms": ms_bf + ref_ms[2], "CIR/s": cirs / ((ms_bf + ref_ms[2]) * 1e-3),
-            "note": "bf16 estimate then 2 FP32 refinement steps (the last residual with FP64 "
+            "note": "bf16 estimate then 2 FP32 refinement steps (the last residual with exact "
                     "sums): within 1e-5 of the FP64 iterate (accuracy_vs_oracle_fp64)"},
         "wall_ms_per_step": wall_bf,
         "roofline": {"bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS,
@@ -514,7 +533,7 @@ def other_rows(plan, cfg, y, H, torch, args):
     X = H.clone()
     work = torch.empty_like(y)
     ms, _ = time_steps(lambda: plan.refine(y, X, 1, work=work), max(2, args.steps // 4), 1, torch)
-    res["refine_1_step"] = {"ms": ms, "note": "FP64-accumulated residual + f32s correlation"}
+    res["refine_1_step"] = {"ms": ms, "note": "exact-sum residual + f32s correlation"}
     del q, Hq, A, X, work
     res["eq8_lags"] = eq8_lags(cfg, y, H, res, torch, args)
     res["uneven_batch"] = uneven_batch(torch, args)
@@ -1036,6 +1055,24 @@ def adjoint_probe(torch):
     print(json.dumps({"adjoint_probe": True}), flush=True)
 
 
+def exact_probe(torch):
+    """Three launches each of the residual r = y - P x on the precision-study
+    frames, with exact sums and with FP64 sums, nothing timed."""
+    import synth
+    from paper_2206_05506_amd import Plan
+    cfg = synth.PRECISION
+    with Plan(cfg.N, cfg.T, cfg.L, cfg.R) as p:
+        y = _randn_c64((cfg.B, cfg.R, cfg.N), 41, torch)
+        X = _randn_c64((cfg.B, cfg.R, cfg.K), 42, torch)
+        A = torch.empty_like(y)
+        for prec in ("exact", "f64acc"):
+            for _ in range(3):
+                p.adjoint(X, prec, alpha=-1.0, beta=1.0, C=y, out=A)
+        torch.cuda.synchronize()
+        del y, X, A
+    print(json.dumps({"exact_probe": True}), flush=True)
+
+
 def varlen_probe(torch):
     """Three persistent launches of the uneven batch and three plain copies
     of its code buffer (the counters' calibration), nothing timed."""
@@ -1081,6 +1118,9 @@ def main():
         return
     if args.varlen_probe:
         varlen_probe(torch)
+        return
+    if args.exact_probe:
+        exact_probe(torch)
         return
     out, ctx = headline(torch, args)
     if not args.no_cpu:
