@@ -818,9 +818,9 @@ def test_entry_point_statuses_follow_the_documented_checks():
             batch = rnd.choice([0, 1, 2, 3, -1])
             op = rnd.choice(["estimate", "pack", "estimate_cp", "refine", "adjoint"])
             if op == "estimate":
-                prec = rnd.choice([0, 1, 2, 4, 9, -1])
+                prec = rnd.choice([0, 1, 2, 4, 5, 9, -1])
                 a, b = maybe("y"), maybe("H")
-                want = (-1 if prec not in (0, 1, 2, 4) else 0 if batch == 0 else
+                want = (-1 if prec not in (0, 1, 2, 4, 5) else 0 if batch == 0 else
                         -1 if a is None or b is None or batch < 0 else 0)
                 st = lib.pnce_estimate(h, None, a, b, batch, prec, 1.0 / N, None, 0.0)
             elif op == "pack":
@@ -844,10 +844,10 @@ def test_entry_point_statuses_follow_the_documented_checks():
                         else 0)
                 st = lib.pnce_refine(h, None, a, b, c, batch, steps)
             else:
-                prec = rnd.choice([1, 2, 5])
+                prec = rnd.choice([1, 2, 5, 6])
                 beta = rnd.choice([0.0, 1.0])
                 a, b, c = maybe("H"), maybe("A"), maybe("C")
-                want = (-1 if prec == 5 else 0 if batch == 0 else
+                want = (-1 if prec == 6 else 0 if batch == 0 else
                         -1 if a is None or b is None or (beta != 0.0 and c is None) or batch < 0
                         else 0)
                 st = lib.pnce_adjoint(h, None, a, b, c, batch, prec, 1.0 / N, beta)
