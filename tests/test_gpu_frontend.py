@@ -34,7 +34,7 @@ def _raw(y, cp, seed):
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d_C%d" % s)
-@pytest.mark.parametrize("prec", ["bf16", "f32s", "f32"])
+@pytest.mark.parametrize("prec", ["bf16", "f32s", "f32", "exact"])
 def test_estimate_cp_equals_prefix_free_estimate(shape, prec):
     N, T, L, R, B, cp = shape
     y = synth.gaussian((B, R, N), N + cp).astype(np.complex64)
@@ -63,7 +63,7 @@ def test_pack_cp_bit_exact(shape, fmt):
     assert np.array_equal(q.view(ref_q.dtype), ref_q)
 
 
-@pytest.mark.parametrize("prec", ["bf16", "f32s", "f64"])
+@pytest.mark.parametrize("prec", ["bf16", "f32s", "f64", "exact"])
 @pytest.mark.parametrize("chunk", [16, 1, 64])   # ragged last chunk; one frame; one chunk
 def test_stream_from_host_equals_device_estimate(prec, chunk):
     N, T, L, R, F, cp = 1023, 16, 32, 64, 40, 32
