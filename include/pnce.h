@@ -325,6 +325,9 @@ pnce_status pnce_pack_cp(const pnce_plan *plan, void *stream, const void *Y_raw,
  *   PNCE_HOST_STAGING_BYTES(R, N, cp, min(chunk, frames), precision) bytes;
  *   its contents on return are unspecified.
  * copy_stream may equal stream (the copies then do not overlap).
+ * Unlike the compute calls, this call creates and destroys four HIP events
+ * (hipEventDisableTiming) and enqueues copies: it is not meant for stream
+ * capture.
  * Errors: PNCE_E_INVALID for chunk < 1, a NULL pointer with frames > 0 or a
  * staging buffer that is too small; otherwise as for pnce_estimate_cp. An
  * error after the first chunk was queued leaves H partly written.
