@@ -572,10 +572,9 @@ pnce_status pnce_estimate_host(const pnce_plan *plan, void *stream, void *copy_s
   if (!Y_host || !H || !staging)
     return fail(PNCE_E_INVALID, "Y_host, H and staging must be non-NULL");
   if (pnce_status st = check_batch(plan, frames)) return st;
-  if (pnce_status st = check_batch(plan, chunk)) return st;
   const size_t esz = c_bytes(precision);
   const size_t fbytes = (size_t)plan->R * (size_t)(plan->N + cp) * esz;
-  const int per = chunk < frames ? chunk : frames;  // frames per staging half
+  const int per = chunk < frames ? chunk : frames;  // frames per staging half (<= frames)
   if (staging_bytes / 2 / fbytes < (size_t)per)
     return fail(PNCE_E_INVALID, "staging is smaller than 2 * min(chunk, frames) raw frames");
   if (pnce_status st = check_align(staging, 16, "staging")) return st;

@@ -103,5 +103,9 @@ def test_stream_from_host_back_to_back_reuses_staging():
             p.stream_from_host(ha, cp, chunk, "f32s", staging=staging[:-1])
         with pytest.raises(ValueError):
             p.stream_from_host(ha, cp, 0, "f32s")
+        # a chunk larger than the batch is one chunk of the whole batch
+        Hc = p.stream_from_host(ha, cp, 1 << 30, "f32s")
+        torch.cuda.synchronize()
+        assert torch.equal(Hc, Ha)
         empty = torch.empty((0, R, N + cp), dtype=torch.complex64).pin_memory()
         assert p.stream_from_host(empty, cp, chunk, "bf16").shape == (0, R, T * L)
