@@ -918,6 +918,9 @@ def front_end(plan, cfg, y, torch, lat_h2d_us, args):
     chunk = 32
     ms, _ = time_steps(lambda: plan.stream_from_host(host, cp, chunk, "bf16", out=H),
                        max(2, args.steps // 4), 1, torch)
+    # the box's own host-to-device rate for the same bytes: one plain copy
+    ms_copy, _ = time_steps(lambda: raw.copy_(host, non_blocking=True), max(2, args.steps // 4), 1,
+                            torch)
     ms_dev, _ = time_steps(lambda: plan.estimate_cp(raw, cp, "bf16", out=H), args.steps, 2,
                            torch)
     byt = raw.numel() * 8
@@ -925,6 +928,8 @@ def front_end(plan, cfg, y, torch, lat_h2d_us, args):
     del raw, host, H
     return {"cp": cp, "frames": B, "chunk_frames": chunk,
             "host_stream_ms": ms, "host_stream_GB/s": byt / ms / 1e6,
+            "plain_h2d_copy_ms": ms_copy, "plain_h2d_copy_GB/s": byt / ms_copy / 1e6,
+            "host_stream_vs_plain_copy": ms_copy / ms,
             "host_stream_CIR/s": B * R * cfg.T / (ms * 1e-3),
             "device_resident_cp_ms": ms_dev,
             "frame_latency_with_h2d_us": lat_h2d_us,
