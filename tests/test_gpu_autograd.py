@@ -30,7 +30,7 @@ def test_gradcheck_fp64_tiny_instance():
                                         eps=1e-6, atol=1e-9, rtol=1e-7)
 
 
-@pytest.mark.parametrize("prec", ["f32", "f32s"])
+@pytest.mark.parametrize("prec", ["f32", "f32s", "exact"])
 def test_backward_equals_oracle_adjoint(prec):
     from paper_2206_05506_amd.autograd import correlate
     N, T, L, R, B = 255, 4, 16, 8, 3
@@ -44,14 +44,15 @@ def test_backward_equals_oracle_adjoint(prec):
     assert perr(host(gY), oracle.adjoint(G, s)) <= 1e-5
 
 
-def test_loss_gradient_equals_oracle():
+@pytest.mark.parametrize("prec", ["f32s", "exact"])
+def test_loss_gradient_equals_oracle(prec):
     from paper_2206_05506_amd.autograd import residual_loss
     N, T, L, R, B = 127, 4, 16, 6, 2
     y = synth.gaussian((B, R, N), 5).astype(np.complex64)
     x = synth.gaussian((B, R, T * L), 6).astype(np.complex64) * 0.1
     with _plan(N, T, L, R) as p:
         xd = dev(x).requires_grad_(True)
-        loss = residual_loss(dev(y), xd, p, "f32s")
+        loss = residual_loss(dev(y), xd, p, prec)
         (g,) = torch.autograd.grad(loss, xd)
         s = p.sequence()
     ref_loss, ref_g = oracle.loss_grad(y, s, x)
