@@ -394,8 +394,11 @@ __global__ __launch_bounds__(64 * NWV, 8 / NWV) void exact_kernel(ExArgs a, int 
       for (int jj = 0; jj < 2; ++jj) {
         const int ant = a0 + 2 * kh + jj;
         const size_t o = ((size_t)(b * a.R + ant) * a.ld_out + ocol(c) + m) * 2;
-        cpre[c][jj] = (a.beta != 0.0 && m < nout(c) && ant < a.R) ? *(const f2a8 *)(a.cin + o)
-                                                                   : f2a8{0.f, 0.f};
+        // streaming load: cin is read once and should not evict the rows
+        // that the next column groups read again
+        cpre[c][jj] = (a.beta != 0.0 && m < nout(c) && ant < a.R)
+                          ? __builtin_nontemporal_load((const f2a8 *)(a.cin + o))
+                          : f2a8{0.f, 0.f};
       }
     }
   };
