@@ -247,7 +247,10 @@ class Plan:
         library-held stream per device) while the previous chunk is estimated
         on the current stream. Returns H [F, R, T*L] on the device; the
         current stream carries the last estimate, and Y_host must stay
-        unchanged until it has run."""
+        unchanged until it has run. A caller that streams repeatedly should
+        pass the same `staging` buffer (uint8, at least
+        host_staging_bytes(...) bytes) to every call rather than let each
+        call allocate one."""
         if int(chunk) < 1:
             raise ValueError("chunk must be >= 1")
         prec = PRECISIONS[precision]
