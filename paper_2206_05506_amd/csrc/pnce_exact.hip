@@ -16,16 +16,19 @@
 // rounded at 2^(e - 63), far below FP32 resolution of the row.
 //
 // Tile: 4 antennas x 8 digits = the 32 rows of the matrix-core A operand, by
-// 4 waves x 32*NB output columns. A workgroup takes one block of 4 antennas
-// of one frame and a share of its column groups (all of them unless the
-// launch would be too small to fill the chip). It first finds each row's
-// exponent (wave w scans antenna w), then, per column group, streams the
-// rows through LDS in 256-sample stages, converting every sample into its
-// digits on the way (two stages in flight in registers, one barrier per
-// stage). The +-1 operand is expanded from the sequence bit stream in LDS;
-// without column segments, block c's fragment at k-step i is block 0's at
-// k-step i - c (a block of 32 columns is one k-step of 32 terms), so a wave
-// expands one fragment per k-step and rotates 2*NB of them.
+// NWV waves x 32*NB output columns (8 waves for outputs wider than 512
+// columns, else 4). A workgroup takes one block of 4 antennas of one frame
+// and a share of its column groups (all of them unless the launch would be
+// too small to fill the chip). It first finds each row's exponent (the
+// first stages' loads already in flight), then streams the rows through LDS
+// in stages of 64*NWV samples, one pipeline across its column groups (they
+// all read the same rows): each stage is converted into digits between the
+// k-steps of the stage before (two stages in flight in registers, one
+// barrier per stage). The +-1 operand is expanded from the sequence bit
+// stream in LDS through a nibble table; without column segments, block c's
+// fragment at k-step i is block 0's at k-step i - c (a block of 32 columns
+// is one k-step of 32 terms), so a wave expands one fragment per k-step and
+// rotates 2*NB of them.
 #include <algorithm>
 #include <type_traits>
 
