@@ -485,8 +485,9 @@ def headline(torch, args):
                     "(8x the contraction's operations), result correctly rounded to FP32"},
         "bf16_plus_2_refine_steps": {
             "ms": ms_bf + ref_ms[2], "CIR/s": cirs / ((ms_bf + ref_ms[2]) * 1e-3),
-            "note": "bf16 estimate then 2 FP32 refinement steps (the last residual with exact "
-                    "sums): within 1e-5 of the FP64 iterate (accuracy_vs_oracle_fp64)"},
+            "note": "bf16 estimate then 2 refinement steps (sums on four int8 digits, the "
+                    "last residual exact): within 1e-5 of the FP64 iterate "
+                    "(accuracy_vs_oracle_fp64)"},
         "wall_ms_per_step": wall_bf,
         "roofline": {"bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
@@ -533,7 +534,7 @@ def other_rows(plan, cfg, y, H, torch, args):
     X = H.clone()
     work = torch.empty_like(y)
     ms, _ = time_steps(lambda: plan.refine(y, X, 1, work=work), max(2, args.steps // 4), 1, torch)
-    res["refine_1_step"] = {"ms": ms, "note": "exact-sum residual + f32s correlation"}
+    res["refine_1_step"] = {"ms": ms, "note": "exact-sum residual + four-digit (exact32) correlation"}
     del q, Hq, A, X, work
     res["eq8_lags"] = eq8_lags(cfg, y, H, res, torch, args)
     res["uneven_batch"] = uneven_batch(torch, args)

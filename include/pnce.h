@@ -98,6 +98,12 @@ typedef int pnce_status;
                            /* at most 65535 terms per output (else            */
                            /* PNCE_E_UNSUPPORTED); a row holding inf or NaN   */
                            /* gives NaN outputs.                              */
+#define PNCE_PREC_EXACT32 6 /* as PNCE_PREC_EXACT with 30 bits cut into four  */
+                            /* digits (half the matrix work): exact for       */
+                            /* elements within 2^6 of their row's largest     */
+                            /* magnitude, smaller ones rounded at 2^-30 of    */
+                            /* the row bound (an error below 2^-31 max|x| per */
+                            /* term, under FP32 rounding of typical sums)     */
 
 /* Reduced-precision storage formats of Y (the half-precision conversion
  * before correlation, Section III-B). */
@@ -172,8 +178,8 @@ pnce_status pnce_get_shape(const pnce_plan *plan, int *N, int *T, int *L, int *R
  * Y: [batch][R][N] c64 (c128 when precision == PNCE_PREC_F64);
  * H: [batch][R][T*L] c64 (c128 for PNCE_PREC_F64), read only if beta != 0;
  * scales: NULL or `batch` device floats. Y and H must not overlap.
- * precision: PNCE_PREC_F32, _F32S, _BF16, _F64, _F64ACC or _EXACT (alpha and
- * beta then in FP64).
+ * precision: PNCE_PREC_F32, _F32S, _BF16, _F64, _F64ACC, _EXACT or _EXACT32
+ * (alpha and beta then in FP64).
  * Errors: null Y/H, batch < 0, unknown precision -> PNCE_E_INVALID.
  */
 pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y,
@@ -245,8 +251,8 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream,
  * the residual y - P h of the receive model of Eq. 9.
  * G: [batch][R][T*L]; A, C: [batch][R][N]; c64, or c128 for
  * PNCE_PREC_F64. C may equal A, or be NULL when beta == 0. G must not
- * overlap A. precision: PNCE_PREC_F32, _F32S, _BF16, _F64, _F64ACC or
- * _EXACT (alpha and beta then in FP64).
+ * overlap A. precision: PNCE_PREC_F32, _F32S, _BF16, _F64, _F64ACC, _EXACT
+ * or _EXACT32 (alpha and beta then in FP64).
  */
 pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
                          void *A, const void *C, int batch, int precision,
@@ -256,10 +262,12 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
  * Least-squares refinement of a CIR estimate (the correlator's bias floor
  * comes from the -1/M term of Eq. 1; each step removes part of it):
  *   repeat `steps` times:  r = y - P x;  x = x + P^T r / N.
- * Both contractions are FP32-accurate (PNCE_PREC_F32S), except the residual
- * of the last step, whose sums are exact (PNCE_PREC_EXACT: r is y - P x
- * rounded once to FP32), or accumulated in FP64 (PNCE_PREC_F64ACC) when
- * they have more than 65535 terms.
+ * The correlations and the inner steps' residuals are summed on four int8
+ * digits (PNCE_PREC_EXACT32: exact to 2^-30 of each row's largest element,
+ * then one rounding to FP32); the last residual is exact (PNCE_PREC_EXACT:
+ * r is y - P x rounded once to FP32). Residual sums of more than 65535
+ * terms are FP32-accurate (PNCE_PREC_F32S) in the inner steps and
+ * accumulated in FP64 (PNCE_PREC_F64ACC) in the last.
  * y: [batch][R][N] c64 (the original, unquantised frames);
  * X: [batch][R][T*L] c64, in: the starting estimate, out: refined;
  * work: device scratch of batch*R*N*8 bytes (the residual). steps >= 0.

@@ -26,6 +26,7 @@ PNCE_PREC_BF16 = 2
 PNCE_PREC_F64 = 3
 PNCE_PREC_F64ACC = 4
 PNCE_PREC_EXACT = 5
+PNCE_PREC_EXACT32 = 6
 
 PNCE_LAGS_ADJACENT = 0
 PNCE_LAGS_EQ8 = 1

@@ -11,12 +11,13 @@ import torch
 
 from . import _lib
 from ._lib import (PNCE_FMT_BF16, PNCE_FMT_E4M3, PNCE_FMT_F16, PNCE_PREC_BF16,
-                   PNCE_PREC_EXACT, PNCE_PREC_F32, PNCE_PREC_F32S, PNCE_PREC_F64,
-                   PNCE_PREC_F64ACC,
+                   PNCE_PREC_EXACT, PNCE_PREC_EXACT32, PNCE_PREC_F32, PNCE_PREC_F32S,
+                   PNCE_PREC_F64, PNCE_PREC_F64ACC,
                    PNCE_W_LAG_ALIAS)
 
 PRECISIONS = {"f32": PNCE_PREC_F32, "f32s": PNCE_PREC_F32S, "bf16": PNCE_PREC_BF16,
-              "f64": PNCE_PREC_F64, "f64acc": PNCE_PREC_F64ACC, "exact": PNCE_PREC_EXACT}
+              "f64": PNCE_PREC_F64, "f64acc": PNCE_PREC_F64ACC, "exact": PNCE_PREC_EXACT,
+              "exact32": PNCE_PREC_EXACT32}
 FORMATS = {"bf16": PNCE_FMT_BF16, "f16": PNCE_FMT_F16, "e4m3": PNCE_FMT_E4M3}
 _CODE_DTYPE = {"bf16": torch.int16, "f16": torch.int16, "e4m3": torch.uint8}
 

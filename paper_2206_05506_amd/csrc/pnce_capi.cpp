@@ -103,7 +103,8 @@ std::vector<uint32_t> bit_stream(const std::vector<signed char> &s, int len_word
 
 bool valid_prec(int p) {
   return p == PNCE_PREC_F32 || p == PNCE_PREC_F32S || p == PNCE_PREC_BF16 ||
-         p == PNCE_PREC_F64 || p == PNCE_PREC_F64ACC || p == PNCE_PREC_EXACT;
+         p == PNCE_PREC_F64 || p == PNCE_PREC_F64ACC || p == PNCE_PREC_EXACT ||
+         p == PNCE_PREC_EXACT32;
 }
 
 bool valid_fmt(int f) {
@@ -185,9 +186,10 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.rseg_len = sg.rlen;
     a.rseg_lag = sg.rlag;
     e = pnce::launch_tg64(a, s);
-  } else if (precision == PNCE_PREC_EXACT) {
+  } else if (precision == PNCE_PREC_EXACT || precision == PNCE_PREC_EXACT32) {
     if (positions > 65535)
-      return fail(PNCE_E_UNSUPPORTED, "PNCE_PREC_EXACT sums at most 65535 terms per output");
+      return fail(PNCE_E_UNSUPPORTED,
+                  "PNCE_PREC_EXACT and _EXACT32 sum at most 65535 terms per output");
     pnce::ExArgs a{};
     a.in = (const float *)in;
     a.out = (float *)out;
@@ -210,6 +212,7 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.rseg_len = sg.rlen;
     a.rseg_lag = sg.rlag;
     a.rseg_n = sg.rn;
+    a.digits = precision == PNCE_PREC_EXACT ? 8 : 4;
     e = pnce::launch_exact(a, s);
   } else {
     pnce::TgArgs a{};
@@ -654,17 +657,21 @@ namespace {
 // The refinement loop on `batch` frames with the residual in `work`.
 pnce_status refine_steps(const pnce_plan *plan, hipStream_t s, const void *y, void *X,
                          void *work, int batch, int steps) {
-  // The last residual is summed exactly (int8 digits) when its sums have at
-  // most 65535 terms, else in FP64 on the FP64 matrix cores.
+  // Sums on int8 digits while they have at most 65535 terms: four digits
+  // (exact to 2^-30 of each row's largest element) for the inner steps and
+  // the correlations, eight (exact) for the last residual. Longer residual
+  // sums: FP32-accurate inner steps, FP64 sums for the last one.
   const long terms = plan->D != plan->L ? (long)(plan->T - 1) * plan->D + plan->L : plan->K;
-  const int last_prec = terms <= 65535 ? PNCE_PREC_EXACT : PNCE_PREC_F64ACC;
+  const bool digits = terms <= 65535;
+  const int inner_prec = digits ? PNCE_PREC_EXACT32 : PNCE_PREC_F32S;
+  const int last_prec = digits ? PNCE_PREC_EXACT : PNCE_PREC_F64ACC;
   for (int j = 0; j < steps; ++j) {
     // r = y - P x   (P x = sum_k x[k] s[(n-k) mod N]: adjoint stream, alpha -1)
-    const int prec = (j + 1 < steps) ? PNCE_PREC_F32S : last_prec;
+    const int prec = (j + 1 < steps) ? inner_prec : last_prec;
     if (pnce_status st = run_adj(plan, s, prec, X, work, y, batch, -1.0, 1.0)) return st;
-    // x = x + P^T r / N
-    if (pnce_status st = run_fwd(plan, s, PNCE_PREC_F32S, pnce::IN_C64, work, plan->N, plan->N,
-                                 X, X, nullptr, batch, 1.0 / plan->N, 1.0))
+    // x = x + P^T r / N   (N <= 65535 terms)
+    if (pnce_status st = run_fwd(plan, s, PNCE_PREC_EXACT32, pnce::IN_C64, work, plan->N,
+                                 plan->N, X, X, nullptr, batch, 1.0 / plan->N, 1.0))
       return st;
   }
   return PNCE_OK;

@@ -55,8 +55,8 @@ inline int virtual_cols(int c_len, int seg_len, int seg_lag, int gran) {
 hipError_t launch_tg(int mode, int in_fmt, const TgArgs &a, hipStream_t s);
 
 // Contraction with exact sums (pnce_exact.hip): complex64 rows, int8 matrix
-// cores on eight 8-bit fixed-point digits per value, alpha and beta in FP64.
-// Same geometry fields as TgArgs; t_len in [2, 65535].
+// cores on `digits` (8 or 4) 8-bit fixed-point digits per value, alpha and
+// beta in FP64. Same geometry fields as TgArgs; t_len in [2, 65535].
 struct ExArgs {
   const float *in;
   float *out;
@@ -71,6 +71,7 @@ struct ExArgs {
   int seg_len, seg_lag;
   int poff;
   int rseg_len, rseg_lag, rseg_n;
+  int digits;
 };
 hipError_t launch_exact(const ExArgs &a, hipStream_t s);
 

@@ -30,7 +30,7 @@ def test_gradcheck_fp64_tiny_instance():
                                         eps=1e-6, atol=1e-9, rtol=1e-7)
 
 
-@pytest.mark.parametrize("prec", ["f32", "f32s", "exact"])
+@pytest.mark.parametrize("prec", ["f32", "f32s", "exact", "exact32"])
 def test_backward_equals_oracle_adjoint(prec):
     from paper_2206_05506_amd.autograd import correlate
     N, T, L, R, B = 255, 4, 16, 8, 3
@@ -44,7 +44,7 @@ def test_backward_equals_oracle_adjoint(prec):
     assert perr(host(gY), oracle.adjoint(G, s)) <= 1e-5
 
 
-@pytest.mark.parametrize("prec", ["f32s", "exact"])
+@pytest.mark.parametrize("prec", ["f32s", "exact", "exact32"])
 def test_loss_gradient_equals_oracle(prec):
     from paper_2206_05506_amd.autograd import residual_loss
     N, T, L, R, B = 127, 4, 16, 6, 2

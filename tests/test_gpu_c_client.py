@@ -29,7 +29,7 @@ def _run(args, tmp_path, y, op=None):
     return p, fout
 
 
-@pytest.mark.parametrize("prec", [1, 2, 5])   # PNCE_PREC_F32S, _BF16, _EXACT
+@pytest.mark.parametrize("prec", [1, 2, 5, 6])   # PNCE_PREC_F32S, _BF16, _EXACT, _EXACT32
 @pytest.mark.parametrize("spacing,fb", [(0, 0), (1, 0x3F9)])
 def test_c_client_estimate(tmp_path, prec, spacing, fb):
     N, T, L, R, B = 1023, 16, 32, 64, 2

@@ -91,7 +91,7 @@ def test_eq8_rejects_overlapping_blocks():
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=IDS)
-@pytest.mark.parametrize("prec", ["f32", "f32s", "bf16", "f64acc", "exact"])
+@pytest.mark.parametrize("prec", ["f32", "f32s", "bf16", "f64acc", "exact", "exact32"])
 def test_estimate_parity(shape, prec):
     N, T, L, R, B = shape
     d = oracle.degree_of(N)
@@ -106,7 +106,7 @@ def test_estimate_parity(shape, prec):
     ref = oracle.correlate(x, s, T * L, lag)
     err = perr(H, ref)
     print(f"eq8 estimate {prec} N={N} T={T} L={L}: relerr {err:.3e}")
-    assert err <= (TOL_F64ACC if prec in ("f64acc", "exact") else TOL32)
+    assert err <= (TOL_F64ACC if prec in ("f64acc", "exact", "exact32") else TOL32)
 
 
 @pytest.mark.parametrize("shape", [SHAPES[1], SHAPES[2], SHAPES[7]], ids=[IDS[1], IDS[2], IDS[7]])
@@ -120,7 +120,7 @@ def test_estimate_f64_parity(shape):
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=IDS)
-@pytest.mark.parametrize("prec", ["f32", "f32s", "bf16", "f64acc", "exact"])
+@pytest.mark.parametrize("prec", ["f32", "f32s", "bf16", "f64acc", "exact", "exact32"])
 def test_adjoint_parity(shape, prec):
     """One contraction over the lag blocks (zero in the guard lags), with
     alpha / beta."""
@@ -135,7 +135,7 @@ def test_adjoint_parity(shape, prec):
         A2 = host(p.adjoint(dev(G), prec, alpha=-1.0, beta=1.0, C=dev(C)))
     g = bf16_round(G) if prec == "bf16" else G.astype(np.complex128)
     ref = oracle.adjoint(g, s, lag)
-    tol = TOL_F64ACC if prec in ("f64acc", "exact") else TOL32
+    tol = TOL_F64ACC if prec in ("f64acc", "exact", "exact32") else TOL32
     err = perr(A, ref)
     print(f"eq8 adjoint {prec} N={N} T={T} L={L}: relerr {err:.3e}")
     assert err <= tol

@@ -1,15 +1,19 @@
-"""PNCE_PREC_EXACT: the contraction with exact sums (int8 matrix cores on
-eight 8-bit fixed-point digits per value, combined in FP64).
+"""PNCE_PREC_EXACT and PNCE_PREC_EXACT32: the contraction with exact sums
+(int8 matrix cores on eight or four 8-bit fixed-point digits per value,
+combined in FP64).
 
 Bar, element by element against the FP64 oracle on the same input: every
-output is the exact result rounded once to FP32, so
+output is the exact sum of the fixed-point inputs rounded once to FP32, so
     |out - ref| <= 2^-24 |ref| (1 + 2^-20) + slack,
 slack = 2^-45 |alpha| sum_t |x_t| (the oracle's own FP64 rounding, far above
-the kernel's two FP64 roundings), plus, for rows whose elements span more
-than 2^38, the fixed-point rounding of the small ones: t_len 2^-61 max|x|.
+the kernel's FP64 roundings), plus the fixed-point rounding of the row's
+small elements: each element is rounded at 2^(e - 63) (eight digits) or
+2^(e - 31) (four), with 2^e <= 2 max|x| the power of two above the row's
+largest |re| or |im|, so t_len 2^-62 |alpha| max|x| (eight digits, only
+where a row spans more than 2^38) or t_len 2^-30 |alpha| max|x| (four).
 Where the sum cancels, the slack term carries the bound; elsewhere the
-result is correctly rounded FP32, which FP32 or FP64-accumulated sums
-followed by a rounding only approach.
+eight-digit result is correctly rounded FP32, which FP32 or
+FP64-accumulated sums followed by a rounding only approach.
 """
 import numpy as np
 import pytest
@@ -29,23 +33,27 @@ def _plan(N, T, L, R, spacing="adjacent"):
     return Plan(N, T, L, R, spacing=spacing)
 
 
-def _check(out, ref, x, alpha=1.0, spread=False, what=""):
+def _check(out, ref, x, alpha=1.0, spread=False, prec="exact", what=""):
     """out, ref: [..., C]; x: the input rows [..., t] (same leading dims)."""
     out = np.asarray(out, dtype=np.complex128)
     absx = np.abs(x.real) + np.abs(x.imag)
     row_sum = absx.sum(axis=-1, keepdims=True)
     slack = 2.0 ** -45 * abs(alpha) * row_sum
-    if spread:
+    if spread or prec == "exact32":
         mx = np.maximum(np.abs(x.real), np.abs(x.imag)).max(axis=-1, keepdims=True)
-        slack = slack + x.shape[-1] * 2.0 ** -61 * abs(alpha) * mx
+        unit = 2.0 ** -30 if prec == "exact32" else 2.0 ** -62
+        slack = slack + x.shape[-1] * unit * abs(alpha) * mx
     for part in (np.real, np.imag):
         err = np.abs(part(out) - part(ref))
-        bound = U32 * (1 + 2.0 ** -20) * np.abs(part(ref)) + slack
+        bound = U32 * (1 + 2.0 ** -20) * (np.abs(part(ref)) + slack) + slack
         # a zero bound (a row of zeros) demands an exact zero
         ratio = np.where(bound > 0, err / np.where(bound > 0, bound, 1.0),
                          np.where(err > 0, np.inf, 0.0))
         worst = float(np.max(ratio)) if err.size else 0.0
         assert worst <= 1.0, f"{what}: error {worst:.3f} x the bound"
+
+
+EXACT = ["exact", "exact32"]
 
 
 # (N, T, L, R, B, spacing): ragged antenna blocks (R % 4 != 0), one to
@@ -68,38 +76,41 @@ SHAPES = [
 IDS = ["N%d_T%d_L%d_R%d_B%d_%s" % s for s in SHAPES]
 
 
+@pytest.mark.parametrize("prec", EXACT)
 @pytest.mark.parametrize("shape", SHAPES, ids=IDS)
-def test_exact_correlator_correctly_rounded(shape):
+def test_exact_correlator_correctly_rounded(shape, prec):
     N, T, L, R, B, spacing = shape
     y = synth.gaussian((B, R, N), N + R).astype(np.complex64)
     with _plan(N, T, L, R, spacing) as p:
         s, lag = p.sequence(), p.lags()
-        H = host(p.estimate(dev(y), "exact"))
-        H1 = host(p.estimate(dev(y), "exact", alpha=1.0))
+        H = host(p.estimate(dev(y), prec))
+        H1 = host(p.estimate(dev(y), prec, alpha=1.0))
     y64 = y.astype(np.complex128)
     ref = oracle.correlate(y64, s, T * L, lag)
-    _check(H, ref, y64[..., :], alpha=1.0 / N, what="H = YP/N")
-    _check(H1, ref * N, y64, alpha=1.0, what="H = YP")
+    _check(H, ref, y64, alpha=1.0 / N, prec=prec, what="H = YP/N")
+    _check(H1, ref * N, y64, alpha=1.0, prec=prec, what="H = YP")
 
 
+@pytest.mark.parametrize("prec", EXACT)
 @pytest.mark.parametrize("shape", SHAPES[:-1], ids=IDS[:-1])
-def test_exact_adjoint_correctly_rounded(shape):
+def test_exact_adjoint_correctly_rounded(shape, prec):
     N, T, L, R, B, spacing = shape
     K = T * L
     G = synth.gaussian((B, R, K), K + 3).astype(np.complex64)
     C = synth.gaussian((B, R, N), K + 4).astype(np.complex64)
     with _plan(N, T, L, R, spacing) as p:
         s, lag = p.sequence(), p.lags()
-        A = host(p.adjoint(dev(G), "exact", alpha=1.0))
-        Ar = host(p.adjoint(dev(G), "exact", alpha=-1.0, beta=1.0, C=dev(C)))
+        A = host(p.adjoint(dev(G), prec, alpha=1.0))
+        Ar = host(p.adjoint(dev(G), prec, alpha=-1.0, beta=1.0, C=dev(C)))
     G64 = G.astype(np.complex128)
     PG = N * oracle.adjoint(G64, s, lag)
-    _check(A, PG, G64, what="A = G P^T")
+    _check(A, PG, G64, prec=prec, what="A = G P^T")
     # the residual of the receive model, y - P x (beta = 1 adds C exactly)
-    _check(Ar, C.astype(np.complex128) - PG, G64, what="C - G P^T")
+    _check(Ar, C.astype(np.complex128) - PG, G64, prec=prec, what="C - G P^T")
 
 
-def test_exact_wide_dynamic_range_and_special_values():
+@pytest.mark.parametrize("prec", EXACT)
+def test_exact_wide_dynamic_range_and_special_values(prec):
     """Rows whose elements span 2^-140 .. 2^20 (subnormals, zeros, signed
     zeros, exact powers of two), a row of zeros, and a row holding inf: its
     outputs are NaN and no other row is touched."""
@@ -115,23 +126,24 @@ def test_exact_wide_dynamic_range_and_special_values():
     y[0, 5, 100] = np.inf
     with _plan(N, T, L, R) as p:
         s = p.sequence()
-        H = host(p.estimate(dev(y), "exact"))
+        H = host(p.estimate(dev(y), prec))
     assert np.isnan(H[0, 5]).all()
     assert np.array_equal(H[0, 1], np.zeros(T * L, np.complex64))
     keep = [r for r in range(R) if r != 5]
     y64 = y[:, keep].astype(np.complex128)
     ref = oracle.correlate(y64, s, T * L)
-    _check(H[:, keep], ref, y64, alpha=1.0 / N, spread=True, what="wide range")
+    _check(H[:, keep], ref, y64, alpha=1.0 / N, spread=True, prec=prec, what="wide range")
 
 
-def test_exact_scales_and_beta():
+@pytest.mark.parametrize("prec", EXACT)
+def test_exact_scales_and_beta(prec):
     N, T, L, R, B = 511, 8, 32, 12, 3
     y = synth.gaussian((B, R, N), 21).astype(np.complex64)
     H0 = synth.gaussian((B, R, T * L), 22).astype(np.complex64)
     sc = np.array([0.5, 3.0, 1e-3], dtype=np.float32)
     with _plan(N, T, L, R) as p:
         Hd = dev(H0)
-        p.estimate(dev(y), "exact", out=Hd, scales=torch.from_numpy(sc).cuda(), beta=-0.75,
+        p.estimate(dev(y), prec, out=Hd, scales=torch.from_numpy(sc).cuda(), beta=-0.75,
                    alpha=1.0)
         H = host(Hd)
         s = p.sequence()
@@ -139,32 +151,35 @@ def test_exact_scales_and_beta():
     ref = sc.astype(np.float64)[:, None, None] * oracle.correlate(y64, s, T * L) * N \
         - 0.75 * H0.astype(np.complex128)
     scale_rows = np.broadcast_to(sc.astype(np.float64)[:, None, None], (B, R, 1))
-    _check(H, ref, y64 * scale_rows, what="scales, beta")
+    _check(H, ref, y64 * scale_rows, prec=prec, what="scales, beta")
 
 
-def test_exact_matches_fp64_matrix_core_path():
-    """The FP64-accumulating path and the exact path on the same frames:
-    both within their bars of the oracle, the exact one never further."""
+@pytest.mark.parametrize("prec,other", [("exact", "f64acc"), ("exact32", "f32s")])
+def test_exact_never_further_than_the_path_it_replaces(prec, other):
+    """Eight digits against FP64 sums on the FP64 matrix cores, four digits
+    against the FP32-accurate bf16 split (the refinement's inner steps): on
+    the same frames the digit path's largest error is never larger."""
     N, T, L, R, B = 1023, 16, 32, 64, 2
     y = synth.gaussian((B, R, N), 31).astype(np.complex64)
     with _plan(N, T, L, R) as p:
-        He = host(p.estimate(dev(y), "exact")).astype(np.complex128)
-        Hf = host(p.estimate(dev(y), "f64acc")).astype(np.complex128)
+        He = host(p.estimate(dev(y), prec)).astype(np.complex128)
+        Hf = host(p.estimate(dev(y), other)).astype(np.complex128)
         s = p.sequence()
     ref = oracle.correlate(y.astype(np.complex128), s, T * L)
     ee, ef = np.abs(He - ref), np.abs(Hf - ref)
-    print(f"max error: exact {ee.max():.3e}, f64acc {ef.max():.3e}")
+    print(f"max error: {prec} {ee.max():.3e}, {other} {ef.max():.3e}")
     assert ee.max() <= ef.max() * (1 + 1e-12) + 1e-30
 
 
-def test_exact_refuses_more_than_65535_terms():
+@pytest.mark.parametrize("prec", EXACT)
+def test_exact_refuses_more_than_65535_terms(prec):
     from paper_2206_05506_amd._lib import PnceError
     N, T, L, R = 8191, 1024, 65, 1        # the adjoint sums T*L = 66560 terms
     with _plan(N, T, L, R) as p:
         G = torch.zeros((1, R, T * L), dtype=torch.complex64, device="cuda")
         with pytest.raises(PnceError, match="65535"):
-            p.adjoint(G, "exact")
-        p.estimate(torch.zeros((1, R, N), dtype=torch.complex64, device="cuda"), "exact")
+            p.adjoint(G, prec)
+        p.estimate(torch.zeros((1, R, N), dtype=torch.complex64, device="cuda"), prec)
 
 
 def test_refine_last_residual_is_correctly_rounded():

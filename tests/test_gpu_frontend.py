@@ -34,7 +34,7 @@ def _raw(y, cp, seed):
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d_C%d" % s)
-@pytest.mark.parametrize("prec", ["bf16", "f32s", "f32", "exact"])
+@pytest.mark.parametrize("prec", ["bf16", "f32s", "f32", "exact", "exact32"])
 def test_estimate_cp_equals_prefix_free_estimate(shape, prec):
     N, T, L, R, B, cp = shape
     y = synth.gaussian((B, R, N), N + cp).astype(np.complex64)

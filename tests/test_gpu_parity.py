@@ -58,7 +58,7 @@ TOL_F64ACC = 2e-7   # FP64 sums, one rounding of each output to FP32
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
-@pytest.mark.parametrize("prec", ["f32", "f32s", "bf16", "f64acc", "exact"])
+@pytest.mark.parametrize("prec", ["f32", "f32s", "bf16", "f64acc", "exact", "exact32"])
 def test_estimate_parity(shape, prec):
     N, T, L, R, B = shape
     K = T * L
@@ -71,7 +71,7 @@ def test_estimate_parity(shape, prec):
     ref = oracle.correlate(x, s, K)
     err = perr(H, ref)
     print(f"estimate {prec} N={N} K={K} R={R} B={B}: relerr {err:.3e}")
-    assert err <= (TOL_F64ACC if prec in ("f64acc", "exact") else TOL32)
+    assert err <= (TOL_F64ACC if prec in ("f64acc", "exact", "exact32") else TOL32)
 
 
 @pytest.mark.parametrize("shape", [SHAPES[2], SHAPES[4], SHAPES[6]],
@@ -114,7 +114,7 @@ def test_estimate_scales_and_beta():
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "N%d_T%d_L%d_R%d_B%d" % s)
-@pytest.mark.parametrize("prec", ["f32", "f32s", "f64acc", "exact"])
+@pytest.mark.parametrize("prec", ["f32", "f32s", "f64acc", "exact", "exact32"])
 def test_adjoint_parity(shape, prec):
     N, T, L, R, B = shape
     K = T * L
@@ -125,7 +125,7 @@ def test_adjoint_parity(shape, prec):
         A = host(p.adjoint(dev(G), prec))
         A2 = host(p.adjoint(dev(G), prec, alpha=-1.0, beta=1.0, C=dev(C)))
     ref = oracle.adjoint(G, s)
-    tol = TOL_F64ACC if prec in ("f64acc", "exact") else TOL32
+    tol = TOL_F64ACC if prec in ("f64acc", "exact", "exact32") else TOL32
     assert perr(A, ref) <= tol
     ref2 = C.astype(np.complex128) - N * ref
     assert perr(A2, ref2) <= tol
@@ -818,9 +818,9 @@ def test_entry_point_statuses_follow_the_documented_checks():
             batch = rnd.choice([0, 1, 2, 3, -1])
             op = rnd.choice(["estimate", "pack", "estimate_cp", "refine", "adjoint"])
             if op == "estimate":
-                prec = rnd.choice([0, 1, 2, 4, 5, 9, -1])
+                prec = rnd.choice([0, 1, 2, 4, 5, 6, 9, -1])
                 a, b = maybe("y"), maybe("H")
-                want = (-1 if prec not in (0, 1, 2, 4, 5) else 0 if batch == 0 else
+                want = (-1 if prec not in (0, 1, 2, 4, 5, 6) else 0 if batch == 0 else
                         -1 if a is None or b is None or batch < 0 else 0)
                 st = lib.pnce_estimate(h, None, a, b, batch, prec, 1.0 / N, None, 0.0)
             elif op == "pack":
@@ -844,10 +844,10 @@ def test_entry_point_statuses_follow_the_documented_checks():
                         else 0)
                 st = lib.pnce_refine(h, None, a, b, c, batch, steps)
             else:
-                prec = rnd.choice([1, 2, 5, 6])
+                prec = rnd.choice([1, 2, 5, 6, 8])
                 beta = rnd.choice([0.0, 1.0])
                 a, b, c = maybe("H"), maybe("A"), maybe("C")
-                want = (-1 if prec == 6 else 0 if batch == 0 else
+                want = (-1 if prec == 8 else 0 if batch == 0 else
                         -1 if a is None or b is None or (beta != 0.0 and c is None) or batch < 0
                         else 0)
                 st = lib.pnce_adjoint(h, None, a, b, c, batch, prec, 1.0 / N, beta)
