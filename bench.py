@@ -83,9 +83,10 @@ def parse():
                          "(1024 frames, T*L=1024 -> N=1023), and of the FP32-accurate estimate of "
                          "the FP32-baseline shape, for rocprofv3 counters")
     ap.add_argument("--exact-probe", action="store_true",
-                    help="only 3 launches each of the last refinement residual r = y - P x on "
-                         "the 512 precision-study frames with exact sums (int8 digits) and with "
-                         "FP64 sums (FP64 matrix cores), for rocprofv3 counters")
+                    help="only 3 launches each of the refinement residual r = y - P x on "
+                         "the 512 precision-study frames with exact sums (eight int8 digits), "
+                         "FP64 sums (FP64 matrix cores), four int8 digits and the bf16 split, "
+                         "for rocprofv3 counters")
     ap.add_argument("--varlen-probe", action="store_true",
                     help="only 3 persistent launches of the 4096-frame uneven batch (default "
                          "schedule) and 3 plain copies of its code buffer, for rocprofv3 counters")
@@ -376,10 +377,12 @@ def headline(torch, args):
     ref_ms = {}
     for k in (1, 2, 5):
         ref_ms[k], _ = time_steps(lambda: plan.refine(y, X, k, work=work), 2, 1, torch)
-    # its last residual r = y - P x both ways: exact sums on int8 digits (the
-    # one refinement runs) and FP64 sums on the FP64 matrix cores
+    # its residual r = y - P x: the last step's both ways, exact sums on int8
+    # digits (the one refinement runs) and FP64 sums on the FP64 matrix
+    # cores; the inner steps' on four int8 digits (the one refinement runs)
+    # and as the FP32-accurate bf16 split
     resid = {}
-    for prec in ("exact", "f64acc"):
+    for prec in ("exact", "f64acc", "exact32", "f32s"):
         resid[prec], _ = time_steps(
             lambda: plan.adjoint(X, prec, alpha=-1.0, beta=1.0, C=y, out=work), 2, 1, torch)
     del X, work, H2
@@ -483,6 +486,13 @@ def headline(torch, args):
             "note": "r = y - P x over all frames; exact: every value in 62-bit fixed point "
                     "cut into eight int8 digits, exact int32 sums on v_mfma_i32_32x32x32_i8 "
                     "(8x the contraction's operations), result correctly rounded to FP32"},
+        "inner_residual_ms": {
+            "four_int8_digits": resid["exact32"], "bf16_split": resid["f32s"],
+            "speedup": resid["f32s"] / resid["exact32"],
+            "int8_frac": 4.0 * flops / resid["exact32"] / 1e9 / INT8_PEAK_TOPS,
+            "note": "r = y - P x of the inner refinement steps: four int8 digits of a 30-bit "
+                    "fixed-point value (exact to 2^-30 of each row's largest element, then one "
+                    "rounding) against three bf16 parts with FP32 accumulation"},
         "bf16_plus_2_refine_steps": {
             "ms": ms_bf + ref_ms[2], "CIR/s": cirs / ((ms_bf + ref_ms[2]) * 1e-3),
             "note": "bf16 estimate then 2 refinement steps (sums on four int8 digits, the "
@@ -1069,7 +1079,8 @@ def adjoint_probe(torch):
 
 def exact_probe(torch):
     """Three launches each of the residual r = y - P x on the precision-study
-    frames, with exact sums and with FP64 sums, nothing timed."""
+    frames: exact sums (eight int8 digits), FP64 sums, four int8 digits and
+    the FP32-accurate bf16 split; nothing timed."""
     import synth
     from paper_2206_05506_amd import Plan
     cfg = synth.PRECISION
@@ -1077,7 +1088,7 @@ def exact_probe(torch):
         y = _randn_c64((cfg.B, cfg.R, cfg.N), 41, torch)
         X = _randn_c64((cfg.B, cfg.R, cfg.K), 42, torch)
         A = torch.empty_like(y)
-        for prec in ("exact", "f64acc"):
+        for prec in ("exact", "f64acc", "exact32", "f32s"):
             for _ in range(3):
                 p.adjoint(X, prec, alpha=-1.0, beta=1.0, C=y, out=A)
         torch.cuda.synchronize()
