@@ -956,6 +956,13 @@ def front_end(plan, cfg, y, torch, lat_h2d_us, args):
                     "airtime per multiplexed block of Eq. 11 at each sample rate"}
 
 
+# (array size N_t = N_r, PN length M, taps L = cyclic prefix C, N_batch) of the
+# latency sweeps: Fig. 6 over M at 16 x 16, Fig. 7 over the array size at
+# M = 2047 (Table I's values)
+LATENCY_POINTS = ([(16, M, 64, nb) for M in (511, 1023, 2047) for nb in (1, 2, 4, 8)] +
+                  [(n, 2047, 128, nb) for n in (16, 32, 64) for nb in (1, 2, 4, 8)])
+
+
 def latency_sweeps(torch, args):
     """Frame latency of Section IV-C/IV-D (Figs. 6 and 7) against the pilot
     airtime of Eq. 11. A frame holds the pilots of all N_t transmitters:
@@ -969,11 +976,9 @@ def latency_sweeps(torch, args):
     (C + M) / F_s * N_t / N_batch at F_s = 10 MHz. Synthetic complex
     Gaussian samples: the latency does not depend on the values."""
     from paper_2206_05506_amd import Plan
-    points = [(16, M, 64, nb) for M in (511, 1023, 2047) for nb in (1, 2, 4, 8)]
-    points += [(n, 2047, 128, nb) for n in (16, 32, 64) for nb in (1, 2, 4, 8)]
     iters = max(50, args.latency_iters)
     rows = []
-    for n_ant, M, L, nb in points:
+    for n_ant, M, L, nb in LATENCY_POINTS:
         blocks = n_ant // nb
         with Plan(M, nb, L, n_ant) as plan:
             raw = _randn_c64((blocks, n_ant, L + M), 1000 + M + nb + n_ant, torch)

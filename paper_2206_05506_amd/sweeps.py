@@ -90,13 +90,18 @@ def _curve(M: int, nb: int, L: int, lnz: int, iters: int, seed: int) -> dict:
     return {"M": M, "N_batch": nb, "L": L, "L_nz": lnz, "frames": F, "mae": pts}
 
 
+# (M, N_batch, L, L_nz) of every curve
+FIG4_CURVES = [(M, nb, 64, 64) for M in (511, 2047) for nb in (1, 2, 4)]
+FIG5_CURVES = [(2047, 4, 128, lnz) for lnz in (1, 4, 16, 64, 128)]
+DEFAULT_ITERS = 50  # realisations per point (Table I)
+
+
 def fig4(iters: int) -> list:
-    return [_curve(M, nb, 64, 64, iters, 100 + 10 * nb + M % 7)
-            for M in (511, 2047) for nb in (1, 2, 4)]
+    return [_curve(M, nb, L, lnz, iters, 100 + 10 * nb + M % 7) for M, nb, L, lnz in FIG4_CURVES]
 
 
 def fig5(iters: int) -> list:
-    return [_curve(2047, 4, 128, lnz, iters, 200 + lnz) for lnz in (1, 4, 16, 64, 128)]
+    return [_curve(M, nb, L, lnz, iters, 200 + lnz) for M, nb, L, lnz in FIG5_CURVES]
 
 
 def table(curves: list, label) -> str:
@@ -113,7 +118,7 @@ def table(curves: list, label) -> str:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--iters", type=int, default=DEFAULT_ITERS)
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     res = {"fig4": fig4(args.iters), "fig5": fig5(args.iters), "iters": args.iters,
