@@ -7,8 +7,8 @@
 // largest magnitude and cut into DG balanced 8-bit digits (the splitting of
 // the Ozaki scheme for error-free matrix products, here one-sided: the other
 // operand is +-1 and exact in int8):
-//   DG = 8: X = round(x * 2^(62 - e)), |X| < 2^62 (PNCE_PREC_EXACT);
-//   DG = 4: X = round(x * 2^(30 - e)), |X| < 2^30 (PNCE_PREC_EXACT32),
+//   DG = 8: X = rint(x * 2^(62 - e)), |X| < 2^62 (PNCE_PREC_EXACT);
+//   DG = 4: X = rint(x * 2^(30 - e)), |X| < 2^30 (PNCE_PREC_EXACT32),
 // with 2^e the power of two just above the row's largest |re| or |im|. Each
 // digit's contraction is summed exactly in int32 (|digit| <= 128, at most
 // 65535 terms, so |sum| < 2^23); the digit sums are combined in FP64 (exact
@@ -51,8 +51,9 @@ template <> struct DigitWord<4> { using T = uint32_t; };
 // x (FP32) in fixed point: X = rint(x * 2^k), k = scale - E for a row whose
 // largest |re| or |im| has biased exponent field E (E >= 1; scale = 188 for
 // DG = 8, 156 for DG = 4), so |X| < 2^(8 DG - 2). x * 2^k is exact (a power
-// of two times x; FP32 subnormals are kept), and so is the rounding to an
-// integer (to nearest, ties to even), the split of an eight-digit X into
+// of two times x; FP32 subnormals are kept) unless it falls below 2^-126,
+// where X is 0 either way; exact too are the rounding to an integer (to
+// nearest, ties to even), the split of an eight-digit X into
 // 32-bit halves (hi = floor(X / 2^32), lo = X - hi 2^32 in [0, 2^32), both
 // exact in FP32) and the conversions. The clamp only acts on rows holding
 // inf or NaN, whose outputs are NaN anyway. Returned as (X + bias) ^ bias,
@@ -164,7 +165,7 @@ template <int NWV, int DG> struct ExGeom {
   static constexpr int lpg = tpa < 64 ? tpa : 64;  // lanes of one maximum reduction
   static constexpr int gpa = tpa / lpg;            // reductions per antenna
   static constexpr int fin = 16 / DG;  // antennas each lane finishes per column
-  static constexpr int scale = 150 + (DG == 8 ? 38 : 6);  // X = x * 2^(scale - E)
+  static constexpr int scale = 150 + (DG == 8 ? 38 : 6);  // X = rint(x * 2^(scale - E))
 };
 constexpr int kLutDw = 16;  // LDS: nibble table, sequence bits, row maxima, stages
 constexpr int kMaxDw = 16;
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(64 * NWV, 8 / NWV) void exact_kernel(ExArgs a, int 
   f2a8 cpre[NB][G::fin];
   // this frame's outputs (a frame is below 2 GiB: 32-bit offsets)
   const size_t frame_out = (size_t)b * a.R * a.ld_out * 2;
-  const float *cin_f = a.cin + frame_out;
+  const float *cin_f = a.cin ? a.cin + frame_out : nullptr;  // read only when beta != 0
   float *out_f = a.out + frame_out;
   auto load_cin = [&]() {
 #pragma unroll
