@@ -101,9 +101,11 @@ typedef int pnce_status;
 #define PNCE_PREC_EXACT32 6 /* as PNCE_PREC_EXACT with 30 bits cut into four  */
                             /* digits (half the matrix work): exact for       */
                             /* elements within 2^6 of their row's largest     */
-                            /* magnitude, smaller ones rounded at 2^-30 of    */
-                            /* the row bound (an error below 2^-31 max|x| per */
-                            /* term, under FP32 rounding of typical sums)     */
+                            /* magnitude, smaller ones rounded to a multiple  */
+                            /* of 2^-30 of the row bound (the power of two    */
+                            /* above that magnitude): an error of at most     */
+                            /* 2^-30 max|x| per term, before the one FP32     */
+                            /* rounding of the output                         */
 
 /* Reduced-precision storage formats of Y (the half-precision conversion
  * before correlation, Section III-B). */
