@@ -198,3 +198,45 @@ def test_refine_last_residual_is_correctly_rounded():
     x64 = x0.astype(np.complex128)
     ref = y.astype(np.complex128) - N * oracle.adjoint(x64, s)
     _check(r, ref, x64, what="residual")
+
+
+def test_exact_full_precision_workload_sampled():
+    """The refinement's contractions at the precision workload's full size
+    and launch shape (512 frames of 256 x 4095, T*L = 2048): the residual
+    r = y - P x with eight and with four digits and the correlation of r
+    with four, over all frames; sampled rows (first, middle and last frame;
+    antennas at both ends and in a ragged spot) against the oracle, element
+    by element to the bar above. Inputs are seeded torch draws on the GPU;
+    the oracle reads the same values copied to the host."""
+    N, T, L, R, B = 4095, 32, 64, 256, 512
+    K = T * L
+    g = torch.Generator(device="cuda")
+    g.manual_seed(53)
+    frames, ants = [0, 257, 511], [0, 101, 255]
+    with _plan(N, T, L, R) as p:
+        s = p.sequence()
+        y = torch.complex(torch.randn((B, R, N), generator=g, device="cuda"),
+                          torch.randn((B, R, N), generator=g, device="cuda")).contiguous()
+        x = (torch.complex(torch.randn((B, R, K), generator=g, device="cuda"),
+                           torch.randn((B, R, K), generator=g, device="cuda")) * 0.05).contiguous()
+        r = torch.empty_like(y)
+        xs = host(x[frames][:, ants])
+        ys = host(y[frames][:, ants])
+        got = {}
+        for prec in EXACT:
+            p.adjoint(x, prec, alpha=-1.0, beta=1.0, C=y, out=r)
+            got[prec] = host(r[frames][:, ants])
+        # the correlation step of the refinement: x + P^T r / N, on four digits
+        p.adjoint(x, "exact", alpha=-1.0, beta=1.0, C=y, out=r)
+        xn = p.estimate(r, "exact32", alpha=1.0 / N, beta=1.0, out=x.clone())
+        rs = host(r[frames][:, ants])
+        xns = host(xn[frames][:, ants])
+        del y, x, r, xn
+        torch.cuda.empty_cache()
+    x64, y64, r64 = (a.astype(np.complex128) for a in (xs, ys, rs))
+    ref_r = y64 - N * oracle.adjoint(x64, s)
+    for prec in EXACT:
+        _check(got[prec], ref_r, x64, prec=prec, what=f"residual {prec}")
+    ref_x = x64 + oracle.correlate(r64, s, K)
+    # x + (1/N) sum_t r_t s'(...), rounded once: the slack is that of r's rows
+    _check(xns, ref_x, r64, alpha=1.0 / N, prec="exact32", what="correlation exact32")
