@@ -20,7 +20,8 @@
 //
 // Tile: 32/DG antennas x DG digits = the 32 rows of the matrix-core A
 // operand, by NWV waves x 32*NB output columns (8 waves for outputs wider
-// than 512 columns, else 4). A workgroup takes one block of antennas of one
+// than 512 columns whose rows are long enough to give each workgroup at
+// least 4 stages, else 4). A workgroup takes one block of antennas of one
 // frame and a share of its column groups (all of them unless the launch
 // would be too small to fill the chip). It first finds each row's exponent
 // (the first stages' loads already in flight), then streams the rows through
@@ -146,8 +147,8 @@ template <int SPT> struct RawEx {
   f32x4 v[SPT / 2];
 };
 
-// Geometry: NWV waves per workgroup (4, or 8 for outputs wider than 512
-// columns, so that each converted stage feeds twice the matrix work), ANT =
+// Geometry: NWV waves per workgroup (4, or 8 for wide outputs with long
+// rows, so that each converted stage feeds twice the matrix work), ANT =
 // 32/DG antennas per tile, TPA threads per antenna, each converting SPT =
 // 32/DG samples of every stage of CH = 64 NWV samples (KS = CH/32 k-steps
 // per barrier). Thread t loads and converts antenna t / TPA, samples
@@ -558,7 +559,11 @@ template <int DG>
 hipError_t launch_exact_dg(const ExArgs &a, hipStream_t s) {
   const int vcols = virtual_cols(a.c_len, a.seg_len, a.seg_lag, 32);
   const int nb = vcols > 256 ? 4 : (vcols > 128 ? 2 : 1);
-  const int nwv = (nb == 4 && vcols > 512) ? 8 : 4;
+  // 8 waves (one workgroup per compute unit) pay off when each workgroup
+  // runs enough stages to hide its fixed latencies (row scan, pipeline
+  // start, epilogue); short rows take 4-wave tiles, two workgroups per unit
+  const long stages8 = (long)((a.t_len + 511) / 512) * ((vcols + 1023) / 1024);
+  const int nwv = (nb == 4 && vcols > 512 && stages8 >= 4) ? 8 : 4;
   const int gw = nwv * 32 * nb;
   const int ngroups = (vcols + gw - 1) / gw;
   constexpr int ant = 32 / DG;
