@@ -491,8 +491,8 @@ def headline(torch, args):
             "speedup": resid["f32s"] / resid["exact32"],
             "int8_frac": 4.0 * flops / resid["exact32"] / 1e9 / INT8_PEAK_TOPS,
             "note": "r = y - P x of the inner refinement steps: four int8 digits of a 30-bit "
-                    "fixed-point value (exact to 2^-30 of each row's largest element, then one "
-                    "rounding) against three bf16 parts with FP32 accumulation"},
+                    "fixed-point value (exact to 2^-30 of each row's largest element, then an "
+                    "FP32 epilogue; no FP64) against three bf16 parts with FP32 accumulation"},
         "bf16_plus_2_refine_steps": {
             "ms": ms_bf + ref_ms[2], "CIR/s": cirs / ((ms_bf + ref_ms[2]) * 1e-3),
             "note": "bf16 estimate then 2 refinement steps (sums on four int8 digits, the "

@@ -99,13 +99,14 @@ typedef int pnce_status;
                            /* PNCE_E_UNSUPPORTED); a row holding inf or NaN   */
                            /* gives NaN outputs.                              */
 #define PNCE_PREC_EXACT32 6 /* as PNCE_PREC_EXACT with 30 bits cut into four  */
-                            /* digits (half the matrix work): exact for       */
-                            /* elements within 2^6 of their row's largest     */
-                            /* magnitude, smaller ones rounded to a multiple  */
-                            /* of 2^-30 of the row bound (the power of two    */
-                            /* above that magnitude): an error of at most     */
-                            /* 2^-30 max|x| per term, before the one FP32     */
-                            /* rounding of the output                         */
+                            /* digits (half the matrix work), and no FP64     */
+                            /* arithmetic: the digit sums combined exactly in */
+                            /* int64, rounded once to FP32, alpha and beta    */
+                            /* applied in FP32. Exact for elements within 2^6 */
+                            /* of their row's largest magnitude, smaller ones */
+                            /* rounded to a multiple of 2^-30 of the row      */
+                            /* bound (the power of two above that magnitude): */
+                            /* an error of at most 2^-30 max|x| per term      */
 
 /* Reduced-precision storage formats of Y (the half-precision conversion
  * before correlation, Section III-B). */
@@ -180,8 +181,8 @@ pnce_status pnce_get_shape(const pnce_plan *plan, int *N, int *T, int *L, int *R
  * Y: [batch][R][N] c64 (c128 when precision == PNCE_PREC_F64);
  * H: [batch][R][T*L] c64 (c128 for PNCE_PREC_F64), read only if beta != 0;
  * scales: NULL or `batch` device floats. Y and H must not overlap.
- * precision: PNCE_PREC_F32, _F32S, _BF16, _F64, _F64ACC, _EXACT or _EXACT32
- * (alpha and beta then in FP64).
+ * precision: PNCE_PREC_F32, _F32S, _BF16, _F64, _F64ACC, _EXACT (alpha and
+ * beta then in FP64) or _EXACT32.
  * Errors: null Y/H, batch < 0, unknown precision -> PNCE_E_INVALID.
  */
 pnce_status pnce_estimate(const pnce_plan *plan, void *stream, const void *Y,
@@ -254,7 +255,7 @@ pnce_status pnce_estimate_packed(const pnce_plan *plan, void *stream,
  * G: [batch][R][T*L]; A, C: [batch][R][N]; c64, or c128 for
  * PNCE_PREC_F64. C may equal A, or be NULL when beta == 0. G must not
  * overlap A. precision: PNCE_PREC_F32, _F32S, _BF16, _F64, _F64ACC, _EXACT
- * or _EXACT32 (alpha and beta then in FP64).
+ * (alpha and beta then in FP64) or _EXACT32.
  */
 pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
                          void *A, const void *C, int batch, int precision,
@@ -266,8 +267,8 @@ pnce_status pnce_adjoint(const pnce_plan *plan, void *stream, const void *G,
  *   repeat `steps` times:  r = y - P x;  x = x + P^T r / N.
  * The correlations and the inner steps' residuals are summed on four int8
  * digits (PNCE_PREC_EXACT32: exact to 2^-30 of each row's largest element,
- * then one rounding to FP32); the last residual is exact (PNCE_PREC_EXACT:
- * r is y - P x rounded once to FP32). Residual sums of more than 65535
+ * then an FP32 epilogue; no FP64 arithmetic); the last residual is exact
+ * (PNCE_PREC_EXACT: r is y - P x rounded once to FP32, FP64 only there). Residual sums of more than 65535
  * terms are FP32-accurate (PNCE_PREC_F32S) in the inner steps and
  * accumulated in FP64 (PNCE_PREC_F64ACC) in the last.
  * y: [batch][R][N] c64 (the original, unquantised frames);

@@ -213,6 +213,8 @@ pnce_status run_tg(const pnce_plan *p, hipStream_t s, int precision, int in_fmt,
     a.rseg_lag = sg.rlag;
     a.rseg_n = sg.rn;
     a.digits = precision == PNCE_PREC_EXACT ? 8 : 4;
+    a.alpha32 = (float)alpha;
+    a.beta32 = (float)beta;
     e = pnce::launch_exact(a, s);
   } else {
     pnce::TgArgs a{};

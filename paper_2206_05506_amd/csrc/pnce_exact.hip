@@ -11,12 +11,14 @@
 //   DG = 4: X = rint(x * 2^(30 - e)), |X| < 2^30 (PNCE_PREC_EXACT32),
 // with 2^e the power of two just above the row's largest |re| or |im|. Each
 // digit's contraction is summed exactly in int32 (|digit| <= 128, at most
-// 65535 terms, so |sum| < 2^23); the digit sums are combined in FP64 (exact
-// for four digits; for eight, two exact partial sums and one rounding when
-// they are added), scaled back, and the output is rounded once to FP32 after
-// alpha and beta are applied in FP64. Row elements within 2^38 (DG = 8) or
-// 2^6 (DG = 4) of the row's largest magnitude are represented exactly;
-// smaller ones are rounded at 2^(e - 63) or 2^(e - 31).
+// 65535 terms, so |sum| < 2^23). Eight digits: the digit sums are combined
+// in FP64 (two exact partial sums, one rounding when they are added),
+// scaled back, alpha and beta applied in FP64, and the output rounded once
+// to FP32. Four digits (no FP64 arithmetic): the digit sums are combined
+// exactly in int64, rounded once to FP32 and scaled back, and alpha and
+// beta are applied in FP32. Row elements within 2^38 (DG = 8) or 2^6
+// (DG = 4) of the row's largest magnitude are represented exactly; smaller
+// ones are rounded at 2^(e - 63) or 2^(e - 31).
 //
 // Tile: 32/DG antennas x DG digits = the 32 rows of the matrix-core A
 // operand, by NWV waves x 32*NB output columns (8 waves for outputs wider
@@ -431,8 +433,12 @@ __global__ __launch_bounds__(64 * NWV, 8 / NWV) void exact_kernel(ExArgs a, int 
   //     swap halves so that lane kh finishes antennas 2kh and 2kh + 1:
   //     total = Q_low + 2^32 Q_high;
   //   DG = 4: antenna 2(v/4) + kh, digit v%4: the lane holds all four digit
-  //     sums of antennas 2jj + kh (jj < 4), whose total is exact in FP64.
-  const double alpha = a.alpha * (a.scales ? (double)a.scales[b] : 1.0);
+  //     sums of antennas 2jj + kh (jj < 4), whose total is exact in int64.
+  // eight digits: alpha and beta in FP64; four: in FP32 (no FP64 arithmetic)
+  [[maybe_unused]] const double alpha =
+      DG == 8 ? a.alpha * (a.scales ? (double)a.scales[b] : 1.0) : 0.0;
+  [[maybe_unused]] const float alpha_f = a.alpha32 * (a.scales ? a.scales[b] : 1.f);
+  const bool use_cin = DG == 8 ? a.beta != 0.0 : a.beta32 != 0.f;
   auto ant_of = [&](int jj) { return a0 + (DG == 8 ? 2 * kh + jj : 2 * jj + kh); };
   // cin of the group's outputs, loaded during its last stage (DG = 8) or
   // at the start of the epilogue (DG = 4: its lanes finish twice the
@@ -452,7 +458,7 @@ __global__ __launch_bounds__(64 * NWV, 8 / NWV) void exact_kernel(ExArgs a, int 
         const uint32_t o = (uint32_t)(ant * a.ld_out + ocol(c) + m) * 2u;
         // streaming load: cin is read once and should not evict the rows
         // that the next column groups read again
-        cpre[c][jj] = (a.beta != 0.0 && m < nout(c) && ant < a.R)
+        cpre[c][jj] = (use_cin && m < nout(c) && ant < a.R)
                           ? __builtin_nontemporal_load((const f2a8 *)(cin_f + o))
                           : f2a8{0.f, 0.f};
       }
@@ -462,16 +468,17 @@ __global__ __launch_bounds__(64 * NWV, 8 / NWV) void exact_kernel(ExArgs a, int 
     if constexpr (!kPrefetchCin) load_cin();
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-      double tot[G::fin][2];  // [antenna ant_of(jj)][re, im]
+      const int col = ocol(c) + m;
+      if constexpr (DG == 8) {
+        double tot[2][2];  // [antenna ant_of(jj)][re, im]
 #pragma unroll
-      for (int ri = 0; ri < 2; ++ri) {
-        const i32x16 &acc = ri ? acc_im[c] : acc_re[c];
-        double q[4];
+        for (int ri = 0; ri < 2; ++ri) {
+          const i32x16 &acc = ri ? acc_im[c] : acc_re[c];
+          double q[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          q[j] = (double)acc[4 * j] + 256.0 * (double)acc[4 * j + 1] +
-                 65536.0 * (double)acc[4 * j + 2] + 16777216.0 * (double)acc[4 * j + 3];
-        if constexpr (DG == 8) {
+          for (int j = 0; j < 4; ++j)
+            q[j] = (double)acc[4 * j] + 256.0 * (double)acc[4 * j + 1] +
+                   65536.0 * (double)acc[4 * j + 2] + 16777216.0 * (double)acc[4 * j + 3];
 #pragma unroll
           for (int jj = 0; jj < 2; ++jj) {
             const double send = kh ? q[jj] : q[2 + jj];
@@ -480,29 +487,54 @@ __global__ __launch_bounds__(64 * NWV, 8 / NWV) void exact_kernel(ExArgs a, int 
             const double hi = kh ? q[2 + jj] : recv;
             tot[jj][ri] = lo + 4294967296.0 * hi;
           }
-        } else {
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) tot[jj][ri] = q[jj];
         }
-      }
-      const int col = ocol(c) + m;
-      if (m < nout(c)) {
+        if (m < nout(c)) {
 #pragma unroll
-        for (int jj = 0; jj < G::fin; ++jj) {
-          const int ant = ant_of(jj);
-          if (ant < a.R) {
-            const int e = e_fin[jj];
-            // 2^(e - scale): X carried scale - e fractional bits
-            const double sc =
-                __builtin_bit_cast(double, (uint64_t)(e - G::scale + 1023) << 52);
-            double re = alpha * (tot[jj][0] * sc), im = alpha * (tot[jj][1] * sc);
-            if (e == 255) re = im = __builtin_nan("");
-            const uint32_t o = (uint32_t)(ant * a.ld_out + col) * 2u;
-            if (a.beta != 0.0) {
-              re += a.beta * (double)cpre[c][jj].x;
-              im += a.beta * (double)cpre[c][jj].y;
+          for (int jj = 0; jj < 2; ++jj) {
+            const int ant = ant_of(jj);
+            if (ant < a.R) {
+              const int e = e_fin[jj];
+              // 2^(e - scale): X carried scale - e fractional bits
+              const double sc =
+                  __builtin_bit_cast(double, (uint64_t)(e - G::scale + 1023) << 52);
+              double re = alpha * (tot[jj][0] * sc), im = alpha * (tot[jj][1] * sc);
+              if (e == 255) re = im = __builtin_nan("");
+              const uint32_t o = (uint32_t)(ant * a.ld_out + col) * 2u;
+              if (use_cin) {
+                re += a.beta * (double)cpre[c][jj].x;
+                im += a.beta * (double)cpre[c][jj].y;
+              }
+              __builtin_nontemporal_store(f2a8{(float)re, (float)im}, (f2a8 *)(out_f + o));
             }
-            __builtin_nontemporal_store(f2a8{(float)re, (float)im}, (f2a8 *)(out_f + o));
+          }
+        }
+      } else {
+        // No FP64: the four digit sums of a row combine exactly in int64
+        // (< 2^47), which is rounded once to FP32 and scaled by 2^(e - scale)
+        // (exact unless the result leaves FP32's normal range); alpha and
+        // beta are applied in FP32.
+        if (m < nout(c)) {
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int ant = ant_of(jj);
+            if (ant < a.R) {
+              float v[2];
+#pragma unroll
+              for (int ri = 0; ri < 2; ++ri) {
+                const i32x16 &acc = ri ? acc_im[c] : acc_re[c];
+                const int64_t t = (int64_t)acc[4 * jj] + (int64_t)acc[4 * jj + 1] * 256 +
+                                  (int64_t)acc[4 * jj + 2] * 65536 +
+                                  (int64_t)acc[4 * jj + 3] * 16777216;
+                v[ri] = alpha_f * __builtin_amdgcn_ldexpf((float)t, e_fin[jj] - G::scale);
+              }
+              if (e_fin[jj] == 255) v[0] = v[1] = __builtin_nanf("");
+              const uint32_t o = (uint32_t)(ant * a.ld_out + col) * 2u;
+              if (use_cin) {
+                v[0] = __builtin_fmaf(a.beta32, cpre[c][jj].x, v[0]);
+                v[1] = __builtin_fmaf(a.beta32, cpre[c][jj].y, v[1]);
+              }
+              __builtin_nontemporal_store(f2a8{v[0], v[1]}, (f2a8 *)(out_f + o));
+            }
           }
         }
       }

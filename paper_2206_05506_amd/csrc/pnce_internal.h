@@ -72,6 +72,7 @@ struct ExArgs {
   int poff;
   int rseg_len, rseg_lag, rseg_n;
   int digits;
+  float alpha32, beta32;  // alpha and beta rounded to FP32 (digits == 4)
 };
 hipError_t launch_exact(const ExArgs &a, hipStream_t s);
 

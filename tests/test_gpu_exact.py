@@ -2,18 +2,23 @@
 (int8 matrix cores on eight or four 8-bit fixed-point digits per value,
 combined in FP64).
 
-Bar, element by element against the FP64 oracle on the same input: every
-output is the exact sum of the fixed-point inputs rounded once to FP32, so
-    |out - ref| <= 2^-24 |ref| (1 + 2^-20) + slack,
-slack = 2^-45 |alpha| sum_t |x_t| (the oracle's own FP64 rounding, far above
-the kernel's FP64 roundings), plus the fixed-point rounding of the row's
-small elements: each element is rounded at 2^(e - 63) (eight digits) or
-2^(e - 31) (four), with 2^e <= 2 max|x| the power of two above the row's
-largest |re| or |im|, so t_len 2^-62 |alpha| max|x| (eight digits, only
-where a row spans more than 2^38) or t_len 2^-30 |alpha| max|x| (four).
-Where the sum cancels, the slack term carries the bound; elsewhere the
-eight-digit result is correctly rounded FP32, which FP32 or
-FP64-accumulated sums followed by a rounding only approach.
+Bar, element by element against the FP64 oracle on the same input. Eight
+digits: every output is the exact sum of the fixed-point inputs, with alpha
+and beta applied in FP64, rounded once to FP32, so
+    |out - ref| <= 2^-24 (1 + 2^-20) (|ref| + slack) + slack.
+Four digits (no FP64 arithmetic): the exact sum rounded to FP32, then alpha
+(itself rounded to FP32, times the frame scale) and beta * cin applied in
+FP32: at most five roundings of 2^-24 of |ref| + |beta cin|,
+    |out - ref| <= 5 * 2^-24 (1 + 2^-10) (|ref| + |beta cin| + slack) + slack.
+slack = 2^-45 |alpha| sum_t |x_t| (the oracle's own FP64 rounding), plus
+the fixed-point rounding of the row's small elements: each element is
+rounded at 2^(e - 63) (eight digits) or 2^(e - 31) (four), with 2^e <=
+2 max|x| the power of two above the row's largest |re| or |im|, so t_len
+2^-62 |alpha| max|x| (eight digits, only where a row spans more than 2^38)
+or t_len 2^-30 |alpha| max|x| (four). Where the sum cancels, the slack term
+carries the bound; elsewhere the eight-digit result is correctly rounded
+FP32, which FP32 or FP64-accumulated sums followed by a rounding only
+approach.
 """
 import numpy as np
 import pytest
@@ -33,8 +38,9 @@ def _plan(N, T, L, R, spacing="adjacent"):
     return Plan(N, T, L, R, spacing=spacing)
 
 
-def _check(out, ref, x, alpha=1.0, spread=False, prec="exact", what=""):
-    """out, ref: [..., C]; x: the input rows [..., t] (same leading dims)."""
+def _check(out, ref, x, alpha=1.0, spread=False, prec="exact", what="", bcin=None):
+    """out, ref: [..., C]; x: the input rows [..., t] (same leading dims);
+    bcin: beta * cin where the call added it (same shape as ref)."""
     out = np.asarray(out, dtype=np.complex128)
     absx = np.abs(x.real) + np.abs(x.imag)
     row_sum = absx.sum(axis=-1, keepdims=True)
@@ -45,7 +51,11 @@ def _check(out, ref, x, alpha=1.0, spread=False, prec="exact", what=""):
         slack = slack + x.shape[-1] * unit * abs(alpha) * mx
     for part in (np.real, np.imag):
         err = np.abs(part(out) - part(ref))
-        bound = U32 * (1 + 2.0 ** -20) * (np.abs(part(ref)) + slack) + slack
+        if prec == "exact32":
+            extra = 0.0 if bcin is None else np.abs(part(bcin))
+            bound = 5 * U32 * (1 + 2.0 ** -10) * (np.abs(part(ref)) + extra + slack) + slack
+        else:
+            bound = U32 * (1 + 2.0 ** -20) * (np.abs(part(ref)) + slack) + slack
         # a zero bound (a row of zeros) demands an exact zero
         ratio = np.where(bound > 0, err / np.where(bound > 0, bound, 1.0),
                          np.where(err > 0, np.inf, 0.0))
@@ -106,7 +116,8 @@ def test_exact_adjoint_correctly_rounded(shape, prec):
     PG = N * oracle.adjoint(G64, s, lag)
     _check(A, PG, G64, prec=prec, what="A = G P^T")
     # the residual of the receive model, y - P x (beta = 1 adds C exactly)
-    _check(Ar, C.astype(np.complex128) - PG, G64, prec=prec, what="C - G P^T")
+    _check(Ar, C.astype(np.complex128) - PG, G64, prec=prec, what="C - G P^T",
+           bcin=C.astype(np.complex128))
 
 
 @pytest.mark.parametrize("prec", EXACT)
@@ -151,7 +162,8 @@ def test_exact_scales_and_beta(prec):
     ref = sc.astype(np.float64)[:, None, None] * oracle.correlate(y64, s, T * L) * N \
         - 0.75 * H0.astype(np.complex128)
     scale_rows = np.broadcast_to(sc.astype(np.float64)[:, None, None], (B, R, 1))
-    _check(H, ref, y64 * scale_rows, prec=prec, what="scales, beta")
+    _check(H, ref, y64 * scale_rows, prec=prec, what="scales, beta",
+           bcin=-0.75 * H0.astype(np.complex128))
 
 
 @pytest.mark.parametrize("prec,other", [("exact", "f64acc"), ("exact32", "f32s")])
@@ -236,7 +248,7 @@ def test_exact_full_precision_workload_sampled():
     x64, y64, r64 = (a.astype(np.complex128) for a in (xs, ys, rs))
     ref_r = y64 - N * oracle.adjoint(x64, s)
     for prec in EXACT:
-        _check(got[prec], ref_r, x64, prec=prec, what=f"residual {prec}")
+        _check(got[prec], ref_r, x64, prec=prec, what=f"residual {prec}", bcin=y64)
     ref_x = x64 + oracle.correlate(r64, s, K)
     # x + (1/N) sum_t r_t s'(...), rounded once: the slack is that of r's rows
-    _check(xns, ref_x, r64, alpha=1.0 / N, prec="exact32", what="correlation exact32")
+    _check(xns, ref_x, r64, alpha=1.0 / N, prec="exact32", what="correlation exact32", bcin=x64)
