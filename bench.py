@@ -368,6 +368,8 @@ def headline(torch, args):
         del qf, sf
     ms_32, _ = time_steps(lambda: plan.estimate(y, "f32s", out=H2), few, 2, torch)
     nmse["fp32_accurate"] = nmse_db(H2, h)
+    ms_x32, _ = time_steps(lambda: plan.estimate(y, "exact32", out=H2), few, 2, torch)
+    nmse["fp32_int8_digits"] = nmse_db(H2, h)
     ms_mf, _ = time_steps(lambda: plan.estimate(y, "f32", out=H2), 3, 1, torch)
     nmse["fp32_mfma"] = nmse_db(H2, h)
 
@@ -457,10 +459,16 @@ def headline(torch, args):
                       "precision": "f32s: FP32-accurate, each FP32 sample split exactly into "
                                    "three bf16 parts, three bf16 matrix-core products",
                       "input": "complex64 frames"},
+        "fp32_int8_digits_path": {"value": cirs / (ms_x32 * 1e-3), "ms_per_step": ms_x32,
+                                  "precision": "exact32: each FP32 row in 30-bit fixed point, "
+                                               "four int8 digits, exact int32 sums, FP32 "
+                                               "epilogue (no FP64); the fastest FP32-class path",
+                                  "input": "complex64 frames"},
         "fp32_mfma_path": {"value": cirs / (ms_mf * 1e-3), "ms_per_step": ms_mf,
                            "precision": "f32: v_mfma_f32_32x32x2_f32",
                            "mfma_frac": flops / ms_mf / 1e9 / FP32_PEAK_TFLOPS},
         "bf16_speedup_vs_fp32": {"fp32_accurate": ms_32 / ms_bf, "fp32_mfma": ms_mf / ms_bf,
+                                 "fp32_int8_digits": ms_x32 / ms_bf,
                                  "delta_nmse_db_vs_fp32_accurate":
                                      nmse["bf16"] - nmse["fp32_accurate"],
                                  "matched_nmse": abs(nmse["bf16"] - nmse["fp32_accurate"])
